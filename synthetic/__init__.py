@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module draws random numbers and lays them out; it holds none of the DG method's
+arithmetic (no basis, no quadrature, no fluxes, no projection), so a mistake here
+cannot cancel between the two implementations that consume its arrays.
+
+Workload recipes (the paper's runs are 3D periodic boxes of isothermal gas driven to
+RMS Mach 0.1-12.8, Sec. 5 table of simulations; its data is not public, so these
+stand in for it):
+  * ``sound_wave``        -- small-amplitude plane sound wave (pointwise field).
+  * ``turbulent_like``    -- modal state with log-normal density (width from the
+                             Mach number) and a smooth random velocity field of the
+                             requested RMS Mach number, with random high-order modes
+                             of decaying amplitude (some cells dip below the density
+                             floor at their Gauss points, some compress strongly).
+  * ``forcing_table``     -- random driving modes on the shell 1 <= |n| <= 2, one per
+                             +/- pair, with complex amplitudes perpendicular to n.
+  * ``gaussian_draws``    -- standard normal numbers for the Ornstein-Uhlenbeck update.
+  * ``mlp_params``        -- random sensor-network parameters rounded to bfloat16.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def nbasis(k: int) -> int:
+    """Number of modes per variable of a total-degree-k expansion in 3D."""
+    return (k + 1) * (k + 2) * (k + 3) // 6
+
+
+def sound_wave(axis: int, amp: float = 1e-3, cs: float = 1.0, rho0: float = 1.0):
+    """Plane sound wave rho = rho0 + amp sin(2 pi x_axis), m_axis = cs amp sin(2 pi x_axis).
+
+    Returns f(x[..., 3], t=0) -> array [4, ...]; the exact linear solution travels at +cs.
+    """
+    def f(x, t=0.0):
+        s = np.sin(2.0 * np.pi * (x[..., axis] - cs * t))
+        out = np.zeros((4,) + x.shape[:-1])
+        out[0] = rho0 + amp * s
+        out[1 + axis] = cs * amp * s
+        return out
+    return f
+
+
+def c1_axis(seed: int) -> int:
+    """Propagation axis of the 16^3 sound-wave workload for a seed."""
+    return int(np.random.default_rng(seed).integers(3))
+
+
+def _smooth(rng, shape, kmax: float, slope: float):
+    """Unit-variance periodic random field on a grid (nz, ny, nx) with power ~ |k|^-slope, |k| <= kmax."""
+    nz, ny, nx = shape
+    noise = rng.standard_normal(shape)
+    F = np.fft.rfftn(noise)
+    kz = np.fft.fftfreq(nz) * nz
+    ky = np.fft.fftfreq(ny) * ny
+    kx = np.fft.rfftfreq(nx) * nx
+    kk = np.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    filt = np.where((kk > 0) & (kk <= kmax), np.maximum(kk, 1.0) ** (-slope / 2.0), 0.0)
+    f = np.fft.irfftn(F * filt, s=shape, axes=(0, 1, 2))
+    sd = f.std()
+    return f / sd if sd > 0 else f
+
+
+def turbulent_like(nx: int, ny: int, nz: int, k: int, mach: float, seed: int,
+                   high_amp: float = 0.08, dtype=np.float64):
+    """Random modal state [4][nb][ncell] resembling driven isothermal turbulence.
+
+    Cell means: log-normal density with variance ln(1 + (mach/3)^2) (solenoidal driving),
+    velocity of RMS |v| = mach.  Higher modes: random, relative amplitude high_amp/(1 + l/4)
+    scaled by the local contrast, so point values vary inside every cell.
+    """
+    rng = np.random.default_rng(seed)
+    shape = (nz, ny, nx)
+    kmax = max(2.0, min(nx, ny, nz) / 4.0)
+    sig2 = np.log(1.0 + (mach / 3.0) ** 2)
+    s = np.sqrt(sig2) * _smooth(rng, shape, kmax, 2.0)
+    rho = np.exp(s - 0.5 * sig2)
+    vel = [mach / np.sqrt(3.0) * _smooth(rng, shape, kmax, 2.0) for _ in range(3)]
+    nb = nbasis(k)
+    nc = nx * ny * nz
+    u = np.zeros((4, nb, nc))
+    u[0, 0] = rho.reshape(-1)
+    for d in range(3):
+        u[1 + d, 0] = (rho * vel[d]).reshape(-1)
+    # local contrast: neighbour differences of the mean fields
+    def contrast(f):
+        c = np.zeros_like(f)
+        for ax in range(3):
+            c += np.abs(np.roll(f, 1, ax) - np.roll(f, -1, ax))
+        return c.reshape(-1)
+    crho = contrast(np.log(rho)) + 0.05
+    vmag = np.sqrt(sum(v * v for v in vel)).reshape(-1) + 0.1
+    for l in range(1, nb):
+        a = high_amp / (1.0 + l / 4.0)
+        u[0, l] = a * u[0, 0] * np.minimum(crho, 1.0) * rng.standard_normal(nc)
+        for d in range(3):
+            u[1 + d, l] = a * u[0, 0] * vmag * rng.standard_normal(nc)
+    return u.astype(dtype)
+
+
+def shell_vectors():
+    """Integer wave vectors with 1 <= |n| <= 2, one of each +/- pair (first non-zero component > 0)."""
+    out = []
+    for nx in range(-2, 3):
+        for ny in range(-2, 3):
+            for nz in range(-2, 3):
+                n2 = nx * nx + ny * ny + nz * nz
+                if not (1 <= n2 <= 4):
+                    continue
+                first = nx if nx != 0 else (ny if ny != 0 else nz)
+                if first > 0:
+                    out.append((nx, ny, nz))
+    return np.array(out, dtype=np.float64)
+
+
+def forcing_table(seed: int, amp: float = 1.0):
+    """Driving-mode table [nmodes][9] = (n, Re/Im a_x, Re/Im a_y, Re/Im a_z) with a perpendicular to n."""
+    rng = np.random.default_rng(seed)
+    n = shell_vectors()
+    tab = np.zeros((len(n), 9))
+    tab[:, :3] = n
+    for i, nv in enumerate(n):
+        re = np.cross(nv, rng.standard_normal(3))
+        im = np.cross(nv, rng.standard_normal(3))
+        re *= amp / np.linalg.norm(nv)
+        im *= amp / np.linalg.norm(nv)
+        tab[i, 3::2] = re
+        tab[i, 4::2] = im
+    return tab
+
+
+def gaussian_draws(seed: int, step: int, n: int):
+    """n standard normal numbers for OU update number ``step`` of stream ``seed``."""
+    rng = np.random.default_rng([seed, step])
+    return rng.standard_normal(n)
+
+
+def to_bf16(a):
+    """Round float values to the nearest bfloat16 (ties to even); returns float32 values."""
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    b = a.view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    b = (b + 0x7FFF + lsb) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def mlp_params(seed: int, sizes=(20, 64, 64, 1)):
+    """Random network parameters [(W [out,in], b [out]), ...] with bf16-representable weights."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        W = to_bf16(rng.standard_normal((fo, fi)) / np.sqrt(fi)).astype(np.float64)
+        b = (0.1 * rng.standard_normal(fo)).astype(np.float32).astype(np.float64)
+        out.append((W, b))
+    return out
+
+
+def random_nu(ncell: int, seed: int):
+    """Per-cell learned-sensor viscosity values (mix of zeros, small and large)."""
+    rng = np.random.default_rng(seed)
+    nu = np.exp(rng.uniform(np.log(1e-5), np.log(0.5), ncell))
+    nu[rng.random(ncell) < 0.3] = 0.0
+    return nu
+
+
+def random_fallback(ncell: int, seed: int, frac: float = 0.2):
+    rng = np.random.default_rng(seed)
+    return (rng.random(ncell) < frac).astype(np.int32)
