@@ -1,0 +1,201 @@
+/*
+ * dg.h -- C ABI of libdg: the modal Discontinuous Galerkin right-hand side and
+ * SSP-RK3 stage update for 3D isothermal Euler on a periodic Cartesian mesh, on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Cernetic, Springel, Guillet & Pakmor (2024), "Supersonic turbulence
+ * simulations with GPU-based high-order Discontinuous Galerkin hydrodynamics",
+ * Sec. 2 (modal Legendre basis, Gauss quadrature, weak form), Sec. 3.1 (von
+ * Neumann-Richtmyer artificial viscosity, positivity), Sec. 3.2 (primitive
+ * projection), Sec. 4.2 (solenoidal Ornstein-Uhlenbeck driving), Sec. 7 (cost,
+ * time step scaling).
+ *
+ * Conventions used by every entry point:
+ *   - cells: nx * ny * nz cubes of edge h, periodic; cell = i + nx*(j + ny*l).
+ *   - basis: phi_(a,b,c)(xi) = Lt_a(xi_1) Lt_b(xi_2) Lt_c(xi_3), Lt_n = sqrt(2n+1) P_n,
+ *     a+b+c <= k, nb = (k+1)(k+2)(k+3)/6 modes ordered by total degree ascending, then a
+ *     descending, then b descending; xi = 2(x - x_K)/h; (1/|K|) Int phi_l phi_m = delta_lm,
+ *     so mode 0 is the cell mean.
+ *   - state u: the weights, stored [var][mode][cell] (var = rho, m_x, m_y, m_z), contiguous,
+ *     element type double (DG_FP64) or float (DG_FP32), in DEVICE memory owned by the caller.
+ *   - projected velocity vhat: [dir][mode][cell], same element type.
+ *   - every call is asynchronous on the stream given in the configuration unless it says
+ *     it synchronises.  Calls on one context must not overlap in time (one stream).
+ *   - return value: DG_OK (0); DG_RETRY (1, recoverable); negative on error, with a
+ *     message from dg_last_error.  No C++ exception crosses the ABI.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum dg_status {
+    DG_OK = 0,
+    DG_RETRY = 1,          /* positivity failure: retry the step with a smaller dt (Sec. 3.1) */
+    DG_EINVAL = -1,        /* null / misaligned pointer, bad size or parameter */
+    DG_EUNSUPPORTED = -2,  /* degree outside 1..3, feature not available for this degree */
+    DG_EHIP = -3,          /* a HIP runtime call failed (text in dg_last_error) */
+    DG_ENOMEM = -4,        /* workspace missing or too small */
+    DG_ESTATE = -5         /* call order violated (e.g. learned sensor without weights) */
+};
+
+enum dg_precision { DG_FP64 = 0, DG_FP32 = 1 };
+
+enum dg_flags {
+    DG_AV = 1,                 /* von Neumann-Richtmyer viscous pressure in the volume flux (Sec. 3.1) */
+    DG_PRIM_PROJ = 2,          /* face velocities from the projected velocity polynomial (Sec. 3.2) */
+    DG_FORCING = 4,            /* driving acceleration source rho a in the momentum rows (Sec. 4.2) */
+    DG_POS_LIMITER = 8,        /* positivity limiter after every stage (Sec. 3.1) */
+    DG_LEARNED_SENSOR = 16,    /* viscosity from the learned per-cell sensor (not in the paper) */
+    DG_FORCE_MEANFREE = 32     /* remove the mass-weighted mean acceleration (exact momentum conservation) */
+};
+
+typedef struct dg_config {
+    int nx, ny, nz;        /* cells per dimension, each >= 1 */
+    int degree;            /* polynomial degree k in {1, 2, 3} (spatial order k+1) */
+    int precision;         /* DG_FP64 or DG_FP32 (bulk arithmetic; reductions are FP64 always) */
+    int flags;             /* OR of dg_flags */
+    double h;              /* cell edge; <= 0 selects 1/nx (unit box along x) */
+    double cs;             /* isothermal sound speed (pressure = cs^2 rho) */
+    double cfl;            /* Courant factor of dg_dt_max */
+    double alpha_visc;     /* quadratic vNR coefficient (paper default 2) */
+    double beta_visc;      /* linear (bulk) coefficient (paper default 0.2) */
+    double rho_floor;      /* positivity floor of the density (1e-3) */
+    void *stream;          /* hipStream_t for every launch; NULL = default stream */
+} dg_config;
+
+typedef struct dg_ctx dg_ctx;
+
+/* Fill a configuration with the defaults: k = 2, FP64, AV | PRIM_PROJ | POS_LIMITER,
+ * h = 1/nx, cs = 1, cfl = 0.3, alpha = 2, beta = 0.2 (Sec. 3.1), floor 1e-3. */
+void dg_config_default(dg_config *cfg, int nx, int ny, int nz);
+
+/* Create a context: checks the configuration, builds the basis / quadrature tables on
+ * the host in FP64 and uploads them (small, owned by the context).  *out = NULL on error.
+ * Errors: DG_EINVAL (null, bad sizes), DG_EUNSUPPORTED (degree), DG_EHIP. */
+int dg_init(const dg_config *cfg, dg_ctx **out);
+
+/* Release the context and its small device tables (not the caller's workspace). */
+void dg_free(dg_ctx *ctx);
+
+/* Text of the last error on this context (static storage inside the context). */
+const char *dg_last_error(const dg_ctx *ctx);
+
+/* Bytes of device scratch the caller must provide (traces, projected velocity, Runge-Kutta
+ * temporaries, driving field at the quadrature points, reduction partials, flags). */
+size_t dg_workspace_bytes(const dg_ctx *ctx);
+
+/* Hand a device workspace of at least dg_workspace_bytes() bytes, 256-byte aligned, to
+ * the context.  The caller owns it and must keep it alive.  Errors: DG_EINVAL, DG_ENOMEM. */
+int dg_set_workspace(dg_ctx *ctx, void *ws, size_t bytes);
+
+/* Driving modes (Sec. 4.2): modes_host[nmodes][9] = (n_x, n_y, n_z, Re a_x, Im a_x,
+ * Re a_y, Im a_y, Re a_z, Im a_z), host memory, FP64; the acceleration is
+ * a(x) = sum_m Re[a_m exp(2 pi i n_m . x)] with x in box units (cell centres at (i+1/2)h).
+ * The table is copied; the field at the quadrature points is rebuilt before the next
+ * right-hand side.  nmodes in 0..64.  Errors: DG_EINVAL. */
+int dg_set_forcing(dg_ctx *ctx, const double *modes_host, int nmodes);
+
+/* Right-hand side dudt = d(weights)/dt of the weak form (Sec. 2.2, weight evolution):
+ * volume flux quadrature with the viscous pressure at interior points, Rusanov fluxes at
+ * the face points, surface lift, driving source.  u and dudt: [4][nb][ncell] device
+ * arrays; dudt is fully overwritten.  dt is the step size used by the Pi_max cap
+ * (Sec. 3.1); dt <= 0 disables the cap.  Errors: DG_EINVAL, DG_ENOMEM (no workspace). */
+int dg_rhs(dg_ctx *ctx, const void *u, void *dudt, double dt);
+
+/* One third-order SSP Runge-Kutta step in place (Shu-Osher form), positivity limiter
+ * after every stage when DG_POS_LIMITER is set.  Synchronises the stream once to read
+ * the 4-byte status into *status_host (may be NULL).  Returns DG_RETRY (and restores u
+ * to its value at entry, kept in the workspace) when a cell mean fell to or below the
+ * floor, i.e. the caller must retry with a smaller dt (Sec. 3.1). */
+int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
+
+/* CFL time step dt = cfl h / ((k+1) max_{cells, interior points} sum_d (|m_d/rho| + cs))
+ * (Sec. 7: dt proportional to h/(k+1)), reduced in FP64.  on_host = 1: *dt_out is host
+ * memory and the call synchronises; on_host = 0: *dt_out is device memory (8 bytes). */
+int dg_dt_max(dg_ctx *ctx, const void *u, double *dt_out, int on_host);
+
+/* Projected velocity (Sec. 3.2, eq. weights_equation with the interior rule):
+ * vhat_{d,l} = (1/8) sum_q w_q phi_l(q) m_d(q)/rho(q); vhat is [3][nb][ncell] device. */
+int dg_project_primitive(dg_ctx *ctx, const void *u, void *vhat);
+
+/* Apply the positivity limiter once (e.g. to initial conditions); synchronises;
+ * *nfail_host = number of cells whose mean is at or below the floor. */
+int dg_limit(dg_ctx *ctx, void *u, long *nfail_host);
+
+/* Conserved totals (mass, momentum x/y/z) = h^3 sum_cells W_v,0, FP64 fixed-order
+ * reduction; out_host[4] host memory; synchronises. */
+int dg_conserved_sums(dg_ctx *ctx, const void *u, double *out_host);
+
+/* Ornstein-Uhlenbeck driving on the shell 1 <= |n| <= 2 (Sec. 4.2), host-side FP64:
+ * dg_forcing_ou_init sets the correlation time t_c and the stationary standard deviation
+ * sigma and zeroes the mode state; dg_forcing_ou_advance applies one update
+ * x <- f x + sigma sqrt(1-f^2) z with f = exp(-dt_drive/t_c), z = the caller's standard
+ * normal draws (z_host[dg_forcing_ou_ndraws()]), projects each mode onto the plane
+ * perpendicular to n (solenoidal) and installs the table as by dg_set_forcing. */
+int dg_forcing_ou_ndraws(void);
+int dg_forcing_ou_init(dg_ctx *ctx, double t_c, double sigma);
+int dg_forcing_ou_advance(dg_ctx *ctx, const double *z_host, double dt_drive);
+/* Copy of the current mode table (nmodes_max rows of 9 doubles); returns nmodes. */
+int dg_forcing_get(const dg_ctx *ctx, double *modes_host, int nmodes_max);
+
+/* ---------------------------------------------------------------------------------
+ * Learned shock sensor (not in the paper; stands in for the compression sensor of
+ * Sec. 3.1).  Network Linear(20,64)-GELU-Linear(64,64)-GELU-Linear(64,1), bf16 weights
+ * and activations on the matrix cores with FP32 accumulation.  Parameters are an FP32
+ * device array of DG_MLP_NPARAM values: W1[64][20], b1[64], W2[64][64], b2[64], W3[1][64],
+ * b3[1] (y = W x + b per layer).  The output t gives nu = 1e-3 (exp(t) - 1), clipped >= 0.
+ * Degree 2 only (DG_EUNSUPPORTED otherwise).
+ * ------------------------------------------------------------------------------- */
+#define DG_MLP_NIN 20
+#define DG_MLP_NHID 64
+#define DG_MLP_NPARAM (64 * 20 + 64 + 64 * 64 + 64 + 64 + 1)
+
+/* Per-cell features x[ncell][20] (float, device): density shape W_rho,l/W_rho,0 (l=1..9),
+ * log10 W_rho,0, cell-mean velocity gradient (from the linear modes of vhat) times
+ * (h/(k+1))/cs, |mean velocity|/cs. */
+int dg_sensor_features(dg_ctx *ctx, const void *u, float *x_dev);
+
+/* Plain-sensor labels nu[ncell] (double, device): max over interior points of
+ * Pi/(rho cs^2) with the vNR form without the Pi_max cap. */
+int dg_sensor_labels(dg_ctx *ctx, const void *u, double *nu_dev);
+
+/* Install network parameters (FP32 device array, DG_MLP_NPARAM values, copied). */
+int dg_sensor_set_params(dg_ctx *ctx, const float *params_dev);
+
+/* Run features + network on u; the per-cell viscosity used by DG_LEARNED_SENSOR is
+ * stored in the workspace. */
+int dg_sensor_infer(dg_ctx *ctx, const void *u);
+
+/* Judge: recompute the plain labels of u and mark for fallback (plain sensor) every
+ * cell with |nu_learned - nu_plain| / (nu_plain + 1e-3) > tau; synchronises and returns
+ * the number of marked cells in *nfallback_host (may be NULL). */
+int dg_sensor_judge(dg_ctx *ctx, const void *u, double tau, long *nfallback_host);
+
+/* Overwrite the stored per-cell viscosity (same element type as the state, device) and
+ * fallback flags (int32 device, 1 = plain sensor); either pointer may be NULL to keep. */
+int dg_sensor_set_nu(dg_ctx *ctx, const void *nu_dev, const int32_t *fallback_dev);
+
+/* Network forward pass for n rows: x[n][20] float -> y[n] float (device). */
+int dg_mlp_forward(dg_ctx *ctx, const float *params_dev, const float *x_dev, int n, float *y_dev);
+
+/* Mean-squared-error loss and its gradient with respect to the parameters for n rows:
+ * grad_dev[DG_MLP_NPARAM] float (overwritten), loss_dev[1] float (device). */
+int dg_mlp_grad(dg_ctx *ctx, const float *params_dev, const float *x_dev, const float *t_dev,
+                int n, float *grad_dev, float *loss_dev);
+
+/* Adam update (Kingma & Ba) of the FP32 parameters in place; m_dev and v_dev are the
+ * moment buffers (DG_MLP_NPARAM floats each, zero before step 1); step counts from 1. */
+int dg_mlp_adam(dg_ctx *ctx, float *params_dev, const float *grad_dev, float *m_dev,
+                float *v_dev, int step, float lr);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

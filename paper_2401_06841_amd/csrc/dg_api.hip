@@ -1,0 +1,588 @@
+// dg_api.hip -- host side of libdg: configuration checks, quadrature tables, workspace
+// layout, kernel launches and the C ABI declared in include/dg.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dg.h"
+#include "dg_ctx.hpp"
+#include "dg_kernels.hpp"
+
+using namespace dg;
+
+// ------------------------------------------------------------------ errors
+int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...)
+{
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return dg_fail((ctx), DG_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                           __FILE__, __LINE__);                                                   \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                                            \
+    do {                                                                                          \
+        hipError_t e_ = hipGetLastError();                                                        \
+        if (e_ != hipSuccess)                                                                     \
+            return dg_fail((ctx), DG_EHIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                           __FILE__, __LINE__);                                                   \
+    } while (0)
+
+// ------------------------------------------------------------------ tables
+// Host-side FP64 construction of the basis / quadrature tables.
+namespace {
+
+// Legendre P_n and P_n' (recurrences (j+1)P_{j+1} = (2j+1)x P_j - j P_{j-1} and
+// P'_{j+1} = (j+1) P_j + x P'_j)
+void legendre_host(int n, double x, double &p, double &dp)
+{
+    double pm = 1.0, pc = x, dm = 0.0, dc = 1.0;
+    if (n == 0) { p = 1.0; dp = 0.0; return; }
+    for (int j = 1; j < n; ++j) {
+        const double pn = ((2 * j + 1) * x * pc - j * pm) / (j + 1);
+        const double dn = (j + 1) * pc + x * dc;
+        pm = pc; pc = pn; dm = dc; dc = dn;
+    }
+    (void)dm;
+    p = pc;
+    dp = dc;
+}
+
+double lt(int n, double x)
+{
+    double p, dp;
+    legendre_host(n, x, p, dp);
+    return std::sqrt(2.0 * n + 1.0) * p;
+}
+
+double dlt(int n, double x)
+{
+    double p, dp;
+    legendre_host(n, x, p, dp);
+    return std::sqrt(2.0 * n + 1.0) * dp;
+}
+
+// Gauss-Legendre rule with n <= 4 points from the closed-form nodes; weights
+// 2 / ((1 - x^2) P_n'(x)^2)
+void gauss_host(int n, double *x, double *w)
+{
+    switch (n) {
+    case 1: x[0] = 0.0; break;
+    case 2: x[0] = -1.0 / std::sqrt(3.0); x[1] = -x[0]; break;
+    case 3: x[0] = -std::sqrt(0.6); x[1] = 0.0; x[2] = -x[0]; break;
+    case 4: {
+        const double a = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(1.2));
+        const double b = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(1.2));
+        x[0] = -a; x[1] = -b; x[2] = b; x[3] = a;
+        break;
+    }
+    default: break;
+    }
+    for (int i = 0; i < n; ++i) {
+        double p, dp;
+        legendre_host(n, x[i], p, dp);
+        w[i] = 2.0 / ((1.0 - x[i] * x[i]) * dp * dp);
+    }
+}
+
+template <int K>
+void build_tables(std::vector<double> &t)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    t.assign(TL::SIZE, 0.0);
+    double g[K + 1], w[K + 1];
+    gauss_host(K + 1, g, w);
+    for (int qz = 0; qz < S::N1; ++qz)
+        for (int qy = 0; qy < S::N1; ++qy)
+            for (int qx = 0; qx < S::N1; ++qx) {
+                const int q = qx + S::N1 * (qy + S::N1 * qz);
+                const double xi[3] = {g[qx], g[qy], g[qz]};
+                t[TL::VW + q] = w[qx] * w[qy] * w[qz];
+                for (int a = 0; a < 3; ++a) t[TL::VXI + 3 * q + a] = xi[a];
+                for (int l = 0; l < S::NB; ++l) {
+                    const int *e = M.e[l];
+                    t[TL::VPHI + q * S::NB + l] = lt(e[0], xi[0]) * lt(e[1], xi[1]) * lt(e[2], xi[2]);
+                    for (int d = 0; d < 3; ++d) {
+                        if (M.dj[d][l] < 0) continue;
+                        double v = 1.0;
+                        for (int a = 0; a < 3; ++a) v *= (a == d) ? dlt(e[a], xi[a]) : lt(e[a], xi[a]);
+                        t[TL::VDPHI + (q * 3 + d) * S::ND + M.dj[d][l]] = v;
+                    }
+                }
+            }
+    for (int r2 = 0; r2 < S::N1; ++r2)
+        for (int r1 = 0; r1 < S::N1; ++r1) {
+            const int r = r1 + S::N1 * r2;
+            t[TL::FW + r] = w[r1] * w[r2];
+            for (int j = 0; j < S::NB2; ++j)
+                t[TL::F2 + r * S::NB2 + j] = lt(M.p2[j][0], g[r1]) * lt(M.p2[j][1], g[r2]);
+        }
+    for (int n = 0; n <= K; ++n) {
+        t[TL::LEND + 2 * n + 0] = lt(n, -1.0);
+        t[TL::LEND + 2 * n + 1] = lt(n, 1.0);
+    }
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ layout
+static void layout(dg_ctx *c, size_t *total)
+{
+    const size_t es = c->es;
+    const size_t nc = (size_t)c->nc;
+    const size_t state = align_up(4 * (size_t)c->nb * nc * es);
+    const size_t vh = align_up(3 * (size_t)c->nb * nc * es);
+    size_t o = 0;
+    c->off.un_copy = o; o += state;
+    c->off.stA = o; o += state;
+    c->off.stB = o; o += state;
+    c->off.L = o; o += state;
+    c->off.vh0 = o; o += vh;
+    c->off.vh1 = o; o += vh;
+    c->off.apts = o; o += (c->cfg.flags & DG_FORCING) ? align_up(3 * (size_t)c->nq * nc * es) : 0;
+    const bool learned = c->cfg.flags & DG_LEARNED_SENSOR;
+    c->off.nu = o; o += align_up(nc * es);
+    c->off.fb = o; o += align_up(nc * 4);
+    c->off.feat = o; o += learned ? align_up(nc * DG_MLP_NIN * 4) : 0;
+    c->off.lab = o; o += learned ? align_up(nc * 8) : 0;
+    c->off.part = o; o += align_up((size_t)c->nblk * 4 * 8);
+    c->off.scal = o; o += align_up(64 * 8);
+    c->off.iflags = o; o += align_up(64 * 4);
+    *total = o;
+}
+
+void dg_config_default(dg_config *cfg, int nx, int ny, int nz)
+{
+    if (!cfg) return;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->nx = nx; cfg->ny = ny; cfg->nz = nz;
+    cfg->degree = 2;
+    cfg->precision = DG_FP64;
+    cfg->flags = DG_AV | DG_PRIM_PROJ | DG_POS_LIMITER;
+    cfg->h = nx > 0 ? 1.0 / nx : 0.0;
+    cfg->cs = 1.0;
+    cfg->cfl = 0.3;
+    cfg->alpha_visc = 2.0;
+    cfg->beta_visc = 0.2;
+    cfg->rho_floor = 1e-3;
+    cfg->stream = nullptr;
+}
+
+int dg_init(const dg_config *cfg, dg_ctx **out)
+{
+    if (!out) return DG_EINVAL;
+    *out = nullptr;
+    if (!cfg) return DG_EINVAL;
+    if (cfg->nx < 1 || cfg->ny < 1 || cfg->nz < 1) return DG_EINVAL;
+    if ((long long)cfg->nx * cfg->ny * cfg->nz > (1LL << 30)) return DG_EINVAL;
+    if (cfg->degree < 1 || cfg->degree > 3) return DG_EUNSUPPORTED;
+    if (cfg->precision != DG_FP64 && cfg->precision != DG_FP32) return DG_EINVAL;
+    if (!(cfg->cs > 0.0) || !(cfg->cfl > 0.0) || cfg->alpha_visc < 0.0 || cfg->beta_visc < 0.0 ||
+        !(cfg->rho_floor >= 0.0))
+        return DG_EINVAL;
+    if ((cfg->flags & DG_LEARNED_SENSOR) && cfg->degree != 2) return DG_EUNSUPPORTED;
+    {
+        // each [var] block of nb mode planes is addressed through one buffer descriptor
+        const long long ncl = (long long)cfg->nx * cfg->ny * cfg->nz;
+        const int kk = cfg->degree, nbk = (kk + 1) * (kk + 2) * (kk + 3) / 6, nqk = (kk + 1) * (kk + 1) * (kk + 1);
+        const long long es = cfg->precision == DG_FP64 ? 8 : 4;
+        const long long maxblk = (long long)(nbk > nqk ? nbk : nqk) * ncl * es;
+        if (maxblk >= (1LL << 32)) return DG_EINVAL;
+    }
+    dg_ctx *c = new (std::nothrow) dg_ctx();
+    if (!c) return DG_ENOMEM;
+    c->cfg = *cfg;
+    if (!(c->cfg.h > 0.0)) c->cfg.h = 1.0 / cfg->nx;
+    c->k = cfg->degree;
+    c->nb = (c->k + 1) * (c->k + 2) * (c->k + 3) / 6;
+    c->nq = (c->k + 1) * (c->k + 1) * (c->k + 1);
+    c->nc = cfg->nx * cfg->ny * cfg->nz;
+    c->es = cfg->precision == DG_FP64 ? 8 : 4;
+    c->nblk = (c->nc + BLOCK - 1) / BLOCK;
+    c->stream = (hipStream_t)cfg->stream;
+    layout(c, &c->ws_need);
+
+    std::vector<double> t;
+    switch (c->k) {
+    case 1: build_tables<1>(t); break;
+    case 2: build_tables<2>(t); break;
+    default: build_tables<3>(t); break;
+    }
+    int rc = DG_OK;
+    hipError_t e = hipMalloc(&c->tab, t.size() * c->es);
+    if (e != hipSuccess) { delete c; return DG_EHIP; }
+    if (c->es == 8) {
+        e = hipMemcpy(c->tab, t.data(), t.size() * 8, hipMemcpyHostToDevice);
+    } else {
+        std::vector<float> tf(t.begin(), t.end());
+        e = hipMemcpy(c->tab, tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMalloc((void **)&c->modes_dev, 64 * 9 * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned, 256, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)&c->mlp_bf16, 8 * DG_MLP_NPARAM);
+    if (e != hipSuccess) rc = DG_EHIP;
+    if (rc != DG_OK) { dg_free(c); return rc; }
+    *out = c;
+    return DG_OK;
+}
+
+void dg_free(dg_ctx *c)
+{
+    if (!c) return;
+    if (c->tab) (void)hipFree(c->tab);
+    if (c->modes_dev) (void)hipFree(c->modes_dev);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->mlp_bf16) (void)hipFree(c->mlp_bf16);
+    delete c;
+}
+
+const char *dg_last_error(const dg_ctx *c) { return c ? c->err : "null context"; }
+
+size_t dg_workspace_bytes(const dg_ctx *c) { return c ? c->ws_need : 0; }
+
+int dg_set_workspace(dg_ctx *c, void *ws, size_t bytes)
+{
+    if (!c) return DG_EINVAL;
+    if (!ws) return dg_fail(c, DG_EINVAL, "workspace pointer is null");
+    if ((uintptr_t)ws & 255) return dg_fail(c, DG_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < c->ws_need)
+        return dg_fail(c, DG_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, c->ws_need);
+    c->ws = (char *)ws;
+    c->forcing_dirty = c->nmodes > 0;
+    return DG_OK;
+}
+
+static int need_ws(dg_ctx *c)
+{
+    if (!c->ws) return dg_fail(c, DG_ENOMEM, "no workspace set (dg_set_workspace)");
+    return DG_OK;
+}
+
+static int check_ptr(dg_ctx *c, const void *p, const char *name)
+{
+    if (!p) return dg_fail(c, DG_EINVAL, "%s is null", name);
+    if ((uintptr_t)p & (c->es - 1)) return dg_fail(c, DG_EINVAL, "%s is misaligned", name);
+    return DG_OK;
+}
+
+int dg_set_forcing(dg_ctx *c, const double *modes_host, int nmodes)
+{
+    if (!c) return DG_EINVAL;
+    if (nmodes < 0 || nmodes > 64 || (nmodes > 0 && !modes_host))
+        return dg_fail(c, DG_EINVAL, "bad forcing table (nmodes=%d)", nmodes);
+    std::memcpy(c->modes_host, modes_host, sizeof(double) * 9 * nmodes);
+    c->nmodes = nmodes;
+    HIPCHK(c, hipMemcpy(c->modes_dev, c->modes_host, sizeof(double) * 9 * (nmodes > 0 ? nmodes : 1),
+                        hipMemcpyHostToDevice));
+    c->forcing_dirty = true;
+    return DG_OK;
+}
+
+int dg_forcing_get(const dg_ctx *c, double *modes_host, int nmodes_max)
+{
+    if (!c || !modes_host) return DG_EINVAL;
+    const int n = c->nmodes < nmodes_max ? c->nmodes : nmodes_max;
+    std::memcpy(modes_host, c->modes_host, sizeof(double) * 9 * n);
+    return c->nmodes;
+}
+
+// ------------------------------------------------------------------ launches
+template <typename T, int K>
+static int launch_forcing_points(dg_ctx *c)
+{
+    const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    hipLaunchKernelGGL((k_forcing_points<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->wp(c->off.apts),
+                       c->modes_dev, c->nmodes, c->tab, g, c->cfg.h);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+template <typename T, int K>
+static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int *fail)
+{
+    const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    hipLaunchKernelGGL((k_project<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, vh, c->tab, g, c->cfg.cs,
+                       part, fail);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+template <typename T, int K>
+static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt)
+{
+    if ((c->cfg.flags & DG_FORCING) && c->forcing_dirty) {
+        int rc = launch_forcing_points<T, K>(c);
+        if (rc) return rc;
+        c->forcing_dirty = false;
+    }
+    RhsArgs a;
+    a.u = u;
+    a.vh = vh;
+    a.out = out;
+    a.tab = c->tab;
+    a.apts = c->wp(c->off.apts);
+    a.nu = c->wp(c->off.nu);
+    a.fb = (const int *)c->wp(c->off.fb);
+    a.part = (double *)c->wp(c->off.part);
+    a.g = Mesh{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    a.flags = c->cfg.flags;
+    if (c->nmodes == 0) a.flags &= ~DG_FORCING;
+    a.h = c->cfg.h;
+    a.cs = c->cfg.cs;
+    a.alpha = c->cfg.alpha_visc;
+    a.beta = c->cfg.beta_visc;
+    a.dt = dt;
+    hipLaunchKernelGGL((k_rhs<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+static bool use_meanfree(const dg_ctx *c)
+{
+    return (c->cfg.flags & DG_FORCING) && (c->cfg.flags & DG_FORCE_MEANFREE) && c->nmodes > 0;
+}
+
+static int launch_abar(dg_ctx *c)
+{
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->nblk, 1,
+                       1.0, c->abar());
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+template <typename T, int K>
+static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
+                        void *un_copy, double ca, double cb, double dt, long long *nlim)
+{
+    StageArgs a;
+    a.ui = ui;
+    a.un = un;
+    a.L = L;
+    a.out = out;
+    a.vh_out = vh_out;
+    a.un_copy = un_copy;
+    a.tab = c->tab;
+    a.abar = (L && use_meanfree(c)) ? c->abar() : nullptr;
+    a.fail = c->fail();
+    a.nlim = nlim;
+    a.g = Mesh{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    a.flags = c->cfg.flags;
+    a.ca = ca;
+    a.cb = cb;
+    a.dt = dt;
+    a.rho_floor = c->cfg.rho_floor;
+    hipLaunchKernelGGL((k_stage<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+template <typename T, int K>
+static int do_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
+{
+    int rc = launch_project<T, K>(c, u, c->wp(c->off.vh0), nullptr, nullptr);
+    if (rc) return rc;
+    rc = launch_rhs<T, K>(c, u, c->wp(c->off.vh0), dudt, dt);
+    if (rc) return rc;
+    if (use_meanfree(c)) {
+        rc = launch_abar(c);
+        if (rc) return rc;
+        hipLaunchKernelGGL((k_meanfree<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, dudt, c->abar(), c->nc);
+        LAUNCHCHK(c);
+    }
+    return DG_OK;
+}
+
+int sensor_infer_impl(dg_ctx *c, const void *u);
+
+template <typename T, int K>
+static int do_step(dg_ctx *c, void *u, double dt, int *status_host)
+{
+    static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
+    static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
+    void *vh[2] = {c->wp(c->off.vh0), c->wp(c->off.vh1)};
+    void *st[3] = {c->wp(c->off.stA), c->wp(c->off.stB), u};
+    const bool learned = c->cfg.flags & DG_LEARNED_SENSOR;
+    int rc = launch_project<T, K>(c, u, vh[0], nullptr, c->fail());
+    if (rc) return rc;
+    const void *ui = u;
+    for (int s = 0; s < 3; ++s) {
+        if (learned) {
+            rc = sensor_infer_impl(c, ui);
+            if (rc) return rc;
+        }
+        rc = launch_rhs<T, K>(c, ui, vh[s & 1], c->wp(c->off.L), dt);
+        if (rc) return rc;
+        if (use_meanfree(c)) {
+            rc = launch_abar(c);
+            if (rc) return rc;
+        }
+        rc = launch_stage<T, K>(c, ui, u, c->wp(c->off.L), st[s], s < 2 ? vh[(s + 1) & 1] : nullptr,
+                                s == 0 ? c->wp(c->off.un_copy) : nullptr, CA[s], CB[s], dt, nullptr);
+        if (rc) return rc;
+        ui = st[s];
+    }
+    HIPCHK(c, hipMemcpyAsync(c->pinned, c->fail(), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int st_flag = ((volatile int *)c->pinned)[0];
+    if (status_host) *status_host = st_flag ? DG_RETRY : DG_OK;
+    if (st_flag) {
+        const size_t bytes = 4 * (size_t)c->nb * c->nc * c->es;
+        HIPCHK(c, hipMemcpyAsync(u, c->wp(c->off.un_copy), bytes, hipMemcpyDeviceToDevice, c->stream));
+        return DG_RETRY;
+    }
+    return DG_OK;
+}
+
+#define DISPATCH(c, FN, ...)                                                        \
+    ((c)->es == 8 ? ((c)->k == 1   ? FN<double, 1>(__VA_ARGS__)                     \
+                     : (c)->k == 2 ? FN<double, 2>(__VA_ARGS__)                     \
+                                   : FN<double, 3>(__VA_ARGS__))                    \
+                  : ((c)->k == 1   ? FN<float, 1>(__VA_ARGS__)                      \
+                     : (c)->k == 2 ? FN<float, 2>(__VA_ARGS__)                      \
+                                   : FN<float, 3>(__VA_ARGS__)))
+
+static int learned_ready(dg_ctx *c)
+{
+    if ((c->cfg.flags & DG_LEARNED_SENSOR) && !c->have_nu && !c->have_params)
+        return dg_fail(c, DG_ESTATE, "learned sensor enabled but neither parameters nor nu were set");
+    return DG_OK;
+}
+
+int dg_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u")) || (rc = check_ptr(c, dudt, "dudt"))) return rc;
+    if ((rc = learned_ready(c))) return rc;
+    if ((c->cfg.flags & DG_LEARNED_SENSOR) && !c->have_nu) {
+        rc = sensor_infer_impl(c, u);
+        if (rc) return rc;
+    }
+    return DISPATCH(c, do_rhs, c, u, dudt, dt);
+}
+
+int dg_rk_step(dg_ctx *c, void *u, double dt, int *status_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
+    if ((c->cfg.flags & DG_LEARNED_SENSOR) && !c->have_params)
+        return dg_fail(c, DG_ESTATE, "learned sensor step needs network parameters");
+    return DISPATCH(c, do_step, c, u, dt, status_host);
+}
+
+template <typename T, int K>
+static int do_dt(dg_ctx *c, const void *u, double *dt_out, int on_host)
+{
+    double *part = (double *)c->wp(c->off.part);
+    int rc = launch_project<T, K>(c, u, nullptr, part, nullptr);
+    if (rc) return rc;
+    double *dst = on_host ? c->scal() + 8 : dt_out;
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 2,
+                       c->cfg.cfl * c->cfg.h / (K + 1), dst);
+    LAUNCHCHK(c);
+    if (on_host) {
+        HIPCHK(c, hipMemcpyAsync(c->pinned, dst, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *dt_out = ((volatile double *)c->pinned)[0];
+    }
+    return DG_OK;
+}
+
+int dg_dt_max(dg_ctx *c, const void *u, double *dt_out, int on_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
+    if (!dt_out) return dg_fail(c, DG_EINVAL, "dt_out is null");
+    return DISPATCH(c, do_dt, c, u, dt_out, on_host);
+}
+
+template <typename T, int K>
+static int do_proj(dg_ctx *c, const void *u, void *vh)
+{
+    return launch_project<T, K>(c, u, vh, nullptr, nullptr);
+}
+
+int dg_project_primitive(dg_ctx *c, const void *u, void *vhat)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = check_ptr(c, u, "u")) || (rc = check_ptr(c, vhat, "vhat"))) return rc;
+    return DISPATCH(c, do_proj, c, u, vhat);
+}
+
+template <typename T, int K>
+static int do_limit(dg_ctx *c, void *u, long *nfail)
+{
+    long long *cnt = (long long *)(c->scal() + 16);
+    int *fl = c->fail();
+    // zero the counters with a tiny copy from pinned host zeros (no memset nodes)
+    std::memset(c->pinned + 8, 0, 16);
+    HIPCHK(c, hipMemcpyAsync(cnt, c->pinned + 8, 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(fl, c->pinned + 8, 4, hipMemcpyHostToDevice, c->stream));
+    int rc = launch_stage<T, K>(c, u, u, nullptr, u, nullptr, nullptr, 0.0, 1.0, 0.0, cnt);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->pinned, cnt, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (nfail) *nfail = (long)((volatile long long *)c->pinned)[0];
+    return DG_OK;
+}
+
+int dg_limit(dg_ctx *c, void *u, long *nfail_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
+    const int saved = c->cfg.flags;
+    c->cfg.flags |= DG_POS_LIMITER;
+    rc = DISPATCH(c, do_limit, c, u, nfail_host);
+    c->cfg.flags = saved;
+    return rc;
+}
+
+template <typename T, int K>
+static int do_sums(dg_ctx *c, const void *u, double *out)
+{
+    const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    double *part = (double *)c->wp(c->off.part);
+    hipLaunchKernelGGL((k_sums<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, g, part);
+    LAUNCHCHK(c);
+    const double h3 = c->cfg.h * c->cfg.h * c->cfg.h;
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 0, h3,
+                       c->scal() + 24);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipMemcpyAsync(c->pinned, c->scal() + 24, 32, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 4; ++i) out[i] = ((volatile double *)c->pinned)[i];
+    return DG_OK;
+}
+
+int dg_conserved_sums(dg_ctx *c, const void *u, double *out_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
+    if (!out_host) return dg_fail(c, DG_EINVAL, "out_host is null");
+    return DISPATCH(c, do_sums, c, u, out_host);
+}

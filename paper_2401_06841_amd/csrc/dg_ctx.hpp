@@ -1,0 +1,44 @@
+// dg_ctx.hpp -- the opaque context behind the C ABI (host-side bookkeeping only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "dg.h"
+
+struct dg_offsets {
+    size_t un_copy, stA, stB, L, vh0, vh1, apts, nu, fb, feat, lab, part, scal, iflags;
+};
+
+struct dg_ctx {
+    dg_config cfg{};
+    int k = 0, nb = 0, nq = 0, nc = 0, nblk = 0;
+    size_t es = 8;                 // element size of the state (8 = FP64, 4 = FP32)
+    hipStream_t stream = nullptr;
+    void *tab = nullptr;           // quadrature tables (element type of the state)
+    double *modes_dev = nullptr;   // driving mode table [64][9]
+    double modes_host[64 * 9] = {};
+    int nmodes = 0;
+    bool forcing_dirty = false;
+    double *pinned = nullptr;      // 256 bytes of pinned host memory for read-backs
+    char *ws = nullptr;            // caller's workspace
+    size_t ws_need = 0;
+    dg_offsets off{};
+    // Ornstein-Uhlenbeck driving state: 16 modes x 3 complex components
+    double ou_tc = 0.0, ou_sigma = 0.0;
+    double ou_x[16 * 6] = {};
+    int ou_ready = 0;
+    // learned sensor
+    void *mlp_bf16 = nullptr;      // device copy of the parameters (fp32 master + bf16 weights)
+    bool have_params = false;
+    bool have_nu = false;
+    char err[512] = {0};
+
+    void *wp(size_t o) const { return ws + o; }
+    double *scal() const { return (double *)(ws + off.scal); }
+    double *abar() const { return scal(); }          // scal[0..2]
+    int *fail() const { return (int *)(ws + off.iflags); }
+};
+
+int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...);

@@ -1,0 +1,776 @@
+// dg_kernels.hpp -- gfx950 kernels of the DG right-hand side and SSP-RK3 stage.
+//
+// Mapping: one lane per cell, 256 cells per workgroup (4 wave64s), cells numbered
+// x-fastest so that a wavefront reads 64 consecutive cells of every [var][mode] plane
+// (fully coalesced 512-byte FP64 / 256-byte FP32 rows).  All quadrature tables are
+// indexed with wave-uniform indices and are fetched with scalar loads; the structural
+// zeros of the derivative tables (modes without an exponent along an axis) are skipped
+// at compile time.  Reductions (CFL maximum, conservation and driving sums) are done in
+// FP64 with a fixed tree order, so repeated runs are bitwise identical.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dg_basis.hpp"
+
+namespace dg {
+
+enum : int { F_AV = 1, F_PRIM = 2, F_FORCE = 4, F_LIMIT = 8, F_LEARNED = 16, F_MEANFREE = 32 };
+
+constexpr int BLOCK = 256;
+
+// Workgroups are dispatched round-robin over the 8 XCDs; remap so that consecutive
+// logical blocks (neighbouring slabs of cells) share one XCD and its L2.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int per = n >> 3;
+    if (b >= (per << 3)) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sum of NV values over the 256 lanes of a block, fixed order; result valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) lds[w * NV + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] = ((lds[i] + lds[NV + i]) + (lds[2 * NV + i] + lds[3 * NV + i]));
+}
+
+__device__ __forceinline__ double block_max(double v, double *lds)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v = wave_max(v);
+    if (lane == 0) lds[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) v = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+    return v;
+}
+
+struct Mesh {
+    int nx, ny, nz, nc;
+};
+
+// Quadrature tables live in the constant address space: wave-uniform indices then
+// compile to scalar (SMEM) loads through the scalar cache instead of per-lane loads.
+template <typename T>
+using ctab = const __attribute__((address_space(4))) T;
+
+template <typename T>
+__device__ __forceinline__ ctab<T> *as_tab(const void *p)
+{
+    return (ctab<T> *)(p);
+}
+
+// periodic neighbours of cell c: nb[0..5] = -x, +x, -y, +y, -z, +z
+__device__ __forceinline__ void neighbours(const Mesh &g, int c, int (&nb)[6], int (&ijk)[3])
+{
+    const int i = c % g.nx;
+    const int r = c / g.nx;
+    const int j = r % g.ny;
+    const int l = r / g.ny;
+    ijk[0] = i; ijk[1] = j; ijk[2] = l;
+    nb[0] = c + ((i == 0) ? g.nx - 1 : -1);
+    nb[1] = c + ((i == g.nx - 1) ? 1 - g.nx : 1);
+    const int sy = g.nx;
+    nb[2] = c + ((j == 0) ? (g.ny - 1) * sy : -sy);
+    nb[3] = c + ((j == g.ny - 1) ? (1 - g.ny) * sy : sy);
+    const int sz = g.nx * g.ny;
+    nb[4] = c + ((l == 0) ? (g.nz - 1) * sz : -sz);
+    nb[5] = c + ((l == g.nz - 1) ? (1 - g.nz) * sz : sz);
+}
+
+
+// Coalesced access to element (mode plane, cell) through buffer resources: one
+// descriptor (4 SGPRs) per variable block, the mode plane as a uniform SGPR offset and
+// the lane part as one 32-bit byte offset shared by every access of the cell.  A block
+// of nb planes must stay below 4 GiB (checked at set-up).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ rsrc_t mkrs(const void *base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xFFFFFFFF, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T bld(rsrc_t r, unsigned voff, unsigned soff);
+
+template <>
+__device__ __forceinline__ double bld<double>(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
+template <>
+__device__ __forceinline__ float bld<float>(rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bst(rsrc_t r, unsigned voff, unsigned soff, T v);
+
+template <>
+__device__ __forceinline__ void bst<double>(rsrc_t r, unsigned voff, unsigned soff, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          voff, soff, 0);
+}
+
+template <>
+__device__ __forceinline__ void bst<float>(rsrc_t r, unsigned voff, unsigned soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+
+// a [nvar][nb][nc] array viewed through one descriptor per variable
+template <typename T, int NV>
+struct Field {
+    rsrc_t r[NV];
+    unsigned pstride;   // bytes between mode planes
+    __device__ __forceinline__ Field(const void *base, int nb, int nc)
+    {
+        pstride = (unsigned)nc * (unsigned)sizeof(T);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r[v] = mkrs((const char *)base + (size_t)v * nb * pstride);
+    }
+    // trace sources: density block of u, then the three blocks of the projected velocity
+    __device__ __forceinline__ Field(const void *u, const void *vh, int nb, int nc)
+    {
+        pstride = (unsigned)nc * (unsigned)sizeof(T);
+        r[0] = mkrs(u);
+#pragma unroll
+        for (int v = 1; v < NV; ++v) r[v] = mkrs((const char *)vh + (size_t)(v - 1) * nb * pstride);
+    }
+    __device__ __forceinline__ Field(const Field &) = default;
+    __device__ __forceinline__ T get(int v, int l, unsigned boff) const { return bld<T>(r[v], boff, l * pstride); }
+    __device__ __forceinline__ void put(int v, int l, unsigned boff, T x) const { bst<T>(r[v], boff, l * pstride, x); }
+};
+
+// fast reciprocal: hardware estimate refined by two Newton steps (about 1 ulp)
+__device__ __forceinline__ double rcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ float rcp(float x)
+{
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = fmaf(-x, r, 1.0f);
+    return fmaf(r, e, r);
+}
+
+// ------------------------------------------------------------------ arguments
+struct RhsArgs {
+    const void *u;          // [4][NB][nc]
+    const void *vh;         // [3][NB][nc] projected velocity of u
+    void *out;              // [4][NB][nc] right-hand side
+    const void *tab;        // quadrature tables (TabLayout)
+    const void *apts;       // [3][NQ][nc] driving acceleration at the volume points
+    const void *nu;         // [nc] learned viscosity
+    const int *fb;          // [nc] fallback flags
+    double *part;           // [nblocks][4] driving partial sums (mode-0 source, mass)
+    Mesh g;
+    int flags;
+    double h, cs, alpha, beta, dt;
+};
+
+struct StageArgs {
+    const void *ui;         // stage input u^(i)
+    const void *un;         // u^n (may alias ui for stage 1)
+    const void *L;          // right-hand side of u^(i) (NULL: plain copy/limit of ui)
+    void *out;              // u^(i+1) (may alias un)
+    void *vh_out;           // projection of u^(i+1) for the next stage, or NULL
+    void *un_copy;          // where to keep u^n for a retry, or NULL
+    const void *tab;
+    const double *abar;     // removed mean acceleration (3), or NULL
+    int *fail;              // positivity failure flag
+    long long *nlim;        // count of failing cells (may be NULL)
+    Mesh g;
+    int flags;
+    double ca, cb, dt, rho_floor;
+};
+
+// ------------------------------------------------------------------ helpers
+template <typename T, int K, int NV>
+__device__ __forceinline__ void load_field(const Field<T, NV> &f, unsigned bo, T (&W)[NV][Shape<K>::NB])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int l = 0; l < Shape<K>::NB; ++l) W[v][l] = f.get(v, l, bo);
+}
+
+template <typename T, int K, int NV>
+__device__ __forceinline__ void store_field(const Field<T, NV> &f, unsigned bo, const T (&W)[NV][Shape<K>::NB])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int l = 0; l < Shape<K>::NB; ++l) f.put(v, l, bo, W[v][l]);
+}
+
+// projected velocity of one cell from its weights (Sec. 3.2): vh_{d,l} = 1/8 sum_q w_q phi_l v_d
+template <typename T, int K>
+__device__ __forceinline__ void project_cell(const T (&W)[4][Shape<K>::NB], ctab<T> *tab,
+                                             T (&V)[3][Shape<K>::NB], double *smax, T cs)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) V[d][l] = T(0);
+    double sm = 0.0;
+    for (int q = 0; q < S::NQ; ++q) {
+        ctab<T> *ph = tab + TL::VPHI + q * S::NB;
+        T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            const T p = ph[l];
+            rho += W[0][l] * p;
+            m0 += W[1][l] * p;
+            m1 += W[2][l] * p;
+            m2 += W[3][l] * p;
+        }
+        const T ir = rcp(rho);
+        const T v0 = m0 * ir, v1 = m1 * ir, v2 = m2 * ir;
+        if (smax) {
+            const double s = (double)fabs(v0) + (double)fabs(v1) + (double)fabs(v2) + 3.0 * (double)cs;
+            sm = fmax(sm, s);
+        }
+        const T wq = T(0.125) * tab[TL::VW + q];
+        const T a0 = wq * v0, a1 = wq * v1, a2 = wq * v2;
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            const T p = ph[l];
+            V[0][l] += a0 * p;
+            V[1][l] += a1 * p;
+            V[2][l] += a2 * p;
+        }
+    }
+    if (smax) *smax = sm;
+}
+
+// isothermal Rusanov flux across a face with normal +e_D between the low (L) and high
+// (R) states; u = (rho, m), v = velocity (Sec. 2.2 numerical flux)
+template <int D, typename T>
+__device__ __forceinline__ void rusanov(T cs, T cs2, const T (&uL)[4], const T (&vL)[3], const T (&uR)[4],
+                                        const T (&vR)[3], T (&F)[4])
+{
+    const T lam = fmax(fabs(vL[D]), fabs(vR[D])) + cs;
+    const T hl = T(0.5) * lam;
+    F[0] = T(0.5) * (uL[1 + D] + uR[1 + D]) - hl * (uR[0] - uL[0]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+        F[1 + j] = T(0.5) * (uL[1 + D] * vL[j] + uR[1 + D] * vR[j]) - hl * (uR[1 + j] - uL[1 + j]);
+    F[1 + D] += T(0.5) * cs2 * (uL[0] + uR[0]);
+}
+
+// von Neumann-Richtmyer viscous pressure at one point (Sec. 3.1)
+template <typename T>
+__device__ __forceinline__ T vnr_pi(T rho, T divv, T hp, T alpha, T beta, T cs, T inv_dt)
+{
+    const T s = -divv;
+    T pi = alpha * rho * hp * hp * s * s + beta * rho * cs * hp * s;
+    const T pmax = T(0.5) * rho * hp * hp * s * inv_dt;
+    pi = fmin(pi, pmax);
+    return s > T(0) ? pi : T(0);
+}
+
+// ---------------------------------------------------------------- face pass
+// Surface integral of one face (normal axis D, side s: 0 = low, 1 = high) lifted into L.
+template <typename T, int K, int D>
+__device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsigned bn, int s,
+                                     ctab<T> *tab, bool prim, T cs, T cs2, T (&L)[4][Shape<K>::NB])
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    T Co[4][S::NB2], Cn[4][S::NB2];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) { Co[v][j] = T(0); Cn[v][j] = T(0); }
+    // collapse the 3D expansions onto the face: Lt_e(+-1) along D
+    ctab<T> *lend = tab + TL::LEND;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            const int e = M.e[l][D];
+            const T wo = src.get(v, l, bo);
+            const T wn = src.get(v, l, bn);
+            Co[v][M.d2[D][l]] += wo * lend[2 * e + s];
+            Cn[v][M.d2[D][l]] += wn * lend[2 * e + 1 - s];
+            // keep at most one variable's loads in flight (register pressure)
+            if (l == S::NB - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+    T Dacc[4][S::NB2];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) Dacc[v][j] = T(0);
+#pragma unroll 1
+    for (int r = 0; r < S::NF; ++r) {
+        ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
+        T uo[4], un[4], vo[3], vn[3];
+        T ao[4] = {T(0), T(0), T(0), T(0)}, an[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) {
+            const T f = f2[j];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                ao[v] += Co[v][j] * f;
+                an[v] += Cn[v][j] * f;
+            }
+        }
+        uo[0] = ao[0];
+        un[0] = an[0];
+        if (prim) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                vo[d] = ao[1 + d]; uo[1 + d] = ao[0] * ao[1 + d];
+                vn[d] = an[1 + d]; un[1 + d] = an[0] * an[1 + d];
+            }
+        } else {
+            const T io = rcp(ao[0]), in = rcp(an[0]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                uo[1 + d] = ao[1 + d]; vo[d] = ao[1 + d] * io;
+                un[1 + d] = an[1 + d]; vn[d] = an[1 + d] * in;
+            }
+        }
+        T F[4];
+        if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
+        else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
+        const T wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];   // outward normal
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T g = wr * F[v];
+#pragma unroll
+            for (int j = 0; j < S::NB2; ++j) Dacc[v][j] += g * f2[j];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) L[v][l] += Dacc[v][M.d2[D][l]] * lend[2 * M.e[l][D] + s];
+}
+
+// ------------------------------------------------------------------ RHS kernel
+// dw/dt = (1/(4h)) [ sum_q w_q grad_xi(phi) . F(q) - sum_faces +- sum_r w_r phi F*(r) ]
+//         + (1/8) sum_q w_q phi rho a (Sec. 2.2 weight evolution; Sec. 3.1; Sec. 4.2)
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_rhs(RhsArgs a)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    constexpr int NB = S::NB, ND = S::ND;
+    __shared__ double lds[4 * 4];
+    ctab<T> *tab = as_tab<T>(a.tab);
+    const int nc = a.g.nc;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int c0 = blk * BLOCK + threadIdx.x;
+    const bool active = c0 < nc;
+    const int c = active ? c0 : 0;
+
+    const bool av = a.flags & F_AV;
+    const bool prim = a.flags & F_PRIM;
+    const bool force = a.flags & F_FORCE;
+    const T cs = (T)a.cs, cs2 = (T)(a.cs * a.cs);
+    const T hp = (T)(a.h / (K + 1));
+    // dt <= 0: no Pi_max cap (a huge finite factor keeps 0 * cap = 0)
+    const T inv_dt = a.dt > 0.0 ? (T)(1.0 / a.dt) : (sizeof(T) == 4 ? T(1e30f) : T(1e300));
+    const T alpha = (T)a.alpha, beta = (T)a.beta;
+    const T two_h = (T)(2.0 / a.h);
+
+    const unsigned bo = (unsigned)c * sizeof(T);
+    const Field<T, 4> U(a.u, NB, nc);
+    const Field<T, 3> VH(a.vh, NB, nc);
+    T W[4][NB];
+    load_field<T, K, 4>(U, bo, W);
+
+    // derivative-relevant coefficients of the projected velocity (divergence, Sec. 3.1)
+    T G[3][ND];
+    bool learned = false;
+    T nu = T(0), trg = T(0);
+    if (av) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int l = 0; l < NB; ++l)
+                if (M.dj[d][l] >= 0) G[d][M.dj[d][l]] = VH.get(d, l, bo);
+        if (a.flags & F_LEARNED) {
+            learned = a.fb[c] == 0;
+            nu = ((const T *)a.nu)[c];
+            // cell-mean divergence from the linear modes: d/dxi Lt_1 = sqrt(3)
+            trg = two_h * T(1.7320508075688772) * (G[0][M.dj[0][1]] + G[1][M.dj[1][2]] + G[2][M.dj[2][3]]);
+        }
+    }
+
+    T L[4][NB];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) L[v][l] = T(0);
+    T fs0 = T(0), fs1 = T(0), fs2 = T(0);
+    const Field<T, 3> AP(a.apts, S::NQ, nc);
+    const T half_h = (T)(0.5 * a.h);
+
+    // ---- volume integral
+#pragma unroll 1
+    for (int q = 0; q < S::NQ; ++q) {
+        ctab<T> *ph = tab + TL::VPHI + q * NB;
+        ctab<T> *dph = tab + TL::VDPHI + q * 3 * ND;
+        const T wq = tab[TL::VW + q];
+        T rho = T(0), m[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            const T p = ph[l];
+            rho += W[0][l] * p;
+            m[0] += W[1][l] * p;
+            m[1] += W[2][l] * p;
+            m[2] += W[3][l] * p;
+        }
+        T pi = T(0);
+        if (av) {
+            T div = T(0);
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int j = 0; j < ND; ++j) div += G[d][j] * dph[d * ND + j];
+            div *= two_h;
+            const T pv = vnr_pi<T>(rho, div, hp, alpha, beta, cs, inv_dt);
+            // learned sensor: Pi = nu rho cs^2 capped by the same Pi_max with |tr G|;
+            // none where the cell expands and nu is below nu0 = 1e-3
+            T pl = nu * rho * cs2;
+            pl = fmin(pl, T(0.5) * rho * hp * hp * fabs(trg) * inv_dt);
+            pl = (trg >= T(0) && nu < T(1e-3)) || !(nu > T(0)) ? T(0) : pl;
+            pi = learned ? pl : pv;
+        }
+        const T ir = rcp(rho);
+        const T pw = (cs2 * rho + pi) * wq;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T md = m[d] * wq;
+            const T mdr = md * ir;
+            T F[4];
+            F[0] = md;
+            F[1] = mdr * m[0];
+            F[2] = mdr * m[1];
+            F[3] = mdr * m[2];
+            F[1 + d] += pw;
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                if (M.dj[d][l] < 0) continue;
+                const T dp = dph[d * ND + M.dj[d][l]];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) L[v][l] += dp * F[v];
+            }
+        }
+        if (force) {
+            const T rw = rho * wq;
+            const T s0 = rw * AP.get(0, q, bo);
+            const T s1 = rw * AP.get(1, q, bo);
+            const T s2 = rw * AP.get(2, q, bo);
+            fs0 += s0; fs1 += s1; fs2 += s2;
+            const T t0 = s0 * half_h, t1 = s1 * half_h, t2 = s2 * half_h;
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const T p = ph[l];
+                L[1][l] += t0 * p;
+                L[2][l] += t1 * p;
+                L[3][l] += t2 * p;
+            }
+        }
+    }
+    const T mass0 = W[0][0];
+
+    // ---- surface integral (traces: rho and either the projected velocity or m)
+    int nbr[6], ijk[3];
+    neighbours(a.g, c, nbr, ijk);
+    const Field<T, 4> SRC = prim ? Field<T, 4>(a.u, a.vh, NB, nc) : U;
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s)
+        face<T, K, 0>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * sizeof(T), s, tab, prim, cs, cs2, L);
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s)
+        face<T, K, 1>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * sizeof(T), s, tab, prim, cs, cs2, L);
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s)
+        face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, cs, cs2, L);
+
+    const T inv4h = (T)(0.25 / a.h);
+    if (active) {
+        const Field<T, 4> O(a.out, NB, nc);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) O.put(v, l, bo, L[v][l] * inv4h);
+    }
+    if (force && a.part) {
+        double acc[4] = {active ? 0.125 * (double)fs0 : 0.0, active ? 0.125 * (double)fs1 : 0.0,
+                         active ? 0.125 * (double)fs2 : 0.0, active ? (double)mass0 : 0.0};
+        block_sum<4>(acc, lds);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a.part[blk * 4 + i] = acc[i];
+    }
+}
+
+// --------------------------------------------------------------- stage kernel
+// out = ca*un + cb*(ui + dt*(L - abar W_rho)) (Shu-Osher SSP-RK3 stage), then the
+// positivity limiter (Sec. 3.1) with FP64 comparisons, then the projected velocity of
+// the result for the next stage.
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    constexpr int NB = S::NB;
+    __shared__ double lds[4];
+    const int nc = a.g.nc;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int c0 = blk * BLOCK + threadIdx.x;
+    const bool active = c0 < nc;
+    const int c = active ? c0 : 0;
+    const unsigned bo = (unsigned)c * sizeof(T);
+    ctab<T> *tab = as_tab<T>(a.tab);
+
+    T U[4][NB];
+    load_field<T, K, 4>(Field<T, 4>(a.ui, NB, nc), bo, U);
+    if (a.un_copy && active) store_field<T, K, 4>(Field<T, 4>(a.un_copy, NB, nc), bo, U);
+    if (a.L) {
+        const Field<T, 4> LF(a.L, NB, nc);
+        const Field<T, 4> UN(a.un, NB, nc);
+        const T ca = (T)a.ca, cb = (T)a.cb, dt = (T)a.dt;
+        T ab[3] = {T(0), T(0), T(0)};
+        if (a.abar) { ab[0] = (T)a.abar[0]; ab[1] = (T)a.abar[1]; ab[2] = (T)a.abar[2]; }
+        const bool use_un = a.ca != 0.0;
+#pragma unroll
+        for (int v = 3; v >= 0; --v)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                T rhs = LF.get(v, l, bo);
+                if (v > 0) rhs -= ab[v - 1] * U[0][l];
+                const T x = U[v][l] + dt * rhs;
+                U[v][l] = use_un ? ca * UN.get(v, l, bo) + cb * x : cb * x;
+            }
+    }
+    if (a.flags & F_LIMIT) {
+        // minimum density over the volume and face Gauss points
+        T rmin = T(__builtin_huge_valf());
+#pragma unroll 1
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<T> *ph = tab + TL::VPHI + q * NB;
+            T r = T(0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) r += U[0][l] * ph[l];
+            rmin = fmin(rmin, r);
+        }
+        ctab<T> *lend = tab + TL::LEND;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                T C[S::NB2];
+#pragma unroll
+                for (int j = 0; j < S::NB2; ++j) C[j] = T(0);
+#pragma unroll
+                for (int l = 0; l < NB; ++l) C[M.d2[d][l]] += U[0][l] * lend[2 * M.e[l][d] + s];
+#pragma unroll 1
+                for (int r = 0; r < S::NF; ++r) {
+                    ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
+                    T val = T(0);
+#pragma unroll
+                    for (int j = 0; j < S::NB2; ++j) val += C[j] * f2[j];
+                    rmin = fmin(rmin, val);
+                }
+            }
+        const double mean = (double)U[0][0];
+        const double fl = a.rho_floor;
+        const double rm = (double)rmin;
+        int bad = 0;
+        if (!(mean > fl)) {
+            bad = active ? 1 : 0;
+        } else if (rm < fl) {
+            const T theta = (T)((mean - fl) / (mean - rm));
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int l = 1; l < NB; ++l) U[v][l] *= theta;
+        }
+        if (bad) atomicOr(a.fail, 1);
+        if (a.nlim) {
+            double cnt[1] = {(double)bad};
+            block_sum<1>(cnt, lds);
+            if (threadIdx.x == 0 && cnt[0] > 0.0) atomicAdd((unsigned long long *)a.nlim, (unsigned long long)cnt[0]);
+        }
+    }
+    if (active) store_field<T, K, 4>(Field<T, 4>(a.out, NB, nc), bo, U);
+    if (a.vh_out) {
+        T V[3][NB];
+        project_cell<T, K>(U, tab, V, nullptr, T(0));
+        if (active) store_field<T, K, 3>(Field<T, 3>(a.vh_out, NB, nc), bo, V);
+    }
+}
+
+// ------------------------------------------------------------ projection kernel
+// vhat of u (Sec. 3.2) and, optionally, the per-block maximum signal speed for the
+// CFL step and a reset of the failure flag.
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, const void *tab_, Mesh g,
+                                                   double cs, double *part, int *fail)
+{
+    using S = Shape<K>;
+    constexpr int NB = S::NB;
+    __shared__ double lds[4];
+    const int nc = g.nc;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int c0 = blk * BLOCK + threadIdx.x;
+    const bool active = c0 < nc;
+    const int c = active ? c0 : 0;
+    const unsigned bo = (unsigned)c * sizeof(T);
+    if (fail && blockIdx.x == 0 && threadIdx.x == 0) *fail = 0;
+    T W[4][NB];
+    load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
+    T V[3][NB];
+    double sm = 0.0;
+    project_cell<T, K>(W, as_tab<T>(tab_), V, part ? &sm : nullptr, (T)cs);
+    if (vh_ && active) store_field<T, K, 3>(Field<T, 3>(vh_, NB, nc), bo, V);
+    if (part) {
+        sm = block_max(active ? sm : 0.0, lds);
+        if (threadIdx.x == 0) part[blk] = sm;
+    }
+}
+
+// driving acceleration a(x) = sum_m Re[a_m exp(2 pi i n_m.x)] at every volume point (Sec. 4.2)
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_forcing_points(void *apts_, const double *modes, int nmodes,
+                                                          const void *tab_, Mesh g, double h)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    const int nc = g.nc;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= nc) return;
+    ctab<T> *tab = as_tab<T>(tab_);
+    const int i = c % g.nx, r = c / g.nx, j = r % g.ny, l = r / g.ny;
+    T *ap = (T *)apts_;
+    for (int q = 0; q < S::NQ; ++q) {
+        const double x = (i + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + 0]) * h;
+        const double y = (j + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + 1]) * h;
+        const double z = (l + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + 2]) * h;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int m = 0; m < nmodes; ++m) {
+            const double *e = modes + 9 * m;
+            double sp, cp;
+            sincospi(2.0 * (e[0] * x + e[1] * y + e[2] * z), &sp, &cp);
+            ax += e[3] * cp - e[4] * sp;
+            ay += e[5] * cp - e[6] * sp;
+            az += e[7] * cp - e[8] * sp;
+        }
+        ap[(0 * S::NQ + q) * (size_t)nc + c] = (T)ax;
+        ap[(1 * S::NQ + q) * (size_t)nc + c] = (T)ay;
+        ap[(2 * S::NQ + q) * (size_t)nc + c] = (T)az;
+    }
+}
+
+// per-block sums of the cell means (conservation totals, Sec. 2.2: w_0 is the mean)
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_sums(const void *u_, Mesh g, double *part)
+{
+    constexpr int NB = Shape<K>::NB;
+    __shared__ double lds[16];
+    const int nc = g.nc;
+    const int c0 = blockIdx.x * BLOCK + threadIdx.x;
+    const bool active = c0 < nc;
+    const int c = active ? c0 : 0;
+    const T *u = (const T *)u_;
+    double v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = active ? (double)u[(i * NB) * (size_t)nc + c] : 0.0;
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[blockIdx.x * 4 + i] = v[i];
+}
+
+// single-block fixed-order reductions of per-block partials
+// mode 0: out[i] = scale * sum part[.][i], i < 4
+// mode 1: out[0..2] = sum part[.][0..2] / sum part[.][3]   (mass-weighted mean acceleration)
+// mode 2: out[0] = num / max part[.]                        (CFL step)
+__global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double *out)
+{
+    __shared__ double lds[16];
+    if (mode == 2) {
+        double m = 0.0;
+        for (int i = threadIdx.x; i < np; i += BLOCK) m = fmax(m, part[i]);
+        m = block_max(m, lds);
+        if (threadIdx.x == 0) out[0] = scale / m;
+        return;
+    }
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < np; i += BLOCK)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += part[4 * i + k];
+    block_sum<4>(s, lds);
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) out[k] = scale * s[k];
+        } else {
+            out[0] = s[0] / s[3];
+            out[1] = s[1] / s[3];
+            out[2] = s[2] / s[3];
+        }
+    }
+}
+
+// dudt_m -= abar W_rho (mean-free driving applied to a stand-alone right-hand side)
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_meanfree(const void *u_, void *dudt_, const double *abar, int nc)
+{
+    constexpr int NB = Shape<K>::NB;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= nc) return;
+    const T *u = (const T *)u_;
+    T *o = (T *)dudt_;
+    const T ab[3] = {(T)abar[0], (T)abar[1], (T)abar[2]};
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+        const T r = u[l * (size_t)nc + c];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) o[((1 + d) * NB + l) * (size_t)nc + c] -= ab[d] * r;
+    }
+}
+
+}  // namespace dg
