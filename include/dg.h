@@ -66,13 +66,17 @@ typedef struct dg_config {
     double alpha_visc;     /* quadratic vNR coefficient (paper default 2) */
     double beta_visc;      /* linear (bulk) coefficient (paper default 0.2) */
     double rho_floor;      /* positivity floor of the density (1e-3) */
+    double rho_floor_rel;  /* the limiter lifts the minimum point density to max(rho_floor,
+                              rho_floor_rel * cell mean) (0.1; 0 = absolute floor only) */
+    double cfl_visc;       /* viscous stability factor of dg_dt_max (0.1; <= 0 disables) */
     void *stream;          /* hipStream_t for every launch; NULL = default stream */
 } dg_config;
 
 typedef struct dg_ctx dg_ctx;
 
 /* Fill a configuration with the defaults: k = 2, FP64, AV | PRIM_PROJ | POS_LIMITER,
- * h = 1/nx, cs = 1, cfl = 0.3, alpha = 2, beta = 0.2 (Sec. 3.1), floor 1e-3. */
+ * h = 1/nx, cs = 1, cfl = 0.3, alpha = 2, beta = 0.2 (Sec. 3.1), floor 1e-3, relative
+ * floor 0.1, viscous factor 0.1. */
 void dg_config_default(dg_config *cfg, int nx, int ny, int nz);
 
 /* Create a context: checks the configuration, builds the basis / quadrature tables on
@@ -109,14 +113,19 @@ int dg_set_forcing(dg_ctx *ctx, const double *modes_host, int nmodes);
 int dg_rhs(dg_ctx *ctx, const void *u, void *dudt, double dt);
 
 /* One third-order SSP Runge-Kutta step in place (Shu-Osher form), positivity limiter
- * after every stage when DG_POS_LIMITER is set.  Synchronises the stream once to read
+ * after every stage when DG_POS_LIMITER is set (Sec. 3.1: all high-order weights of a cell
+ * scaled by one factor so that the density at every volume and face Gauss point is at
+ * least max(rho_floor, rho_floor_rel * cell mean)).  Synchronises the stream once to read
  * the 4-byte status into *status_host (may be NULL).  Returns DG_RETRY (and restores u
  * to its value at entry, kept in the workspace) when a cell mean fell to or below the
  * floor, i.e. the caller must retry with a smaller dt (Sec. 3.1). */
 int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
 
-/* CFL time step dt = cfl h / ((k+1) max_{cells, interior points} sum_d (|m_d/rho| + cs))
- * (Sec. 7: dt proportional to h/(k+1)), reduced in FP64.  on_host = 1: *dt_out is host
+/* Time step dt = min(dt_adv, dt_visc), reduced in FP64 over all cells and interior points:
+ * dt_adv = cfl h / ((k+1) max sum_d (|m_d/rho| + cs)) (Sec. 7: dt proportional to h/(k+1));
+ * with DG_AV and cfl_visc > 0, dt_visc = cfl_visc (h/p)^2 / max nu, the explicit stability
+ * bound of the viscous pressure read as a bulk viscosity nu = alpha (h/p)^2 |div v| +
+ * beta cs (h/p) at compressing points (Sec. 3.1; p = k+1).  on_host = 1: *dt_out is host
  * memory and the call synchronises; on_host = 0: *dt_out is device memory (8 bytes). */
 int dg_dt_max(dg_ctx *ctx, const void *u, double *dt_out, int on_host);
 
@@ -131,6 +140,14 @@ int dg_limit(dg_ctx *ctx, void *u, long *nfail_host);
 /* Conserved totals (mass, momentum x/y/z) = h^3 sum_cells W_v,0, FP64 fixed-order
  * reduction; out_host[4] host memory; synchronises. */
 int dg_conserved_sums(dg_ctx *ctx, const void *u, double *out_host);
+
+/* Instrumentation: with enable = 1 every launch of the right-hand-side kernel and of the
+ * stage-combination kernel issued by dg_rhs / dg_rk_step is bracketed by HIP events on
+ * the context stream and the elapsed times are accumulated (counters cleared);
+ * enable = 0 stops.  dg_profile_read synchronises and writes out_host[4] = {RHS-kernel
+ * milliseconds, RHS launches, stage-kernel milliseconds, stage launches}. */
+int dg_profile(dg_ctx *ctx, int enable);
+int dg_profile_read(dg_ctx *ctx, double *out_host);
 
 /* Ornstein-Uhlenbeck driving on the shell 1 <= |n| <= 2 (Sec. 4.2), host-side FP64:
  * dg_forcing_ou_init sets the correlation time t_c and the stationary standard deviation

@@ -92,12 +92,13 @@ class _Cfg(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("k", ctypes.c_int),
                 ("h", ctypes.c_double), ("cs", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("rho_floor", ctypes.c_double),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("rho_floor_rel", ctypes.c_double), ("cfl_visc", ctypes.c_double)]
 
 
 @dataclasses.dataclass
 class Cfg:
-    """Mesh and method parameters (defaults: Sec. 3.1 alpha=2, beta=0.2; floor 1e-3)."""
+    """Mesh and method parameters (defaults: Sec. 3.1 alpha=2, beta=0.2; floor 1e-3; the
+    limiter aims at max(floor, rho_floor_rel * cell mean))."""
     nx: int
     ny: int
     nz: int
@@ -109,6 +110,8 @@ class Cfg:
     beta: float = 0.2
     rho_floor: float = 1e-3
     flags: int = POS_LIMITER
+    rho_floor_rel: float = 0.1
+    cfl_visc: float = 0.1
 
     def __post_init__(self):
         if self.h is None:
@@ -128,7 +131,8 @@ class Cfg:
 
     def c(self):
         return ctypes.byref(_Cfg(self.nx, self.ny, self.nz, self.k, self.h, self.cs, self.cfl,
-                                 self.alpha, self.beta, self.rho_floor, self.flags))
+                                 self.alpha, self.beta, self.rho_floor, self.flags, self.rho_floor_rel,
+                                 self.cfl_visc))
 
 
 def _d(a):

@@ -48,6 +48,8 @@ typedef struct {
     int nx, ny, nz, k;
     double h, cs, cfl, alpha, beta, rho_floor;
     int flags;
+    double rho_floor_rel;
+    double cfl_visc;
 } orc_cfg;
 
 /* ---------------------------------------------------------------- 1D pieces */
@@ -578,8 +580,14 @@ int orc_rhs_cells(const orc_cfg *cfg, const double *u, double dt, const double *
 
 /* ------------------------------------------------------------ time step */
 
-/* CFL time step (Sec. 7: dt proportional to h/(k+1)); reading:
- * dt = cfl h / ((k+1) max_{K,q} sum_d (|m_d/rho| + cs)) over the interior Gauss points. */
+/* Time step.  Advective part (Sec. 7: dt proportional to h/(k+1)); reading:
+ * dt_adv = cfl h / ((k+1) max_{K,q} sum_d (|m_d/rho| + cs)) over the interior Gauss points.
+ * Viscous part (reading; the paper only caps Pi so that one step cannot reverse the
+ * compression, Sec. 3.1): with artificial viscosity on, the viscous pressure acts as a
+ * bulk viscosity nu = Pi / (rho |div v|) = alpha (h/p)^2 |div v| + beta cs (h/p) at
+ * compressing points (div v of the projected velocity, p = k+1), and the explicit
+ * stability bound dt_visc = cfl_visc (h/p)^2 / max nu applies; dt = min(dt_adv, dt_visc).
+ * cfl_visc <= 0 or AV off: advective part only. */
 double orc_dt_max(const orc_cfg *cfg, const double *u)
 {
     if (check_cfg(cfg)) return -1.0;
@@ -587,33 +595,60 @@ double orc_dt_max(const orc_cfg *cfg, const double *u)
     make_tabs(cfg->k, T);
     long nc = ncell_of(cfg);
     int nb = T->nb;
+    double hp = cfg->h / (cfg->k + 1);
+    int visc = (cfg->flags & ORC_AV) && cfg->cfl_visc > 0.0;
     double *smax = malloc(sizeof(double) * nc);
+    double *numax = malloc(sizeof(double) * nc);
     #pragma omp parallel for schedule(static)
     for (long c = 0; c < nc; ++c) {
-        double sm = 0.0;
+        double sm = 0.0, nm = 0.0;
+        double vh[3 * NBMAX];
+        if (visc) project_cell(T, u, nc, c, vh);
         for (int q = 0; q < T->nq; ++q) {
             double rho = expand(u, nb, nc, 0, c, T->vphi[q]);
             double s = 0.0;
             for (int d = 0; d < 3; ++d) s += fabs(expand(u, nb, nc, 1 + d, c, T->vphi[q]) / rho) + cfg->cs;
             if (s > sm) sm = s;
+            if (visc) {
+                double divv = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    for (int l = 0; l < nb; ++l) divv += vh[d * nb + l] * T->vdphi[q][d][l];
+                divv *= 2.0 / cfg->h;
+                if (divv < 0.0) {
+                    double nu = cfg->alpha * hp * hp * (-divv) + cfg->beta * cfg->cs * hp;
+                    if (nu > nm) nm = nu;
+                }
+            }
         }
         smax[c] = sm;
+        numax[c] = nm;
     }
-    double m = 0.0;
-    for (long c = 0; c < nc; ++c) if (smax[c] > m) m = smax[c];
+    double m = 0.0, nmax = 0.0;
+    for (long c = 0; c < nc; ++c) {
+        if (smax[c] > m) m = smax[c];
+        if (numax[c] > nmax) nmax = numax[c];
+    }
     free(smax);
+    free(numax);
     free(T);
-    return cfg->cfl * cfg->h / ((cfg->k + 1) * m);
+    double dt = cfg->cfl * cfg->h / ((cfg->k + 1) * m);
+    if (visc && nmax > 0.0) {
+        double dv = cfg->cfl_visc * hp * hp / nmax;
+        if (dv < dt) dt = dv;
+    }
+    return dt;
 }
 
 /* ----------------------------------------------------- positivity limiter */
 
 /* Positivity limiter of one cell (Sec. 3.1, last paragraph; floor 1e-3 from the
  * density-PDF figure): rho_min over all volume and face Gauss points; if below the
- * floor while the mean is above it, scale every high-order weight of all four
- * variables by theta = (mean - floor)/(mean - rho_min).  A mean at or below the
- * floor cannot be fixed by scaling: return 1 (the step must be retried with a
- * smaller dt).  Returns 0 otherwise; *theta_out gets the factor used (1 = none). */
+ * target while the mean is above the floor, scale every high-order weight of all four
+ * variables by theta = (mean - target)/(mean - rho_min).  Reading (the paper does not
+ * state the value the scaling aims at): target = max(floor, rho_floor_rel * mean), so a
+ * limited cell keeps no near-vacuum interior point where m/rho would be unbounded.  A mean
+ * at or below the floor cannot be fixed by scaling: return 1 (the step must be retried
+ * with a smaller dt).  Returns 0 otherwise; *theta_out gets the factor used (1 = none). */
 static int limit_cell(const orc_cfg *cfg, const tabs_t *T, double *u, long nc, long c, double *theta_out)
 {
     int nb = T->nb;
@@ -631,8 +666,10 @@ static int limit_cell(const orc_cfg *cfg, const tabs_t *T, double *u, long nc, l
             }
     if (theta_out) *theta_out = 1.0;
     if (!(mean > cfg->rho_floor)) return 1;
-    if (rmin < cfg->rho_floor) {
-        double theta = (mean - cfg->rho_floor) / (mean - rmin);
+    double target = cfg->rho_floor;
+    if (cfg->rho_floor_rel * mean > target) target = cfg->rho_floor_rel * mean;
+    if (rmin < target) {
+        double theta = (mean - target) / (mean - rmin);
         for (int v = 0; v < NV; ++v)
             for (int l = 1; l < nb; ++l) u[((long)v * nb + l) * nc + c] *= theta;
         if (theta_out) *theta_out = theta;

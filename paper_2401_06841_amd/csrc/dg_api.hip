@@ -184,6 +184,8 @@ void dg_config_default(dg_config *cfg, int nx, int ny, int nz)
     cfg->alpha_visc = 2.0;
     cfg->beta_visc = 0.2;
     cfg->rho_floor = 1e-3;
+    cfg->rho_floor_rel = 0.1;
+    cfg->cfl_visc = 0.1;
     cfg->stream = nullptr;
 }
 
@@ -197,7 +199,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
     if (cfg->degree < 1 || cfg->degree > 3) return DG_EUNSUPPORTED;
     if (cfg->precision != DG_FP64 && cfg->precision != DG_FP32) return DG_EINVAL;
     if (!(cfg->cs > 0.0) || !(cfg->cfl > 0.0) || cfg->alpha_visc < 0.0 || cfg->beta_visc < 0.0 ||
-        !(cfg->rho_floor >= 0.0))
+        !(cfg->rho_floor >= 0.0) || !(cfg->rho_floor_rel >= 0.0) || !(cfg->rho_floor_rel < 1.0))
         return DG_EINVAL;
     if ((cfg->flags & DG_LEARNED_SENSOR) && cfg->degree != 2) return DG_EUNSUPPORTED;
     {
@@ -248,6 +250,9 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
 void dg_free(dg_ctx *c)
 {
     if (!c) return;
+    for (int i = 0; i < 2 * dg_ctx::NEV; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
     if (c->tab) (void)hipFree(c->tab);
     if (c->modes_dev) (void)hipFree(c->modes_dev);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -305,6 +310,64 @@ int dg_forcing_get(const dg_ctx *c, double *modes_host, int nmodes_max)
     return c->nmodes;
 }
 
+// ------------------------------------------------------------------ timing
+static int prof_drain(dg_ctx *c)
+{
+    for (int i = 0; i < c->nev; ++i) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventSynchronize(c->ev[i][1]));
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i][0], c->ev[i][1]));
+        c->prof_ms[c->ev_kind[i]] += ms;
+        c->prof_n[c->ev_kind[i]] += 1;
+    }
+    c->nev = 0;
+    return DG_OK;
+}
+
+// bracket one launch with events when profiling: call with stop = 0 before, 1 after
+static int prof_mark(dg_ctx *c, int kind, int stop)
+{
+    if (!c->prof) return DG_OK;
+    if (!stop && c->nev >= 2 * dg_ctx::NEV) {
+        int rc = prof_drain(c);
+        if (rc) return rc;
+    }
+    const int i = c->nev;
+    HIPCHK(c, hipEventRecord(c->ev[i][stop], c->stream));
+    if (stop) {
+        c->ev_kind[i] = kind;
+        c->nev++;
+    }
+    return DG_OK;
+}
+
+int dg_profile(dg_ctx *c, int enable)
+{
+    if (!c) return DG_EINVAL;
+    if (enable) {
+        for (int i = 0; i < 2 * dg_ctx::NEV; ++i)
+            for (int j = 0; j < 2; ++j)
+                if (!c->ev[i][j]) HIPCHK(c, hipEventCreate(&c->ev[i][j]));
+        c->nev = 0;
+        c->prof_ms[0] = c->prof_ms[1] = 0.0;
+        c->prof_n[0] = c->prof_n[1] = 0;
+    }
+    c->prof = enable != 0;
+    return DG_OK;
+}
+
+int dg_profile_read(dg_ctx *c, double *out)
+{
+    if (!c || !out) return DG_EINVAL;
+    int rc = prof_drain(c);
+    if (rc) return rc;
+    out[0] = c->prof_ms[0];
+    out[1] = (double)c->prof_n[0];
+    out[2] = c->prof_ms[1];
+    out[3] = (double)c->prof_n[1];
+    return DG_OK;
+}
+
 // ------------------------------------------------------------------ launches
 template <typename T, int K>
 static int launch_forcing_points(dg_ctx *c)
@@ -320,7 +383,13 @@ template <typename T, int K>
 static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int *fail)
 {
     const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
-    hipLaunchKernelGGL((k_project<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, vh, c->tab, g, c->cfg.cs,
+    ProjArgs pa;
+    pa.cs = c->cfg.cs;
+    pa.h = c->cfg.h;
+    pa.alpha = c->cfg.alpha_visc;
+    pa.beta = c->cfg.beta_visc;
+    pa.visc = (c->cfg.flags & DG_AV) && c->cfg.cfl_visc > 0.0;
+    hipLaunchKernelGGL((k_project<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, vh, c->tab, g, pa,
                        part, fail);
     LAUNCHCHK(c);
     return DG_OK;
@@ -351,9 +420,11 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     a.alpha = c->cfg.alpha_visc;
     a.beta = c->cfg.beta_visc;
     a.dt = dt;
+    int rc = prof_mark(c, 0, 0);
+    if (rc) return rc;
     hipLaunchKernelGGL((k_rhs<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
     LAUNCHCHK(c);
-    return DG_OK;
+    return prof_mark(c, 0, 1);
 }
 
 static bool use_meanfree(const dg_ctx *c)
@@ -364,7 +435,7 @@ static bool use_meanfree(const dg_ctx *c)
 static int launch_abar(dg_ctx *c)
 {
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->nblk, 1,
-                       1.0, c->abar());
+                       1.0, 0.0, c->abar());
     LAUNCHCHK(c);
     return DG_OK;
 }
@@ -390,9 +461,12 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.cb = cb;
     a.dt = dt;
     a.rho_floor = c->cfg.rho_floor;
+    a.rho_floor_rel = c->cfg.rho_floor_rel;
+    int rc = prof_mark(c, 1, 0);
+    if (rc) return rc;
     hipLaunchKernelGGL((k_stage<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
     LAUNCHCHK(c);
-    return DG_OK;
+    return prof_mark(c, 1, 1);
 }
 
 template <typename T, int K>
@@ -498,8 +572,10 @@ static int do_dt(dg_ctx *c, const void *u, double *dt_out, int on_host)
     int rc = launch_project<T, K>(c, u, nullptr, part, nullptr);
     if (rc) return rc;
     double *dst = on_host ? c->scal() + 8 : dt_out;
+    const double hp = c->cfg.h / (K + 1);
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 2,
-                       c->cfg.cfl * c->cfg.h / (K + 1), dst);
+                       c->cfg.cfl * c->cfg.h / (K + 1), c->cfg.cfl_visc > 0.0 ? c->cfg.cfl_visc * hp * hp : 0.0,
+                       dst);
     LAUNCHCHK(c);
     if (on_host) {
         HIPCHK(c, hipMemcpyAsync(c->pinned, dst, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -569,7 +645,7 @@ static int do_sums(dg_ctx *c, const void *u, double *out)
     hipLaunchKernelGGL((k_sums<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, g, part);
     LAUNCHCHK(c);
     const double h3 = c->cfg.h * c->cfg.h * c->cfg.h;
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 0, h3,
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 0, h3, 0.0,
                        c->scal() + 24);
     LAUNCHCHK(c);
     HIPCHK(c, hipMemcpyAsync(c->pinned, c->scal() + 24, 32, hipMemcpyDeviceToHost, c->stream));

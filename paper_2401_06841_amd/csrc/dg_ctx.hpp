@@ -33,6 +33,14 @@ struct dg_ctx {
     void *mlp_bf16 = nullptr;      // device copy of the parameters (fp32 master + bf16 weights)
     bool have_params = false;
     bool have_nu = false;
+    // kernel timing (dg_profile)
+    static constexpr int NEV = 64;
+    bool prof = false;
+    hipEvent_t ev[2 * NEV][2] = {};    // [slot][start/stop]
+    int ev_kind[2 * NEV] = {};         // 0 = rhs kernel, 1 = stage kernel
+    int nev = 0;
+    double prof_ms[2] = {0.0, 0.0};
+    long prof_n[2] = {0, 0};
     char err[512] = {0};
 
     void *wp(size_t o) const { return ws + o; }

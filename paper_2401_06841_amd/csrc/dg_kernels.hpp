@@ -213,7 +213,7 @@ struct StageArgs {
     long long *nlim;        // count of failing cells (may be NULL)
     Mesh g;
     int flags;
-    double ca, cb, dt, rho_floor;
+    double ca, cb, dt, rho_floor, rho_floor_rel;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -547,8 +547,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 
 // --------------------------------------------------------------- stage kernel
 // out = ca*un + cb*(ui + dt*(L - abar W_rho)) (Shu-Osher SSP-RK3 stage), then the
-// positivity limiter (Sec. 3.1) with FP64 comparisons, then the projected velocity of
-// the result for the next stage.
+// positivity limiter (Sec. 3.1; target minimum max(floor, rel * mean)) with FP64
+// comparisons, then the projected velocity of the result for the next stage.
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
 {
@@ -618,11 +618,12 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
         const double mean = (double)U[0][0];
         const double fl = a.rho_floor;
         const double rm = (double)rmin;
+        const double target = fmax(fl, a.rho_floor_rel * mean);
         int bad = 0;
         if (!(mean > fl)) {
             bad = active ? 1 : 0;
-        } else if (rm < fl) {
-            const T theta = (T)((mean - fl) / (mean - rm));
+        } else if (rm < target) {
+            const T theta = (T)((mean - target) / (mean - rm));
 #pragma unroll
             for (int v = 0; v < 4; ++v)
 #pragma unroll
@@ -644,14 +645,22 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
 }
 
 // ------------------------------------------------------------ projection kernel
-// vhat of u (Sec. 3.2) and, optionally, the per-block maximum signal speed for the
-// CFL step and a reset of the failure flag.
+struct ProjArgs {
+    double cs, h, alpha, beta;
+    int visc;   // also reduce the largest bulk viscosity of the viscous pressure
+};
+
+// vhat of u (Sec. 3.2) and, optionally, per-block maxima for the time step (signal speed
+// sum_d |v_d| + cs; viscosity alpha (h/p)^2 |div v| + beta cs h/p at compressing points)
+// and a reset of the failure flag.
 template <typename T, int K>
-__global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, const void *tab_, Mesh g,
-                                                   double cs, double *part, int *fail)
+__global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, const void *tab_, Mesh g, ProjArgs pa,
+                                                   double *part, int *fail)
 {
     using S = Shape<K>;
-    constexpr int NB = S::NB;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    constexpr int NB = S::NB, ND = S::ND;
     __shared__ double lds[4];
     const int nc = g.nc;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -660,15 +669,40 @@ __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, co
     const int c = active ? c0 : 0;
     const unsigned bo = (unsigned)c * sizeof(T);
     if (fail && blockIdx.x == 0 && threadIdx.x == 0) *fail = 0;
+    ctab<T> *tab = as_tab<T>(tab_);
     T W[4][NB];
     load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
     T V[3][NB];
     double sm = 0.0;
-    project_cell<T, K>(W, as_tab<T>(tab_), V, part ? &sm : nullptr, (T)cs);
+    project_cell<T, K>(W, tab, V, part ? &sm : nullptr, (T)pa.cs);
     if (vh_ && active) store_field<T, K, 3>(Field<T, 3>(vh_, NB, nc), bo, V);
     if (part) {
+        double nm = 0.0;
+        if (pa.visc) {
+            // most negative divergence of the projected velocity over the interior points
+            const double hp = pa.h / (K + 1);
+            double smin = 0.0;
+#pragma unroll 1
+            for (int q = 0; q < S::NQ; ++q) {
+                ctab<T> *dph = tab + TL::VDPHI + q * 3 * ND;
+                T div = T(0);
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+#pragma unroll
+                    for (int l = 0; l < NB; ++l)
+                        if (M.dj[d][l] >= 0) div += V[d][l] * dph[d * ND + M.dj[d][l]];
+                smin = fmin(smin, (double)div);
+            }
+            const double s = -smin * (2.0 / pa.h);
+            if (s > 0.0) nm = pa.alpha * hp * hp * s + pa.beta * pa.cs * hp;
+        }
         sm = block_max(active ? sm : 0.0, lds);
-        if (threadIdx.x == 0) part[blk] = sm;
+        __syncthreads();
+        nm = block_max(active ? nm : 0.0, lds);
+        if (threadIdx.x == 0) {
+            part[2 * blk] = sm;
+            part[2 * blk + 1] = nm;
+        }
     }
 }
 
@@ -727,15 +761,26 @@ __global__ void __launch_bounds__(BLOCK) k_sums(const void *u_, Mesh g, double *
 // single-block fixed-order reductions of per-block partials
 // mode 0: out[i] = scale * sum part[.][i], i < 4
 // mode 1: out[0..2] = sum part[.][0..2] / sum part[.][3]   (mass-weighted mean acceleration)
-// mode 2: out[0] = num / max part[.]                        (CFL step)
-__global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double *out)
+// mode 2: out[0] = min(scale / max part[.][0], scale2 / max part[.][1])   (time step; the
+//         second term only when scale2 > 0 and the maximum is positive)
+__global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double scale2,
+                                                 double *out)
 {
     __shared__ double lds[16];
     if (mode == 2) {
-        double m = 0.0;
-        for (int i = threadIdx.x; i < np; i += BLOCK) m = fmax(m, part[i]);
+        double m = 0.0, n = 0.0;
+        for (int i = threadIdx.x; i < np; i += BLOCK) {
+            m = fmax(m, part[2 * i]);
+            n = fmax(n, part[2 * i + 1]);
+        }
         m = block_max(m, lds);
-        if (threadIdx.x == 0) out[0] = scale / m;
+        __syncthreads();
+        n = block_max(n, lds);
+        if (threadIdx.x == 0) {
+            double dt = scale / m;
+            if (scale2 > 0.0 && n > 0.0) dt = fmin(dt, scale2 / n);
+            out[0] = dt;
+        }
         return;
     }
     double s[4] = {0.0, 0.0, 0.0, 0.0};

@@ -30,7 +30,8 @@ class dg_config(ctypes.Structure):
                 ("degree", ctypes.c_int), ("precision", ctypes.c_int), ("flags", ctypes.c_int),
                 ("h", ctypes.c_double), ("cs", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("alpha_visc", ctypes.c_double), ("beta_visc", ctypes.c_double),
-                ("rho_floor", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("rho_floor", ctypes.c_double), ("rho_floor_rel", ctypes.c_double), ("cfl_visc", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
 
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -50,6 +51,8 @@ _SIGS = {
     "dg_project_primitive": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_limit": (ctypes.c_int, [_vp, _vp, _lp]),
     "dg_conserved_sums": (ctypes.c_int, [_vp, _vp, _dp]),
+    "dg_profile": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dg_profile_read": (ctypes.c_int, [_vp, _dp]),
     "dg_forcing_ou_ndraws": (ctypes.c_int, []),
     "dg_forcing_ou_init": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
     "dg_forcing_ou_advance": (ctypes.c_int, [_vp, _dp, ctypes.c_double]),
@@ -93,6 +96,8 @@ class Config:
     alpha_visc: float = 2.0
     beta_visc: float = 0.2
     rho_floor: float = 1e-3
+    rho_floor_rel: float = 0.1
+    cfl_visc: float = 0.1
 
     @property
     def nb(self):
@@ -124,7 +129,8 @@ class Context:
             stream = torch.cuda.current_stream()
         self.stream = stream
         c = dg_config(cfg.nx, cfg.ny, cfg.nz, cfg.degree, cfg.precision, cfg.flags, cfg.h, cfg.cs, cfg.cfl,
-                      cfg.alpha_visc, cfg.beta_visc, cfg.rho_floor, ctypes.c_void_p(stream.cuda_stream))
+                      cfg.alpha_visc, cfg.beta_visc, cfg.rho_floor, cfg.rho_floor_rel, cfg.cfl_visc,
+                      ctypes.c_void_p(stream.cuda_stream))
         h = ctypes.c_void_p()
         rc = _lib.dg_init(ctypes.byref(c), ctypes.byref(h))
         if rc != DG_OK:
@@ -218,6 +224,17 @@ def dg_conserved_sums(ctx: Context, u):
     out = (ctypes.c_double * 4)()
     ctx._chk(_lib.dg_conserved_sums(ctx.h, _ptr(u), out))
     return list(out)
+
+
+def dg_profile(ctx: Context, enable: bool):
+    ctx._chk(_lib.dg_profile(ctx.h, 1 if enable else 0))
+
+
+def dg_profile_read(ctx: Context):
+    """(rhs_ms_total, rhs_launches, stage_ms_total, stage_launches)."""
+    out = (ctypes.c_double * 4)()
+    ctx._chk(_lib.dg_profile_read(ctx.h, out))
+    return out[0], int(out[1]), out[2], int(out[3])
 
 
 def dg_forcing_ou_ndraws() -> int:

@@ -1,0 +1,123 @@
+"""Time-stepping driver around libdg (host control flow only; all arithmetic on the GPU).
+
+One driver step: CFL time step from dg_dt_max (FP64 reduction on the GPU, one 8-byte
+read-back), Ornstein-Uhlenbeck driving updates on the host whenever the simulation time
+crosses the next update time (every t_c/100, Sec. 4.2), then dg_rk_step; when the step
+reports a positivity failure the state has been restored and the step is retried with
+half the time step (Sec. 3.1).  Checkpoints are the raw [var][mode][cell] array plus a
+JSON record of the run parameters, the simulation time and the driving state.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import os
+
+import numpy as np
+
+from . import dg
+
+
+@dataclasses.dataclass
+class Driving:
+    mach: float               # target RMS Mach number
+    sigma: float              # stationary standard deviation of each OU component
+    seed: int = 0
+
+    @property
+    def t_c(self) -> float:   # eddy turnover time T = L / (2 cs Mach) with L = cs = 1 (Sec. 4.2)
+        return 1.0 / (2.0 * self.mach)
+
+    @property
+    def dt_drive(self) -> float:
+        return self.t_c / 100.0
+
+
+def gaussian_draws(seed: int, update: int, n: int):
+    """Standard normal draws for OU update number ``update`` of stream ``seed``."""
+    return np.random.default_rng([seed, update]).standard_normal(n)
+
+
+class Simulation:
+    def __init__(self, cfg: dg.Config, u=None, driving: Driving | None = None, retry_limit: int = 30):
+        import torch
+        self.cfg = cfg
+        self.ctx = dg.dg_init(cfg)
+        self.u = self.ctx.empty_state() if u is None else u
+        if u is None:
+            self.u.zero_()
+            self.u[0, 0] = 1.0                      # density 1, at rest (mode 0 is the mean)
+        self.t = 0.0
+        self.nstep = 0
+        self.retries = 0
+        self.retry_limit = retry_limit
+        self.driving = driving
+        self.n_drive = 0
+        self.next_drive = 0.0
+        if driving is not None:
+            dg.dg_forcing_ou_init(self.ctx, driving.t_c, driving.sigma)
+            self._drive(1e30)                       # start from the stationary distribution
+            self.next_drive = driving.dt_drive
+        self._torch = torch
+
+    def _drive(self, dt_drive):
+        z = gaussian_draws(self.driving.seed, self.n_drive, dg.dg_forcing_ou_ndraws())
+        dg.dg_forcing_ou_advance(self.ctx, z, dt_drive)
+        self.n_drive += 1
+
+    def step(self):
+        dt = dg.dg_dt_max(self.ctx, self.u)
+        if not (dt > 0.0 and np.isfinite(dt)):
+            raise RuntimeError(f"invalid time step {dt} at step {self.nstep}")
+        if self.driving is not None:
+            while self.t + dt >= self.next_drive:
+                self._drive(self.driving.dt_drive)
+                self.next_drive += self.driving.dt_drive
+        tries = 0
+        while dg.dg_rk_step(self.ctx, self.u, dt) == dg.DG_RETRY:
+            self.retries += 1
+            tries += 1
+            if tries > self.retry_limit:
+                raise RuntimeError(f"positivity retries exhausted at step {self.nstep}")
+            dt *= 0.5
+        self.t += dt
+        self.nstep += 1
+        return dt
+
+    def rms_mach(self):
+        """Volume-weighted RMS Mach number from the cell means (Sec. 4.1 definition with the
+        velocity of each cell's mean state)."""
+        u = self.u
+        rho = u[0, 0].double()
+        v2 = ((u[1:, 0].double() / rho) ** 2).sum(0)
+        return float(self._torch.sqrt(v2.mean()) / self.cfg.cs)
+
+    def save(self, path: str):
+        np.save(path + ".npy", self.u.detach().cpu().numpy())
+        meta = {"cfg": dataclasses.asdict(self.cfg), "t": self.t, "nstep": self.nstep,
+                "driving": dataclasses.asdict(self.driving) if self.driving else None,
+                "n_drive": self.n_drive, "next_drive": self.next_drive,
+                "modes": dg.dg_forcing_get(self.ctx).tolist()}
+        with open(path + ".json", "w") as fh:
+            json.dump(meta, fh)
+
+    @classmethod
+    def load(cls, path: str, precision: int | None = None):
+        import torch
+        with open(path + ".json") as fh:
+            meta = json.load(fh)
+        cfg = dg.Config(**meta["cfg"])
+        if precision is not None:
+            cfg = dataclasses.replace(cfg, precision=precision)
+        arr = np.load(path + ".npy")
+        dtype = torch.float64 if cfg.precision == dg.DG_FP64 else torch.float32
+        u = torch.as_tensor(arr, device="cuda").to(dtype).contiguous()
+        drv = Driving(**meta["driving"]) if meta["driving"] else None
+        sim = cls(cfg, u=u, driving=None)
+        sim.driving = drv
+        sim.t, sim.nstep = meta["t"], meta["nstep"]
+        sim.n_drive, sim.next_drive = meta["n_drive"], meta["next_drive"]
+        if drv is not None:
+            dg.dg_forcing_ou_init(sim.ctx, drv.t_c, drv.sigma)
+            dg.dg_set_forcing(sim.ctx, np.asarray(meta["modes"]))
+        return sim

@@ -63,16 +63,19 @@ def _smooth(rng, shape, kmax: float, slope: float):
 
 
 def turbulent_like(nx: int, ny: int, nz: int, k: int, mach: float, seed: int,
-                   high_amp: float = 0.08, dtype=np.float64):
+                   high_amp: float = 0.08, kmax_frac: float = 0.25, dtype=np.float64):
     """Random modal state [4][nb][ncell] resembling driven isothermal turbulence.
 
     Cell means: log-normal density with variance ln(1 + (mach/3)^2) (solenoidal driving),
-    velocity of RMS |v| = mach.  Higher modes: random, relative amplitude high_amp/(1 + l/4)
-    scaled by the local contrast, so point values vary inside every cell.
+    velocity of RMS |v| = mach.  Higher modes: random density modes of relative amplitude
+    high_amp/(1 + l/4) scaled by the local contrast, random velocity modes of amplitude
+    high_amp/(1 + l/4) times the local speed, and momentum modes built as the first-order
+    product of the two (m_l = v_mean rho_l + rho_mean v_l), so that the velocity m/rho stays
+    bounded inside every cell while the point values vary.
     """
     rng = np.random.default_rng(seed)
     shape = (nz, ny, nx)
-    kmax = max(2.0, min(nx, ny, nz) / 4.0)
+    kmax = max(2.0, min(nx, ny, nz) * kmax_frac)
     sig2 = np.log(1.0 + (mach / 3.0) ** 2)
     s = np.sqrt(sig2) * _smooth(rng, shape, kmax, 2.0)
     rho = np.exp(s - 0.5 * sig2)
@@ -80,22 +83,26 @@ def turbulent_like(nx: int, ny: int, nz: int, k: int, mach: float, seed: int,
     nb = nbasis(k)
     nc = nx * ny * nz
     u = np.zeros((4, nb, nc))
-    u[0, 0] = rho.reshape(-1)
+    r0 = rho.reshape(-1)
+    v0 = [v.reshape(-1) for v in vel]
+    u[0, 0] = r0
     for d in range(3):
-        u[1 + d, 0] = (rho * vel[d]).reshape(-1)
+        u[1 + d, 0] = r0 * v0[d]
     # local contrast: neighbour differences of the mean fields
     def contrast(f):
         c = np.zeros_like(f)
         for ax in range(3):
             c += np.abs(np.roll(f, 1, ax) - np.roll(f, -1, ax))
         return c.reshape(-1)
-    crho = contrast(np.log(rho)) + 0.05
+    crho = np.minimum(contrast(np.log(rho)) + 0.05, 1.0)
     vmag = np.sqrt(sum(v * v for v in vel)).reshape(-1) + 0.1
     for l in range(1, nb):
         a = high_amp / (1.0 + l / 4.0)
-        u[0, l] = a * u[0, 0] * np.minimum(crho, 1.0) * rng.standard_normal(nc)
+        rl = a * r0 * crho * rng.standard_normal(nc)
+        u[0, l] = rl
         for d in range(3):
-            u[1 + d, l] = a * u[0, 0] * vmag * rng.standard_normal(nc)
+            vl = a * vmag * rng.standard_normal(nc)
+            u[1 + d, l] = v0[d] * rl + r0 * vl
     return u.astype(dtype)
 
 

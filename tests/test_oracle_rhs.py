@@ -239,6 +239,37 @@ def test_cfl_uniform_closed_form(k):
     assert abs(dt - 0.3 * cfg.h / ((k + 1) * (np.abs(v0).sum() + 3.0))) < 1e-15
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("gamma", [0.5, 50.0])
+def test_dt_viscous_bound_closed_form(k, gamma):
+    """Uniform compression v = -gamma (x - x_K), rho const: the viscous pressure acts as a
+    bulk viscosity nu = alpha (h/p)^2 (3 gamma) + beta cs (h/p); dt = min(advective CFL step
+    (largest interior |v| sits at the outermost Gauss points), cfl_visc (h/p)^2 / nu)."""
+    N = 4
+    cfg = oracle.Cfg(N, N, N, k, flags=ALL, cfl_visc=0.1)
+    idx = _mode_index(k)
+    rho0 = 1.7
+    u = np.zeros(cfg.shape)
+    u[0, 0] = rho0
+    for d, e in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+        u[1 + d, idx[e]] = -gamma * rho0 * 0.5 * cfg.h / math.sqrt(3)
+    h = cfg.h
+    hp = h / (k + 1)
+    gmax = oracle.gauss(k + 1)[0].max()
+    dt_adv = 0.3 * h / ((k + 1) * 3 * (gamma * 0.5 * h * gmax + 1.0))
+    nu = 2.0 * hp * hp * 3 * gamma + 0.2 * 1.0 * hp
+    dt_visc = 0.1 * hp * hp / nu
+    assert abs(oracle.dt_max(cfg, u) - min(dt_adv, dt_visc)) < 1e-14 * min(dt_adv, dt_visc)
+    # expansion: no viscous bound; AV off: no viscous bound
+    ue = u.copy()
+    ue[1:] *= -1.0
+    assert abs(oracle.dt_max(cfg, ue) - dt_adv) < 1e-14 * dt_adv
+    cfg0 = oracle.Cfg(N, N, N, k, flags=oracle.PRIM_PROJ | oracle.POS_LIMITER, cfl_visc=0.1)
+    assert abs(oracle.dt_max(cfg0, u) - dt_adv) < 1e-14 * dt_adv
+    if gamma > 10:
+        assert dt_visc < dt_adv
+
+
 def test_ssprk3_stability_polynomial():
     for lam in [-1.0, -7.3, 2.1, 0.0]:
         for dt in [0.01, 0.2, 0.4]:
@@ -248,27 +279,32 @@ def test_ssprk3_stability_polynomial():
 
 # -------------------------------------------------------------------- limiter
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_limiter_theta_closed_form(k):
-    cfg = oracle.Cfg(2, 1, 1, k, flags=oracle.POS_LIMITER)
+@pytest.mark.parametrize("rel", [0.0, 0.1, 0.3])
+def test_limiter_theta_closed_form(k, rel):
+    """theta = (mean - target)/(mean - rho_min), target = max(floor, rel * mean): the mean is
+    untouched, every high-order weight of all four variables is scaled by theta and the new
+    minimum sits exactly on the target (linear x-profile: minimum on the low-x face)."""
+    cfg = oracle.Cfg(2, 1, 1, k, flags=oracle.POS_LIMITER, rho_floor_rel=rel)
     idx = _mode_index(k)
     u = np.zeros(cfg.shape)
     u[0, 0] = 0.5
     u[1, 0] = 0.3
     u[0, idx[(1, 0, 0)], 0] = 0.4                 # rho = 0.5 + 0.4 sqrt(3) xi: min at the face
     u[1, idx[(1, 0, 0)], 0] = 0.2
-    u[0, idx[(1, 0, 0)], 1] = 0.1                 # second cell stays above the floor
+    u[0, idx[(1, 0, 0)], 1] = 0.02                # second cell stays above every target
     lim, nfail, theta = oracle.limit(cfg, u)
     assert nfail == 0
+    target = max(1e-3, rel * 0.5)
     rmin = 0.5 - 0.4 * math.sqrt(3)
-    th = (0.5 - 1e-3) / (0.5 - rmin)
+    th = (0.5 - target) / (0.5 - rmin)
     assert abs(theta[0] - th) < 1e-15 and theta[1] == 1.0
     np.testing.assert_allclose(lim[:, 1:, 0], th * u[:, 1:, 0], atol=1e-16)
     assert np.all(lim[:, 0] == u[:, 0])           # means untouched
     assert np.all(lim[:, :, 1] == u[:, :, 1])
     vals = oracle.eval_points(cfg, k + 1, lim[:1])
-    assert vals.min() >= 1e-3 - 1e-15
-    face = 0.5 - th * 0.4 * math.sqrt(3)          # new minimum sits exactly on the floor
-    assert abs(face - 1e-3) < 1e-15
+    assert vals.min() >= target - 1e-15
+    face = 0.5 - th * 0.4 * math.sqrt(3)          # new minimum sits exactly on the target
+    assert abs(face - target) < 1e-15
 
 
 def test_limiter_retry_and_step_restore():
