@@ -1,18 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the DG SSP-RK3 step on one MI355X.
 
-A step is one pass of the whole hot path over the state: CFL time step (FP64
-reduction), driving-mode update when due (host Ornstein-Uhlenbeck + table upload),
-and one SSP-RK3 step (projection, three right-hand sides with viscosity, driving and
-Rusanov faces, three stage combinations with the positivity limiter).  The metric is
-DG degree-of-freedom updates per second per Runge-Kutta stage: 3 * 4 * nb * N^3 per
-step divided by the wall time of the timed steps.
+A step is one pass of the whole hot path over the state: time step (CFL and viscous
+bound, FP64 reduction on the GPU), driving-mode update when due (host Ornstein-Uhlenbeck
++ table upload + driving field at the quadrature points), and one SSP-RK3 step
+(projection, three right-hand sides with viscosity, driving and Rusanov faces, three
+stage combinations with the positivity limiter).  The metric is DG degree-of-freedom
+updates per second per Runge-Kutta stage: 3 * 4 * nb * N^3 per step divided by the
+wall time of the timed steps.
 
-Default workload: 64^3 cells, degree 2 (10 modes per variable, 27 Gauss points),
+Default workload (c2): 64^3 cells, degree 2 (10 modes per variable, 27 Gauss points),
 FP64, artificial viscosity + primitive projection + positivity limiter, mean-free
-solenoidal OU driving on 1 <= |n| <= 2 aimed at RMS Mach ~3 (t_c = T = 1/(2 Mach)).
-The input state is a seeded synthetic turbulence-like modal field (log-normal density,
-RMS velocity 3), resident in HBM before the timed region starts.
+solenoidal OU driving on 1 <= |n| <= 2 aimed at RMS Mach ~3 (t_c = T = 1/(2 Mach)),
+starting from density 1 at rest.  The untimed warm-up steps spin the turbulence up
+(the default 4000 warm-up steps reach t ~ 0.38, a little over two eddy turnover times);
+then exactly K steps are timed with the state resident in HBM.  The same spun-up state,
+rounded to FP32, is then timed on the FP32 path for comparison.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5]
                        [--precision fp64|fp32] [--no-compare] [--no-cpu]
@@ -20,6 +23,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -34,11 +38,13 @@ PEAK_FP64_TFLOPS = 78.6      # MI355X vector = matrix FP64 peak
 PEAK_FP32_VALU_TFLOPS = 78.6  # unpacked FP32 vector rate (packed FP32 is disabled in this build)
 
 WORKLOADS = {
-    # name: (N, degree, default precision, target Mach, driving sigma)
-    "c2": (64, 2, "fp64", 3.0, 3.0),
-    "c3": (128, 3, "fp32", 10.0, 25.0),
-    "c4": (128, 2, "fp32", 10.0, 25.0),
-    "c5": (256, 2, "fp32", 10.0, 25.0),
+    # name: (N, degree, default precision, target Mach, driving sigma, default warm-up steps)
+    # sigma: stationary standard deviation of each OU component, from a spin-up sweep
+    # (RMS Mach grows as (sigma^2 t_c)^(1/3), Sec. 4.2; the calibration is statistical)
+    "c2": (64, 2, "fp64", 3.0, 2.5, 4000),
+    "c3": (128, 3, "fp32", 10.0, 28.0, 1000),
+    "c4": (128, 2, "fp32", 10.0, 28.0, 1000),
+    "c5": (256, 2, "fp32", 10.0, 28.0, 500),
 }
 
 
@@ -65,74 +71,35 @@ def traffic_from_profiles(kernel, workload, precision, launches_unit):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(args, precision, measure_profile=True):
-    import numpy as np
+def _timed(sim, steps, measure_profile):
     import torch
 
-    import synthetic
-    from paper_2401_06841_amd import dg, model
-
-    N, k, _, mach, sigma = WORKLOADS[args.workload]
-    prec = dg.DG_FP64 if precision == "fp64" else dg.DG_FP32
-    flags = dg.DG_AV | dg.DG_PRIM_PROJ | dg.DG_POS_LIMITER | dg.DG_FORCING | dg.DG_FORCE_MEANFREE
-    cfg = dg.Config(N, N, N, degree=k, precision=prec, flags=flags)
-    ctx = dg.dg_init(cfg)
-    u0 = synthetic.turbulent_like(N, N, N, k, mach=mach, seed=args.seed)
-    u = torch.as_tensor(u0, device="cuda").to(ctx.dtype).contiguous()
-    del u0
-    assert dg.dg_limit(ctx, u) == 0
-    t_c = 1.0 / (2.0 * mach)           # eddy turnover time T = L/(2 cs Mach), t_c = T
-    dt_drive = t_c / 100.0
-    dg.dg_forcing_ou_init(ctx, t_c, sigma)
-    nd = dg.dg_forcing_ou_ndraws()
-    dg.dg_forcing_ou_advance(ctx, synthetic.gaussian_draws(args.seed, 0, nd), 1e30)   # stationary start
-    state = {"t": 0.0, "next": dt_drive, "n_drive": 1, "retries": 0, "dt_ms": 0.0, "dt0": None, "dtmin": 1e300}
-
-    def step():
-        t0 = time.perf_counter()
-        dt = dg.dg_dt_max(ctx, u)
-        state["dt_ms"] += 1e3 * (time.perf_counter() - t0)
-        if state["dt0"] is None:
-            state["dt0"] = dt
-        state["dtmin"] = min(state["dtmin"], dt)
-        if not (dt > 1e-3 * state["dt0"]):
-            raise RuntimeError(f"time step collapsed ({dt:.3e} vs {state['dt0']:.3e} at the start): "
-                               "the flow state is not physical")
-        while state["t"] + dt >= state["next"]:
-            dg.dg_forcing_ou_advance(ctx, synthetic.gaussian_draws(args.seed, state["n_drive"], nd), dt_drive)
-            state["n_drive"] += 1
-            state["next"] += dt_drive
-        while dg.dg_rk_step(ctx, u, dt) == dg.DG_RETRY:
-            state["retries"] += 1
-            dt *= 0.5
-        state["t"] += dt
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    state["dt_ms"] = 0.0
-    state["retries"] = 0
+    from paper_2401_06841_amd import dg
+    t_dt = 0.0
+    retries0 = sim.retries
     if measure_profile:
-        dg.dg_profile(ctx, True)
+        dg.dg_profile(sim.ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    dt_min = 1e300
+    for _ in range(steps):
+        dt = sim.step()
+        dt_min = min(dt_min, dt)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = dg.dg_profile_read(ctx) if measure_profile else None
-    dg.dg_profile(ctx, False)
+    prof = dg.dg_profile_read(sim.ctx) if measure_profile else None
+    dg.dg_profile(sim.ctx, False)
+    return wall, prof, sim.retries - retries0, dt_min
 
+
+def _summary(args, sim, precision, wall, prof, retries, dt_min):
+    from paper_2401_06841_amd import model
+    cfg = sim.cfg
+    k = cfg.degree
     dof = 4 * cfg.nb * cfg.ncell
-    value = 3.0 * dof * args.steps / wall
-    out = {"precision": precision, "value": value, "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
-           "dt_reduction_ms_per_step": state["dt_ms"] / args.steps, "retries": state["retries"],
-           "sim_time": state["t"], "drive_updates": state["n_drive"], "dt_first": state["dt0"],
-           "dt_min": state["dtmin"]}
-    # RMS Mach number of the cell means (diagnostic of the synthetic state)
-    rho = u[0, 0].double()
-    v2 = ((u[1:, 0].double() / rho) ** 2).sum(0)
-    out["rms_mach_cell_means"] = float(torch.sqrt(v2.mean()))
+    out = {"precision": precision, "value": 3.0 * dof * args.steps / wall, "wall_s": wall,
+           "ms_per_step": 1e3 * wall / args.steps, "retries": retries, "dt_min": dt_min,
+           "sim_time": sim.t, "rms_mach": sim.rms_mach()}
     if prof:
         rhs_ms, rhs_n, st_ms, st_n = prof
         avg = rhs_ms / max(rhs_n, 1)
@@ -146,22 +113,59 @@ def run_gpu(args, precision, measure_profile=True):
                            "frac": achieved / peak,
                            "traffic": traffic_from_profiles("k_rhs", args.workload, precision, 1)}
         out["algorithmic_flops_per_launch"] = flops
-    ctx.close()
     return out
 
 
-def run_cpu_baseline(args):
-    """The oracle as it stands, timed on the host cores on a bounded sample: 3 SSP-RK3
-    steps (9 stages) of the same workload from the same synthetic input."""
-    import numpy as np
+def run_gpu(args, precision, measure_profile=True):
+    """Spin up from rest (untimed warm-up), then time exactly args.steps steps; then time
+    the same state on the other precision when comparing."""
+    import torch
 
+    from paper_2401_06841_amd import dg
+    from paper_2401_06841_amd.driver import Driving, Simulation
+
+    N, k, _, mach, sigma, _ = WORKLOADS[args.workload]
+    flags = dg.DG_AV | dg.DG_PRIM_PROJ | dg.DG_POS_LIMITER | dg.DG_FORCING | dg.DG_FORCE_MEANFREE
+    prec = dg.DG_FP64 if precision == "fp64" else dg.DG_FP32
+    cfg = dg.Config(N, N, N, degree=k, precision=prec, flags=flags)
+    drv = Driving(mach, sigma, seed=args.seed)
+    sim = Simulation(cfg, driving=drv)
+    for i in range(args.warmup):
+        sim.step()
+        if args.verbose and (i + 1) % 1000 == 0:
+            print(f"warm-up step {i + 1}: t={sim.t:.4f} rms Mach {sim.rms_mach():.3f}", file=sys.stderr, flush=True)
+    wall, prof, retries, dt_min = _timed(sim, args.steps, measure_profile)
+    main = _summary(args, sim, precision, wall, prof, retries, dt_min)
+    compare = None
+    if not args.no_compare:
+        other = "fp32" if precision == "fp64" else "fp64"
+        try:
+            cfg2 = dataclasses.replace(cfg, precision=dg.DG_FP32 if other == "fp32" else dg.DG_FP64)
+            dtype = torch.float32 if other == "fp32" else torch.float64
+            sim2 = Simulation(cfg2, u=sim.u.to(dtype).contiguous(), driving=drv)
+            sim2.t = sim.t
+            for _ in range(min(args.warmup, 20)):
+                sim2.step()
+            w2, p2, r2, d2 = _timed(sim2, args.steps, measure_profile)
+            compare = {other: _summary(args, sim2, other, w2, p2, r2, d2)}
+            sim2.ctx.close()
+        except Exception as exc:  # report, do not hide the main measurement
+            compare = {other: {"error": str(exc)}}
+    sim.ctx.close()
+    return main, compare
+
+
+def run_cpu_baseline(args):
+    """The oracle as it stands, timed on the host cores on a bounded sample: a few SSP-RK3
+    steps of the same workload (same mesh, degree, flags and driving) from the seeded
+    synthetic turbulence-like state (the oracle's cost does not depend on the flow)."""
     import oracle
     import synthetic
 
-    N, k, _, mach, sigma = WORKLOADS[args.workload]
+    N, k, _, mach, sigma, _ = WORKLOADS[args.workload]
     flags = oracle.AV | oracle.PRIM_PROJ | oracle.POS_LIMITER | oracle.FORCING | oracle.FORCE_MEANFREE
     cfg = oracle.Cfg(N, N, N, k, flags=flags)
-    u = synthetic.turbulent_like(N, N, N, k, mach=mach, seed=args.seed)
+    u = synthetic.turbulent_like(N, N, N, k, mach=mach, seed=args.seed, high_amp=0.02, kmax_frac=0.125)
     modes = synthetic.forcing_table(args.seed, amp=sigma)
     nsteps = args.cpu_steps
     t0 = time.perf_counter()
@@ -193,7 +197,8 @@ def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=None)
+    p.add_argument("--verbose", action="store_true")
     p.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     p.add_argument("--precision", default=None, choices=["fp64", "fp32"])
     p.add_argument("--seed", type=int, default=1)
@@ -211,20 +216,11 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    N, k, default_prec, mach, sigma = WORKLOADS[args.workload]
+    N, k, default_prec, mach, sigma, default_warmup = WORKLOADS[args.workload]
+    if args.warmup is None:
+        args.warmup = default_warmup
     precision = args.precision or default_prec
-    main_run = run_gpu(args, precision)
-    compare = None
-    if not args.no_compare:
-        other = "fp32" if precision == "fp64" else "fp64"
-        try:
-            r = run_gpu(args, other)
-            compare = {other: {"value": r["value"], "ms_per_step": r["ms_per_step"],
-                               "roofline_frac": r.get("roofline", {}).get("frac"),
-                               "k_rhs_avg_ms": r.get("kernels", {}).get("k_rhs_avg_ms"),
-                               "retries": r["retries"]}}
-        except Exception as exc:  # report, do not hide the main measurement
-            compare = {other: {"error": str(exc)}}
+    main_run, compare = run_gpu(args, precision)
     cpu = None if args.no_cpu else run_cpu_baseline(args)
     rec = {
         "metric": METRIC,
@@ -247,9 +243,9 @@ def main():
         "roofline": main_run.get("roofline"),
         "cpu_baseline": cpu,
         "kernels": main_run.get("kernels"),
-        "dt_reduction_ms_per_step": main_run["dt_reduction_ms_per_step"],
         "retries": main_run["retries"],
-        "rms_mach_cell_means": main_run["rms_mach_cell_means"],
+        "rms_mach": main_run["rms_mach"],
+        "sim_time": main_run["sim_time"],
         "compare": compare,
         "source_hash": source_hash(),
     }
