@@ -109,10 +109,13 @@ int dg_set_forcing(dg_ctx *ctx, const double *modes_host, int nmodes);
  * volume flux quadrature with the viscous pressure at interior points, Rusanov fluxes at
  * the face points, surface lift, driving source.  u and dudt: [4][nb][ncell] device
  * arrays; dudt is fully overwritten.  dt is the step size used by the Pi_max cap
- * (Sec. 3.1); dt <= 0 disables the cap.  Errors: DG_EINVAL, DG_ENOMEM (no workspace). */
+ * (Sec. 3.1); dt <= 0 disables the cap.  With DG_LEARNED_SENSOR the per-cell viscosity
+ * stored by dg_sensor_infer / dg_sensor_set_nu is used (DG_ESTATE if none).
+ * Errors: DG_EINVAL, DG_ENOMEM (no workspace), DG_ESTATE. */
 int dg_rhs(dg_ctx *ctx, const void *u, void *dudt, double dt);
 
-/* One third-order SSP Runge-Kutta step in place (Shu-Osher form), positivity limiter
+/* One third-order SSP Runge-Kutta step in place (Shu-Osher form; with DG_LEARNED_SENSOR
+ * the network runs on every stage input, DG_ESTATE without parameters), positivity limiter
  * after every stage when DG_POS_LIMITER is set (Sec. 3.1: all high-order weights of a cell
  * scaled by one factor so that the density at every volume and face Gauss point is at
  * least max(rho_floor, rho_floor_rel * cell mean)).  Synchronises the stream once to read

@@ -164,6 +164,7 @@ static void layout(dg_ctx *c, size_t *total)
     c->off.fb = o; o += align_up(nc * 4);
     c->off.feat = o; o += learned ? align_up(nc * DG_MLP_NIN * 4) : 0;
     c->off.lab = o; o += learned ? align_up(nc * 8) : 0;
+    c->off.mlp = o; o += align_up((size_t)256 * (DG_MLP_NPARAM + 1) * 4);   // per-wave network gradients
     c->off.part = o; o += align_up((size_t)c->nblk * 4 * 8);
     c->off.scal = o; o += align_up(64 * 8);
     c->off.iflags = o; o += align_up(64 * 4);
@@ -273,6 +274,8 @@ int dg_set_workspace(dg_ctx *c, void *ws, size_t bytes)
         return dg_fail(c, DG_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, c->ws_need);
     c->ws = (char *)ws;
     c->forcing_dirty = c->nmodes > 0;
+    c->have_nu = false;
+    if (c->cfg.flags & DG_LEARNED_SENSOR) return sensor_reset_flags(c);
     return DG_OK;
 }
 
@@ -485,8 +488,6 @@ static int do_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
     return DG_OK;
 }
 
-int sensor_infer_impl(dg_ctx *c, const void *u);
-
 template <typename T, int K>
 static int do_step(dg_ctx *c, void *u, double dt, int *status_host)
 {
@@ -536,8 +537,8 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host)
 
 static int learned_ready(dg_ctx *c)
 {
-    if ((c->cfg.flags & DG_LEARNED_SENSOR) && !c->have_nu && !c->have_params)
-        return dg_fail(c, DG_ESTATE, "learned sensor enabled but neither parameters nor nu were set");
+    if ((c->cfg.flags & DG_LEARNED_SENSOR) && !c->have_nu)
+        return dg_fail(c, DG_ESTATE, "learned sensor enabled but no viscosity stored (dg_sensor_infer or dg_sensor_set_nu)");
     return DG_OK;
 }
 
@@ -547,10 +548,6 @@ int dg_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
     int rc;
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u")) || (rc = check_ptr(c, dudt, "dudt"))) return rc;
     if ((rc = learned_ready(c))) return rc;
-    if ((c->cfg.flags & DG_LEARNED_SENSOR) && !c->have_nu) {
-        rc = sensor_infer_impl(c, u);
-        if (rc) return rc;
-    }
     return DISPATCH(c, do_rhs, c, u, dudt, dt);
 }
 

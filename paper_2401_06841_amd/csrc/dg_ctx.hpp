@@ -8,7 +8,7 @@
 #include "dg.h"
 
 struct dg_offsets {
-    size_t un_copy, stA, stB, L, vh0, vh1, apts, nu, fb, feat, lab, part, scal, iflags;
+    size_t un_copy, stA, stB, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, scal, iflags;
 };
 
 struct dg_ctx {
@@ -50,3 +50,5 @@ struct dg_ctx {
 };
 
 int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...);
+int sensor_infer_impl(dg_ctx *c, const void *u);
+int sensor_reset_flags(dg_ctx *c);

@@ -763,7 +763,7 @@ __global__ void __launch_bounds__(BLOCK) k_sums(const void *u_, Mesh g, double *
 // mode 1: out[0..2] = sum part[.][0..2] / sum part[.][3]   (mass-weighted mean acceleration)
 // mode 2: out[0] = min(scale / max part[.][0], scale2 / max part[.][1])   (time step; the
 //         second term only when scale2 > 0 and the maximum is positive)
-__global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double scale2,
+static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double scale2,
                                                  double *out)
 {
     __shared__ double lds[16];
