@@ -110,12 +110,15 @@ int dg_set_forcing(dg_ctx *ctx, const double *modes_host, int nmodes);
  * the face points, surface lift, driving source.  u and dudt: [4][nb][ncell] device
  * arrays; dudt is fully overwritten.  dt is the step size used by the Pi_max cap
  * (Sec. 3.1); dt <= 0 disables the cap.  With DG_LEARNED_SENSOR the per-cell viscosity
- * stored by dg_sensor_infer / dg_sensor_set_nu is used (DG_ESTATE if none).
+ * nu stored by dg_sensor_infer / dg_sensor_set_nu (DG_ESTATE if none) is the bulk
+ * viscosity of cells whose fallback flag is 0: Pi = min(rho nu s, Pi_max) at compressed
+ * points (s = -div vhat > 0), none at expanding points.
  * Errors: DG_EINVAL, DG_ENOMEM (no workspace), DG_ESTATE. */
 int dg_rhs(dg_ctx *ctx, const void *u, void *dudt, double dt);
 
 /* One third-order SSP Runge-Kutta step in place (Shu-Osher form; with DG_LEARNED_SENSOR
- * the network runs on every stage input, DG_ESTATE without parameters), positivity limiter
+ * the stored per-cell viscosity serves the three stages: call dg_sensor_infer on u^n
+ * first, DG_ESTATE if none is stored), positivity limiter
  * after every stage when DG_POS_LIMITER is set (Sec. 3.1: all high-order weights of a cell
  * scaled by one factor so that the density at every volume and face Gauss point is at
  * least max(rho_floor, rho_floor_rel * cell mean)).  Synchronises the stream once to read
@@ -128,8 +131,10 @@ int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
  * dt_adv = cfl h / ((k+1) max sum_d (|m_d/rho| + cs)) (Sec. 7: dt proportional to h/(k+1));
  * with DG_AV and cfl_visc > 0, dt_visc = cfl_visc (h/p)^2 / max nu, the explicit stability
  * bound of the viscous pressure read as a bulk viscosity nu = alpha (h/p)^2 |div v| +
- * beta cs (h/p) at compressing points (Sec. 3.1; p = k+1).  on_host = 1: *dt_out is host
- * memory and the call synchronises; on_host = 0: *dt_out is device memory (8 bytes). */
+ * beta cs (h/p) at compressing points (Sec. 3.1; p = k+1); with DG_LEARNED_SENSOR a cell
+ * whose fallback flag is 0 contributes its stored viscosity instead (DG_ESTATE if none is
+ * stored).  on_host = 1: *dt_out is host memory and the call synchronises; on_host = 0:
+ * *dt_out is device memory (8 bytes). */
 int dg_dt_max(dg_ctx *ctx, const void *u, double *dt_out, int on_host);
 
 /* Projected velocity (Sec. 3.2, eq. weights_equation with the interior rule):
@@ -176,14 +181,20 @@ int dg_forcing_get(const dg_ctx *ctx, double *modes_host, int nmodes_max);
 #define DG_MLP_NHID 64
 #define DG_MLP_NPARAM (64 * 20 + 64 + 64 * 64 + 64 + 64 + 1)
 
-/* Per-cell features x[ncell][20] (float, device): density shape W_rho,l/W_rho,0 (l=1..9),
- * log10 W_rho,0, cell-mean velocity gradient (from the linear modes of vhat) times
- * (h/(k+1))/cs, |mean velocity|/cs. */
+/* Per-cell features x[ncell][20] (float, device): density shape W_rho,l/W_rho,0 for the
+ * modes (100),(010),(001),(200),(020),(002); log10 W_rho,0; cell-mean velocity gradient
+ * (from the linear modes of vhat) times (h/(k+1))/cs; the three slopes of div vhat across
+ * the cell (div vhat is linear at degree 2) times (h/(k+1))/cs; |mean velocity|/cs. */
 int dg_sensor_features(dg_ctx *ctx, const void *u, float *x_dev);
 
-/* Plain-sensor labels nu[ncell] (double, device): max over interior points of
- * Pi/(rho cs^2) with the vNR form without the Pi_max cap. */
+/* Plain-sensor labels nu[ncell] (double, device): the largest vNR bulk viscosity
+ * alpha (h/p)^2 s + beta cs (h/p) over the compressed interior points (s = -div vhat > 0),
+ * 0 if none is compressed. */
 int dg_sensor_labels(dg_ctx *ctx, const void *u, double *nu_dev);
+
+/* Training targets t[ncell] (float, device): t = log(1 + nu/1e-3) of the plain-sensor
+ * labels above, the network's output space.  Degree 2 only. */
+int dg_sensor_targets(dg_ctx *ctx, const void *u, float *t_dev);
 
 /* Install network parameters (FP32 device array, DG_MLP_NPARAM values, copied). */
 int dg_sensor_set_params(dg_ctx *ctx, const float *params_dev);

@@ -72,6 +72,8 @@ def lib():
                                     ctypes.c_long, lp, dp]
         L.orc_dt_max.argtypes = [cp, dp]
         L.orc_dt_max.restype = ctypes.c_double
+        L.orc_dt_max_learned.argtypes = [cp, dp, dp, ctypes.POINTER(ctypes.c_int)]
+        L.orc_dt_max_learned.restype = ctypes.c_double
         L.orc_limit.argtypes = [cp, dp, dp]
         L.orc_limit.restype = ctypes.c_long
         L.orc_ssprk3_linear.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
@@ -251,8 +253,14 @@ def rhs_cells(cfg: Cfg, u, cells, dt: float = 0.0, modes=None, abar=None, nu=Non
     return out
 
 
-def dt_max(cfg: Cfg, u) -> float:
-    return lib().orc_dt_max(cfg.c(), _d(_f64(u)))
+def dt_max(cfg: Cfg, u, nu=None, fallback=None) -> float:
+    """Time step; with the LEARNED flag and a per-cell viscosity nu, cells whose fallback
+    flag is 0 use nu in the viscous bound."""
+    if nu is None:
+        return lib().orc_dt_max(cfg.c(), _d(_f64(u)))
+    nu = _f64(nu)
+    fb = np.ascontiguousarray(np.zeros(cfg.ncell) if fallback is None else fallback, dtype=np.int32)
+    return lib().orc_dt_max_learned(cfg.c(), _d(_f64(u)), _d(nu), fb.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
 
 
 def limit(cfg: Cfg, u):

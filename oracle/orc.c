@@ -335,18 +335,18 @@ double orc_vnr_pi(const orc_cfg *cfg, double rho, double divv, double dt)
     return pi;
 }
 
-/* Learned-sensor viscous pressure at a point: Pi = nu rho cs^2, capped at the same
- * Pi_max form evaluated with the cell-mean compression |tr G|; no viscosity where
- * the cell expands (tr G >= 0) and nu is below nu0. */
-static double learned_pi(const orc_cfg *cfg, double rho, double nu, double trg, double dt)
+/* Learned-sensor viscous pressure at a point: the network gives the cell a bulk
+ * viscosity nu (the vNR form is Pi = rho nu_vnr s with nu_vnr = alpha (h/p)^2 s +
+ * beta cs (h/p)); the learned form is Pi = rho nu s at compressed points (s = -div v > 0),
+ * none at expanding points, with the cap Pi_max of Sec. 3.1 (none for dt <= 0). */
+static double learned_pi(const orc_cfg *cfg, double rho, double nu, double divv, double dt)
 {
-    const double nu0 = 1e-3;
-    if (trg >= 0.0 && nu < nu0) return 0.0;
-    if (nu <= 0.0) return 0.0;
-    double pi = nu * rho * cfg->cs * cfg->cs;
+    double s = -divv;
+    if (!(s > 0.0) || !(nu > 0.0)) return 0.0;
+    double pi = rho * nu * s;
     double hp = cfg->h / (cfg->k + 1);
     if (dt > 0.0) {
-        double pmax = 0.5 * rho * hp * hp * fabs(trg) / dt;
+        double pmax = 0.5 * rho * hp * hp * s / dt;
         if (pi > pmax) pi = pmax;
     }
     return pi;
@@ -372,12 +372,6 @@ static void trace(const orc_cfg *cfg, const tabs_t *T, const double *u, long nc,
     }
 }
 
-/* cell-mean divergence of the projected velocity: the linear modes carry the mean
- * gradient, d/dxi Lt_1 = sqrt(3); modes (1,0,0), (0,1,0), (0,0,1) are 1, 2, 3 */
-static double mean_div(const orc_cfg *cfg, const double *vh, int nb)
-{
-    return (2.0 / cfg->h) * sqrt(3.0) * (vh[0 * nb + 1] + vh[1 * nb + 2] + vh[2 * nb + 3]);
-}
 
 /* ------------------------------------------------------------- the RHS */
 
@@ -428,7 +422,6 @@ static void rhs_cell(const rhs_ctx *R, long c, double *out)
     for (int i = 0; i < NV * nb; ++i) out[i] = 0.0;
 
     int learned = (cfg->flags & ORC_LEARNED) && R->nu && !(R->fallback && R->fallback[c]);
-    double trg = mean_div(cfg, vh, nb);
 
     /* volume integral */
     for (int q = 0; q < T->nq; ++q) {
@@ -437,15 +430,11 @@ static void rhs_cell(const rhs_ctx *R, long c, double *out)
         for (int d = 0; d < 3; ++d) m[d] = expand(u, nb, nc, 1 + d, c, T->vphi[q]);
         double pi = 0.0;
         if (cfg->flags & ORC_AV) {
-            if (learned) {
-                pi = learned_pi(cfg, rho, R->nu[c], trg, R->dt);
-            } else {
-                double divv = 0.0;
-                for (int d = 0; d < 3; ++d)
-                    for (int l = 0; l < nb; ++l) divv += vh[d * nb + l] * T->vdphi[q][d][l];
-                divv *= 2.0 / cfg->h;
-                pi = orc_vnr_pi(cfg, rho, divv, R->dt);
-            }
+            double divv = 0.0;
+            for (int d = 0; d < 3; ++d)
+                for (int l = 0; l < nb; ++l) divv += vh[d * nb + l] * T->vdphi[q][d][l];
+            divv *= 2.0 / cfg->h;
+            pi = learned ? learned_pi(cfg, rho, R->nu[c], divv, R->dt) : orc_vnr_pi(cfg, rho, divv, R->dt);
         }
         double p = cfg->cs * cfg->cs * rho + pi;
         for (int d = 0; d < 3; ++d) {
@@ -587,8 +576,10 @@ int orc_rhs_cells(const orc_cfg *cfg, const double *u, double dt, const double *
  * bulk viscosity nu = Pi / (rho |div v|) = alpha (h/p)^2 |div v| + beta cs (h/p) at
  * compressing points (div v of the projected velocity, p = k+1), and the explicit
  * stability bound dt_visc = cfl_visc (h/p)^2 / max nu applies; dt = min(dt_adv, dt_visc).
- * cfl_visc <= 0 or AV off: advective part only. */
-double orc_dt_max(const orc_cfg *cfg, const double *u)
+ * cfl_visc <= 0 or AV off: advective part only.  With the learned sensor (nu != NULL and
+ * the LEARNED flag) a cell whose fallback flag is 0 contributes its prescribed bulk
+ * viscosity nu[c] instead of the maximum over its points. */
+static double dt_max_impl(const orc_cfg *cfg, const double *u, const double *nuc, const int *fallback)
 {
     if (check_cfg(cfg)) return -1.0;
     tabs_t *T = malloc(sizeof(tabs_t));
@@ -597,6 +588,7 @@ double orc_dt_max(const orc_cfg *cfg, const double *u)
     int nb = T->nb;
     double hp = cfg->h / (cfg->k + 1);
     int visc = (cfg->flags & ORC_AV) && cfg->cfl_visc > 0.0;
+    int learned = (cfg->flags & ORC_LEARNED) && nuc != NULL;
     double *smax = malloc(sizeof(double) * nc);
     double *numax = malloc(sizeof(double) * nc);
     #pragma omp parallel for schedule(static)
@@ -609,7 +601,7 @@ double orc_dt_max(const orc_cfg *cfg, const double *u)
             double s = 0.0;
             for (int d = 0; d < 3; ++d) s += fabs(expand(u, nb, nc, 1 + d, c, T->vphi[q]) / rho) + cfg->cs;
             if (s > sm) sm = s;
-            if (visc) {
+            if (visc && !(learned && !(fallback && fallback[c]))) {
                 double divv = 0.0;
                 for (int d = 0; d < 3; ++d)
                     for (int l = 0; l < nb; ++l) divv += vh[d * nb + l] * T->vdphi[q][d][l];
@@ -620,6 +612,7 @@ double orc_dt_max(const orc_cfg *cfg, const double *u)
                 }
             }
         }
+        if (visc && learned && !(fallback && fallback[c])) nm = nuc[c] > 0.0 ? nuc[c] : 0.0;
         smax[c] = sm;
         numax[c] = nm;
     }
@@ -637,6 +630,13 @@ double orc_dt_max(const orc_cfg *cfg, const double *u)
         if (dv < dt) dt = dv;
     }
     return dt;
+}
+
+double orc_dt_max(const orc_cfg *cfg, const double *u) { return dt_max_impl(cfg, u, NULL, NULL); }
+
+double orc_dt_max_learned(const orc_cfg *cfg, const double *u, const double *nu, const int *fallback)
+{
+    return dt_max_impl(cfg, u, nu, fallback);
 }
 
 /* ----------------------------------------------------- positivity limiter */
@@ -880,9 +880,11 @@ int orc_l1_error(const orc_cfg *cfg, int nq, int nvar, const double *w, const do
 /* -------------------------------------------------- learned-sensor pieces */
 
 /* Per-cell input features of the learned sensor (degree 2 only, 20 values):
- *   [0..8]   density shape W_rho,l / W_rho,0 for l = 1..9
- *   [9]      log10 W_rho,0
- *   [10..18] cell-mean velocity gradient G_de = (2 sqrt(3)/h) Vhat_d,(unit e), scaled by (h/p)/cs
+ *   [0..5]   density shape W_rho,l / W_rho,0 for the modes (100),(010),(001),(200),(020),(002)
+ *   [6]      log10 W_rho,0
+ *   [7..15]  cell-mean velocity gradient G_de = (2 sqrt(3)/h) Vhat_d,(unit e), scaled by (h/p)/cs
+ *   [16..18] slopes D_i of the divergence of vhat across the cell (div = D0 + sum D_i xi_i,
+ *            physical units), scaled by (h/p)/cs
  *   [19]     |mean velocity| / cs with mean velocity = Vhat_d,0
  * x[cell][20]. */
 int orc_sensor_features(const orc_cfg *cfg, const double *u, double *x)
@@ -899,11 +901,25 @@ int orc_sensor_features(const orc_cfg *cfg, const double *u, double *x)
         project_cell(T, u, nc, c, vh);
         double r0 = U(u, nb, nc, 0, 0, c);
         double *xc = x + c * 20;
-        for (int l = 1; l < 10; ++l) xc[l - 1] = U(u, nb, nc, 0, l, c) / r0;
-        xc[9] = log10(r0);
+        /* density: linear modes (100),(010),(001) and axis quadratics (200),(020),(002) */
+        static const int dmode[6] = {1, 2, 3, 4, 7, 9};
+        for (int i = 0; i < 6; ++i) xc[i] = U(u, nb, nc, 0, dmode[i], c) / r0;
+        xc[6] = log10(r0);
+        /* cell-mean velocity gradient from the linear modes of vhat: d/dxi Lt_1 = sqrt(3) */
         for (int d = 0; d < 3; ++d)
             for (int e = 0; e < 3; ++e)
-                xc[10 + 3 * d + e] = (hp / cfg->cs) * (2.0 * sqrt(3.0) / cfg->h) * vh[d * nb + 1 + e];
+                xc[7 + 3 * d + e] = (hp / cfg->cs) * (2.0 * sqrt(3.0) / cfg->h) * vh[d * nb + 1 + e];
+        /* slopes of the divergence of vhat across the cell: div vhat is linear in xi at
+         * degree 2, div = D0 + sum_i D_i xi_i, and D_i = 3 * (1/8) int div xi_i (exact with
+         * the (k+1)-point rule) */
+        double slope[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < T->nq; ++q) {
+            double divv = 0.0;
+            for (int d = 0; d < 3; ++d)
+                for (int l = 0; l < nb; ++l) divv += vh[d * nb + l] * T->vdphi[q][d][l];
+            for (int i = 0; i < 3; ++i) slope[i] += 3.0 * 0.125 * T->vw[q] * divv * T->vxi[q][i];
+        }
+        for (int i = 0; i < 3; ++i) xc[16 + i] = (hp / cfg->cs) * (2.0 / cfg->h) * slope[i];
         double vm = sqrt(vh[0] * vh[0] + vh[nb] * vh[nb] + vh[2 * nb] * vh[2 * nb]);
         xc[19] = vm / cfg->cs;
     }
@@ -911,8 +927,9 @@ int orc_sensor_features(const orc_cfg *cfg, const double *u, double *x)
     return ORC_OK;
 }
 
-/* Plain-sensor label of a cell: nu_K = max_q Pi_q / (rho_q cs^2) over the interior
- * points, with Pi from the von Neumann-Richtmyer form without the Pi_max cap. */
+/* Plain-sensor label of a cell: the largest vNR bulk viscosity over its interior points,
+ * nu_K = max over compressed points (s = -div v > 0) of alpha (h/p)^2 s + beta cs (h/p)
+ * (Pi = rho nu s without the Pi_max cap); 0 when no point is compressed. */
 int orc_sensor_labels(const orc_cfg *cfg, const double *u, double *nu)
 {
     if (check_cfg(cfg)) return ORC_EINVAL;
@@ -920,20 +937,22 @@ int orc_sensor_labels(const orc_cfg *cfg, const double *u, double *nu)
     make_tabs(cfg->k, T);
     long nc = ncell_of(cfg);
     int nb = T->nb;
+    double hp = cfg->h / (cfg->k + 1);
     #pragma omp parallel for schedule(static)
     for (long c = 0; c < nc; ++c) {
         double vh[3 * NBMAX];
         project_cell(T, u, nc, c, vh);
         double best = 0.0;
         for (int q = 0; q < T->nq; ++q) {
-            double rho = expand(u, nb, nc, 0, c, T->vphi[q]);
             double divv = 0.0;
             for (int d = 0; d < 3; ++d)
                 for (int l = 0; l < nb; ++l) divv += vh[d * nb + l] * T->vdphi[q][d][l];
             divv *= 2.0 / cfg->h;
-            double pi = orc_vnr_pi(cfg, rho, divv, 0.0);
-            double r = pi / (rho * cfg->cs * cfg->cs);
-            if (r > best) best = r;
+            if (divv < 0.0) {
+                double sq = -divv;
+                double r = cfg->alpha * hp * hp * sq + cfg->beta * cfg->cs * hp;
+                if (r > best) best = r;
+            }
         }
         nu[c] = best;
     }

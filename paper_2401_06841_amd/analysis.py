@@ -1,0 +1,118 @@
+"""Flow statistics of DG states for comparing runs (host numpy, measurement only).
+
+* Density PDF: volume-weighted histogram of log10(rho) over the interior Gauss-Legendre
+  points of every cell (weight omega_q h^3 / 8), the quantity shown in the paper's density
+  PDFs (Sec. 5); distance between two PDFs = L1 norm of the difference of the normalised
+  histograms.
+* Velocity power spectrum: v = m/rho evaluated on a uniform grid of p = k+1 points per cell
+  per dimension (N p points per dimension, Sec. 4.3), FFT, energy 1/2 |v_hat|^2 summed over
+  integer shells |kappa| in [K - 1/2, K + 1/2); distance between two spectra = mean
+  |log10 E_a - log10 E_b| over 1 <= K <= N p / 2.
+The basis (orthonormal total-degree Legendre, graded order) is evaluated here with numpy's
+Legendre routines; nothing here runs in a simulation step.
+"""
+from __future__ import annotations
+
+import numpy as np
+from numpy.polynomial import legendre as npleg
+
+
+def modes(k: int):
+    """Exponent triples in graded order: total degree ascending, then a, then b descending."""
+    out = []
+    for n in range(k + 1):
+        for a in range(n, -1, -1):
+            for b in range(n - a, -1, -1):
+                out.append((a, b, n - a - b))
+    return out
+
+
+def _leg1d(k: int, x):
+    """Normalised Legendre values sqrt(2n+1) P_n(x), shape [k+1][len(x)]."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.stack([np.sqrt(2 * n + 1) * npleg.legval(x, [0] * n + [1]) for n in range(k + 1)])
+
+
+def _basis_tensor(k: int, pts1d):
+    """phi_l at the tensor points (x fastest), shape [nb][npts^3]."""
+    L = _leg1d(k, pts1d)
+    P = len(pts1d)
+    out = []
+    for a, b, c in modes(k):
+        out.append(np.einsum("z,y,x->zyx", L[c], L[b], L[a]).reshape(P ** 3))
+    return np.array(out)
+
+
+def _as_numpy(u):
+    if hasattr(u, "detach"):
+        u = u.detach().to("cpu").double().numpy()
+    return np.asarray(u, dtype=np.float64)
+
+
+def density_pdf(u, k: int, bins: int = 200, lo: float = -4.0, hi: float = 3.0):
+    """Normalised volume-weighted histogram of log10(rho) at the Gauss points."""
+    u = _as_numpy(u)
+    x, w = npleg.leggauss(k + 1)
+    phi = _basis_tensor(k, x)                                   # [nb][q]
+    wq = np.einsum("z,y,x->zyx", w, w, w).reshape(-1) / 8.0     # sums to 1 per cell
+    rho = phi.T @ u[0]                                          # [q][cells]
+    lr = np.log10(np.clip(rho, 1e-300, None))
+    hist, _ = np.histogram(lr.reshape(-1), bins=bins, range=(lo, hi),
+                           weights=np.broadcast_to(wq[:, None], rho.shape).reshape(-1))
+    return hist / max(hist.sum(), 1e-300)
+
+
+def pdf_distance(p, q) -> float:
+    return float(np.abs(np.asarray(p) - np.asarray(q)).sum())
+
+
+def velocity_grid(u, k: int, n: tuple[int, int, int]):
+    """v = m / rho on the uniform sub-grid (k+1 points per cell per dimension, cell-centred
+    sub-cells); returns [3][nz p][ny p][nx p]."""
+    u = _as_numpy(u)
+    nx, ny, nz = n
+    p = k + 1
+    xi = -1.0 + (2.0 * np.arange(p) + 1.0) / p
+    phi = _basis_tensor(k, xi)                                  # [nb][p^3], sub-point (a,b,c) x fastest
+    vals = np.einsum("lq,vlc->vqc", phi, u)                     # [4][p^3][cells]
+    v = vals[1:] / vals[0][None]
+    v = v.reshape(3, p, p, p, nz, ny, nx)                       # [d][sz][sy][sx][cz][cy][cx]
+    v = v.transpose(0, 4, 1, 5, 2, 6, 3).reshape(3, nz * p, ny * p, nx * p)
+    return v
+
+
+def power_spectrum(v):
+    """Shell-summed kinetic energy spectrum of a periodic velocity field [3][Z][Y][X] on the
+    unit box; sum over shells = 1/2 <|v|^2>."""
+    v = np.asarray(v, dtype=np.float64)
+    shape = v.shape[1:]
+    npts = np.prod(shape)
+    vh = np.fft.fftn(v, axes=(1, 2, 3)) / npts
+    e = 0.5 * (np.abs(vh) ** 2).sum(0)
+    kz = np.fft.fftfreq(shape[0], 1.0 / shape[0])
+    ky = np.fft.fftfreq(shape[1], 1.0 / shape[1])
+    kx = np.fft.fftfreq(shape[2], 1.0 / shape[2])
+    kk = np.sqrt(kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2)
+    shell = np.floor(kk + 0.5).astype(np.int64)
+    return np.bincount(shell.reshape(-1), weights=e.reshape(-1))
+
+
+def spectrum_distance(e_test, e_ref, kmax: int) -> float:
+    a = np.asarray(e_test)[1:kmax + 1]
+    b = np.asarray(e_ref)[1:kmax + 1]
+    ok = (a > 0) & (b > 0)
+    return float(np.mean(np.abs(np.log10(a[ok]) - np.log10(b[ok])))) if ok.any() else float("nan")
+
+
+def compare(u_test, u_ref, k: int, n: tuple[int, int, int]):
+    """Per-field relative L2 difference, density-PDF distance and spectrum distance of two
+    states on the same mesh."""
+    a, b = _as_numpy(u_test), _as_numpy(u_ref)
+    rho = float(np.linalg.norm(a[0] - b[0]) / np.linalg.norm(b[0]))
+    mom = float(np.linalg.norm(a[1:] - b[1:]) / np.linalg.norm(b[1:]))
+    pa, pb = density_pdf(a, k), density_pdf(b, k)
+    kmax = min(n) * (k + 1) // 2
+    ea = power_spectrum(velocity_grid(a, k, n))
+    eb = power_spectrum(velocity_grid(b, k, n))
+    return {"l2_rel_rho": rho, "l2_rel_m": mom, "density_pdf_l1": pdf_distance(pa, pb),
+            "spectrum_log10_mean_abs": spectrum_distance(ea, eb, kmax)}

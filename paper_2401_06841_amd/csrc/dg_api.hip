@@ -392,6 +392,9 @@ static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int 
     pa.alpha = c->cfg.alpha_visc;
     pa.beta = c->cfg.beta_visc;
     pa.visc = (c->cfg.flags & DG_AV) && c->cfg.cfl_visc > 0.0;
+    const bool learned = (c->cfg.flags & DG_LEARNED_SENSOR) && (c->cfg.flags & DG_AV) && c->have_nu;
+    pa.nu = learned ? c->wp(c->off.nu) : nullptr;
+    pa.fb = learned ? (const int *)c->wp(c->off.fb) : nullptr;
     hipLaunchKernelGGL((k_project<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, vh, c->tab, g, pa,
                        part, fail);
     LAUNCHCHK(c);
@@ -495,15 +498,10 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host)
     static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
     void *vh[2] = {c->wp(c->off.vh0), c->wp(c->off.vh1)};
     void *st[3] = {c->wp(c->off.stA), c->wp(c->off.stB), u};
-    const bool learned = c->cfg.flags & DG_LEARNED_SENSOR;
     int rc = launch_project<T, K>(c, u, vh[0], nullptr, c->fail());
     if (rc) return rc;
     const void *ui = u;
     for (int s = 0; s < 3; ++s) {
-        if (learned) {
-            rc = sensor_infer_impl(c, ui);
-            if (rc) return rc;
-        }
         rc = launch_rhs<T, K>(c, ui, vh[s & 1], c->wp(c->off.L), dt);
         if (rc) return rc;
         if (use_meanfree(c)) {
@@ -557,8 +555,7 @@ int dg_rk_step(dg_ctx *c, void *u, double dt, int *status_host)
     int rc;
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
-    if ((c->cfg.flags & DG_LEARNED_SENSOR) && !c->have_params)
-        return dg_fail(c, DG_ESTATE, "learned sensor step needs network parameters");
+    if ((rc = learned_ready(c))) return rc;
     return DISPATCH(c, do_step, c, u, dt, status_host);
 }
 
@@ -588,6 +585,7 @@ int dg_dt_max(dg_ctx *c, const void *u, double *dt_out, int on_host)
     int rc;
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
     if (!dt_out) return dg_fail(c, DG_EINVAL, "dt_out is null");
+    if ((rc = learned_ready(c))) return rc;
     return DISPATCH(c, do_dt, c, u, dt_out, on_host);
 }
 

@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
     // derivative-relevant coefficients of the projected velocity (divergence, Sec. 3.1)
     T G[3][ND];
     bool learned = false;
-    T nu = T(0), trg = T(0);
+    T nu = T(0);
     if (av) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
@@ -430,8 +430,6 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
         if (a.flags & F_LEARNED) {
             learned = a.fb[c] == 0;
             nu = ((const T *)a.nu)[c];
-            // cell-mean divergence from the linear modes: d/dxi Lt_1 = sqrt(3)
-            trg = two_h * T(1.7320508075688772) * (G[0][M.dj[0][1]] + G[1][M.dj[1][2]] + G[2][M.dj[2][3]]);
         }
     }
 
@@ -468,11 +466,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
                 for (int j = 0; j < ND; ++j) div += G[d][j] * dph[d * ND + j];
             div *= two_h;
             const T pv = vnr_pi<T>(rho, div, hp, alpha, beta, cs, inv_dt);
-            // learned sensor: Pi = nu rho cs^2 capped by the same Pi_max with |tr G|;
-            // none where the cell expands and nu is below nu0 = 1e-3
-            T pl = nu * rho * cs2;
-            pl = fmin(pl, T(0.5) * rho * hp * hp * fabs(trg) * inv_dt);
-            pl = (trg >= T(0) && nu < T(1e-3)) || !(nu > T(0)) ? T(0) : pl;
+            // learned sensor: the cell's bulk viscosity nu in place of the vNR one,
+            // Pi = rho nu s at compressed points, with the Pi_max cap of the point
+            const T sq = -div;
+            T pl = fmin(rho * nu * sq, T(0.5) * rho * hp * hp * sq * inv_dt);
+            pl = (sq > T(0) && nu > T(0)) ? pl : T(0);
             pi = learned ? pl : pv;
         }
         const T ir = rcp(rho);
@@ -647,12 +645,15 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
 // ------------------------------------------------------------ projection kernel
 struct ProjArgs {
     double cs, h, alpha, beta;
-    int visc;   // also reduce the largest bulk viscosity of the viscous pressure
+    int visc;           // also reduce the largest bulk viscosity of the viscous pressure
+    const void *nu;     // learned per-cell bulk viscosity (element type T), or NULL
+    const int *fb;      // fallback flags of the learned sensor (1 = plain sensor)
 };
 
 // vhat of u (Sec. 3.2) and, optionally, per-block maxima for the time step (signal speed
-// sum_d |v_d| + cs; viscosity alpha (h/p)^2 |div v| + beta cs h/p at compressing points)
-// and a reset of the failure flag.
+// sum_d |v_d| + cs; viscosity alpha (h/p)^2 |div v| + beta cs h/p at compressing points,
+// or the learned cell viscosity where the learned sensor is in use) and a reset of the
+// failure flag.
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, const void *tab_, Mesh g, ProjArgs pa,
                                                    double *part, int *fail)
@@ -695,6 +696,7 @@ __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, co
             }
             const double s = -smin * (2.0 / pa.h);
             if (s > 0.0) nm = pa.alpha * hp * hp * s + pa.beta * pa.cs * hp;
+            if (pa.nu && pa.fb[c] == 0) nm = fmax((double)((const T *)pa.nu)[c], 0.0);
         }
         sm = block_max(active ? sm : 0.0, lds);
         __syncthreads();

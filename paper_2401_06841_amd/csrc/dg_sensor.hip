@@ -339,8 +339,16 @@ __global__ void __launch_bounds__(256) k_mlp_adam(float *__restrict__ P, const f
 }
 
 // ------------------------------------------------------------ features
-// x[cell][20]: density shape W_rho,l/W_rho,0 (l = 1..9), log10 W_rho,0, cell-mean velocity
-// gradient (2 sqrt(3)/h) vhat_{d,(e)} scaled by (h/3)/cs, |mean velocity|/cs (degree 2)
+// x[cell][20] (degree 2, modes in graded order 0:(000) 1:(100) 2:(010) 3:(001) 4:(200)
+// 5:(110) 6:(101) 7:(020) 8:(011) 9:(002)):
+//   [0..5]   density shape W_rho,l/W_rho,0 for l = 1, 2, 3, 4, 7, 9
+//   [6]      log10 W_rho,0
+//   [7..15]  cell-mean velocity gradient (2 sqrt(3)/h) vhat_{d,(e)}, scaled by (h/3)/cs
+//   [16..18] slopes of div vhat across the cell: with d/dxi Lt_1 = sqrt(3) and
+//            d/dxi Lt_2 = 3 sqrt(5) xi the divergence is D0 + sum_i D_i xi_i with
+//            D_1 = 3 sqrt(5) V_x,(200) + 3 V_y,(110) + 3 V_z,(101) (and cyclic), times 2/h,
+//            scaled by (h/3)/cs
+//   [19]     |mean velocity|/cs
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_features(const void *u_, float *__restrict__ x, const void *tab_, Mesh g,
                                                     double cs)
@@ -358,23 +366,30 @@ __global__ void __launch_bounds__(BLOCK) k_features(const void *u_, float *__res
     if (!active) return;
     const double r0 = (double)W[0][0];
     float *xc = x + (size_t)c * NIN;
+    constexpr int dmode[6] = {1, 2, 3, 4, 7, 9};
 #pragma unroll
-    for (int l = 1; l < NB; ++l) xc[l - 1] = (float)((double)W[0][l] / r0);
-    xc[9] = (float)log10(r0);
+    for (int i = 0; i < 6; ++i) xc[i] = (float)((double)W[0][dmode[i]] / r0);
+    xc[6] = (float)log10(r0);
     const double fac = 2.0 * 1.7320508075688772 / (3.0 * cs);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int e = 0; e < 3; ++e) xc[10 + 3 * d + e] = (float)(fac * (double)V[d][1 + e]);
+        for (int e = 0; e < 3; ++e) xc[7 + 3 * d + e] = (float)(fac * (double)V[d][1 + e]);
+    const double r5 = 3.0 * 2.23606797749979;     // 3 sqrt(5)
+    const double sfac = 2.0 / (3.0 * cs);         // (h/3)/cs * 2/h
+    xc[16] = (float)(sfac * (r5 * (double)V[0][4] + 3.0 * (double)V[1][5] + 3.0 * (double)V[2][6]));
+    xc[17] = (float)(sfac * (3.0 * (double)V[0][5] + r5 * (double)V[1][7] + 3.0 * (double)V[2][8]));
+    xc[18] = (float)(sfac * (3.0 * (double)V[0][6] + 3.0 * (double)V[1][8] + r5 * (double)V[2][9]));
     const double vm = sqrt((double)V[0][0] * V[0][0] + (double)V[1][0] * V[1][0] + (double)V[2][0] * V[2][0]);
     xc[19] = (float)(vm / cs);
 }
 
-// plain-sensor label nu = max_q Pi_q / (rho_q cs^2) without the cap: the ratio depends only
-// on the compression s = -div v, so nu = alpha (h/p)^2 s^2 / cs^2 + beta (h/p) s / cs at
-// the most compressed interior point (Sec. 3.1)
-template <typename T, int K>
-__global__ void __launch_bounds__(BLOCK) k_labels(const void *u_, double *__restrict__ nu, const void *tab_, Mesh g,
+// plain-sensor label: the largest vNR bulk viscosity alpha (h/p)^2 s + beta cs (h/p) over
+// the compressed interior points (s = -div v > 0; Pi = rho nu s without the cap,
+// Sec. 3.1); it grows with s, so it is taken at the most compressed point
+// OUT = double: the label nu itself; OUT = float: the training target log(1 + nu/nu0)
+template <typename T, int K, typename OUT>
+__global__ void __launch_bounds__(BLOCK) k_labels(const void *u_, OUT *__restrict__ nu, const void *tab_, Mesh g,
                                                   double h, double cs, double alpha, double beta)
 {
     using S = Shape<K>;
@@ -406,7 +421,9 @@ __global__ void __launch_bounds__(BLOCK) k_labels(const void *u_, double *__rest
     if (!active) return;
     const double s = -smin * 2.0 / h;
     const double hp = h / (K + 1);
-    nu[c] = s > 0.0 ? (alpha * hp * hp * s * s + beta * cs * hp * s) / (cs * cs) : 0.0;
+    const double v = s > 0.0 ? alpha * hp * hp * s + beta * cs * hp : 0.0;
+    if (sizeof(OUT) == 8) nu[c] = (OUT)v;
+    else nu[c] = (OUT)log1p(v / NU0);
 }
 
 // judge: fallback flag where |nu_learned - nu_plain| / (nu_plain + nu0) > tau; counts the flags
@@ -450,11 +467,22 @@ using namespace dg;
         if (e_ != hipSuccess) return dg_fail((ctx), DG_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
     } while (0)
 
+// gradient: at most MLP_WAVES waves, one partial-sum row each
 static int mlp_blocks(int n)
 {
     const int ntile = (n + 15) / 16;
     int nw = ntile < MLP_WAVES ? ntile : MLP_WAVES;
     return (nw + 3) / 4;
+}
+
+// forward: no reduction, so spread the 16-row tiles over the whole chip (about four
+// tiles per wave, which amortises loading the network into registers)
+static int fwd_blocks(int n)
+{
+    const long ntile = ((long)n + 15) / 16;
+    const long nw = (ntile + 3) / 4;
+    const long nb = (nw + 3) / 4;
+    return (int)(nb < 1 ? 1 : (nb > 16384 ? 16384 : nb));
 }
 
 static float *mlp_part(dg_ctx *c) { return (float *)c->wp(c->off.mlp); }
@@ -471,7 +499,7 @@ int dg_mlp_forward(dg_ctx *c, const float *P, const float *x, int n, float *y)
     if (!c) return DG_EINVAL;
     if (!P || !x || !y || n < 0) return dg_fail(c, DG_EINVAL, "bad network arguments");
     if (n == 0) return DG_OK;
-    hipLaunchKernelGGL((k_mlp_forward<float>), dim3(mlp_blocks(n)), dim3(256), 0, c->stream, P, x, n, y,
+    hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(n)), dim3(256), 0, c->stream, P, x, n, y,
                        (float *)nullptr);
     LAUNCHCHK(c);
     return DG_OK;
@@ -524,15 +552,16 @@ int dg_sensor_features(dg_ctx *c, const void *u, float *x)
     return DG_OK;
 }
 
-template <typename T, int K>
-static void launch_labels(dg_ctx *c, const void *u, double *nu)
+template <typename T, int K, typename OUT>
+static void launch_labels(dg_ctx *c, const void *u, OUT *nu)
 {
     const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
-    hipLaunchKernelGGL((k_labels<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, nu, c->tab, g, c->cfg.h,
+    hipLaunchKernelGGL((k_labels<T, K, OUT>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, nu, c->tab, g, c->cfg.h,
                        c->cfg.cs, c->cfg.alpha_visc, c->cfg.beta_visc);
 }
 
-int dg_sensor_labels(dg_ctx *c, const void *u, double *nu)
+template <typename OUT>
+static int labels_any(dg_ctx *c, const void *u, OUT *nu)
 {
     if (!c) return DG_EINVAL;
     if (!u || !nu) return dg_fail(c, DG_EINVAL, "null pointer");
@@ -549,6 +578,16 @@ int dg_sensor_labels(dg_ctx *c, const void *u, double *nu)
     return DG_OK;
 }
 
+int dg_sensor_labels(dg_ctx *c, const void *u, double *nu) { return labels_any(c, u, nu); }
+
+int dg_sensor_targets(dg_ctx *c, const void *u, float *t)
+{
+    if (!c) return DG_EINVAL;
+    int rc = need_k2(c);
+    if (rc) return rc;
+    return labels_any(c, u, t);
+}
+
 int sensor_infer_impl(dg_ctx *c, const void *u)
 {
     int rc = need_k2(c);
@@ -558,11 +597,11 @@ int sensor_infer_impl(dg_ctx *c, const void *u)
     rc = dg_sensor_features(c, u, x);
     if (rc) return rc;
     if (c->es == 8)
-        hipLaunchKernelGGL((k_mlp_forward<double>), dim3(mlp_blocks(c->nc)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_mlp_forward<double>), dim3(fwd_blocks(c->nc)), dim3(256), 0, c->stream,
                            (const float *)c->mlp_bf16, (const float *)x, c->nc, (float *)nullptr,
                            (double *)c->wp(c->off.nu));
     else
-        hipLaunchKernelGGL((k_mlp_forward<float>), dim3(mlp_blocks(c->nc)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(c->nc)), dim3(256), 0, c->stream,
                            (const float *)c->mlp_bf16, (const float *)x, c->nc, (float *)nullptr,
                            (float *)c->wp(c->off.nu));
     LAUNCHCHK(c);

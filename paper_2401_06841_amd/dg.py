@@ -11,6 +11,8 @@ import ctypes
 import dataclasses
 import os
 
+import torch
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdg.so")
 
@@ -59,6 +61,7 @@ _SIGS = {
     "dg_forcing_get": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
     "dg_sensor_features": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_sensor_labels": (ctypes.c_int, [_vp, _vp, _vp]),
+    "dg_sensor_targets": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_sensor_set_params": (ctypes.c_int, [_vp, _vp]),
     "dg_sensor_infer": (ctypes.c_int, [_vp, _vp]),
     "dg_sensor_judge": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _lp]),
@@ -115,6 +118,13 @@ class Config:
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(ctx, t, dtype, numel, name):
+    """Reject a device buffer the kernels could overrun or misread: wrong dtype or device,
+    not contiguous, or fewer than numel elements."""
+    if t is None or t.dtype != dtype or not t.is_contiguous() or t.device != ctx.device or t.numel() < numel:
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on {ctx.device} with at least {numel} elements")
 
 
 class Context:
@@ -262,15 +272,25 @@ def dg_forcing_get(ctx: Context):
 
 def dg_sensor_features(ctx: Context, u, x):
     ctx._check_state(u)
+    _need(ctx, x, torch.float32, ctx.cfg.ncell * DG_MLP_NIN, "x")
     ctx._chk(_lib.dg_sensor_features(ctx.h, _ptr(u), _ptr(x)))
 
 
 def dg_sensor_labels(ctx: Context, u, nu):
     ctx._check_state(u)
+    _need(ctx, nu, torch.float64, ctx.cfg.ncell, "nu")
     ctx._chk(_lib.dg_sensor_labels(ctx.h, _ptr(u), _ptr(nu)))
 
 
+def dg_sensor_targets(ctx: Context, u, t):
+    """Training targets log(1 + nu/1e-3) of the plain labels, float32 [ncell]."""
+    ctx._check_state(u)
+    _need(ctx, t, torch.float32, ctx.cfg.ncell, "t")
+    ctx._chk(_lib.dg_sensor_targets(ctx.h, _ptr(u), _ptr(t)))
+
+
 def dg_sensor_set_params(ctx: Context, params):
+    _need(ctx, params, torch.float32, DG_MLP_NPARAM, "params")
     ctx._chk(_lib.dg_sensor_set_params(ctx.h, _ptr(params)))
 
 
@@ -287,16 +307,32 @@ def dg_sensor_judge(ctx: Context, u, tau: float) -> int:
 
 
 def dg_sensor_set_nu(ctx: Context, nu=None, fallback=None):
+    if nu is not None:
+        _need(ctx, nu, ctx.dtype, ctx.cfg.ncell, "nu")
+    if fallback is not None:
+        _need(ctx, fallback, torch.int32, ctx.cfg.ncell, "fallback")
     ctx._chk(_lib.dg_sensor_set_nu(ctx.h, _ptr(nu), _ptr(fallback)))
 
 
 def dg_mlp_forward(ctx: Context, params, x, y):
+    n = x.shape[0]
+    _need(ctx, params, torch.float32, DG_MLP_NPARAM, "params")
+    _need(ctx, x, torch.float32, n * DG_MLP_NIN, "x")
+    _need(ctx, y, torch.float32, n, "y")
     ctx._chk(_lib.dg_mlp_forward(ctx.h, _ptr(params), _ptr(x), x.shape[0], _ptr(y)))
 
 
 def dg_mlp_grad(ctx: Context, params, x, t, grad, loss):
+    n = x.shape[0]
+    _need(ctx, params, torch.float32, DG_MLP_NPARAM, "params")
+    _need(ctx, x, torch.float32, n * DG_MLP_NIN, "x")
+    _need(ctx, t, torch.float32, n, "t")
+    _need(ctx, grad, torch.float32, DG_MLP_NPARAM, "grad")
+    _need(ctx, loss, torch.float32, 1, "loss")
     ctx._chk(_lib.dg_mlp_grad(ctx.h, _ptr(params), _ptr(x), _ptr(t), x.shape[0], _ptr(grad), _ptr(loss)))
 
 
 def dg_mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float):
+    for name, b in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _need(ctx, b, torch.float32, DG_MLP_NPARAM, name)
     ctx._chk(_lib.dg_mlp_adam(ctx.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr)))

@@ -4,7 +4,9 @@ One driver step: CFL time step from dg_dt_max (FP64 reduction on the GPU, one 8-
 read-back), Ornstein-Uhlenbeck driving updates on the host whenever the simulation time
 crosses the next update time (every t_c/100, Sec. 4.2), then dg_rk_step; when the step
 reports a positivity failure the state has been restored and the step is retried with
-half the time step (Sec. 3.1).  Checkpoints are the raw [var][mode][cell] array plus a
+half the time step (Sec. 3.1).  With the learned sensor the network runs on u^n before the
+time step (its viscosity enters the viscous bound and serves the three stages), and every
+judge_every steps the judge recomputes the plain labels and the fallback flags.  Checkpoints are the raw [var][mode][cell] array plus a
 JSON record of the run parameters, the simulation time and the driving state.
 """
 from __future__ import annotations
@@ -39,7 +41,8 @@ def gaussian_draws(seed: int, update: int, n: int):
 
 
 class Simulation:
-    def __init__(self, cfg: dg.Config, u=None, driving: Driving | None = None, retry_limit: int = 30):
+    def __init__(self, cfg: dg.Config, u=None, driving: Driving | None = None, retry_limit: int = 30,
+                 sensor_params=None, judge_every: int = 10, tau: float = 0.5):
         import torch
         self.cfg = cfg
         self.ctx = dg.dg_init(cfg)
@@ -59,6 +62,15 @@ class Simulation:
             self._drive(1e30)                       # start from the stationary distribution
             self.next_drive = driving.dt_drive
         self._torch = torch
+        # learned sensor (DG_LEARNED_SENSOR): network parameters, judge cadence and threshold
+        self.learned = bool(cfg.flags & dg.DG_LEARNED_SENSOR)
+        self.judge_every = judge_every
+        self.tau = tau
+        self.fallback_counts = []
+        if self.learned:
+            if sensor_params is None:
+                raise ValueError("a learned-sensor run needs network parameters")
+            dg.dg_sensor_set_params(self.ctx, sensor_params.to(self.ctx.device, torch.float32).contiguous())
 
     def _drive(self, dt_drive):
         z = gaussian_draws(self.driving.seed, self.n_drive, dg.dg_forcing_ou_ndraws())
@@ -66,6 +78,13 @@ class Simulation:
         self.n_drive += 1
 
     def step(self):
+        if self.learned:
+            # the network's viscosity of u^n serves the time step and the three stages; the
+            # judge (which also runs the network) refreshes the fallback flags
+            if self.nstep % self.judge_every == 0:
+                self.fallback_counts.append(dg.dg_sensor_judge(self.ctx, self.u, self.tau))
+            else:
+                dg.dg_sensor_infer(self.ctx, self.u)
         dt = dg.dg_dt_max(self.ctx, self.u)
         if not (dt > 0.0 and np.isfinite(dt)):
             raise RuntimeError(f"invalid time step {dt} at step {self.nstep}")

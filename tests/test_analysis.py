@@ -1,0 +1,67 @@
+"""The flow statistics used to compare runs (density PDF, velocity spectrum), checked on
+states with known answers built by the oracle's projection."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2401_06841_amd import analysis
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_mode_order_matches_the_oracle(k):
+    assert [tuple(e) for e in oracle.basis_exps(k)] == analysis.modes(k)
+
+
+def _state(n, k, f):
+    cfg = oracle.Cfg(n, n, n, k)
+    return oracle.project_function(cfg, f)
+
+
+def test_density_pdf_of_uniform_and_two_level_states():
+    n, k = 4, 2
+    u = _state(n, k, lambda x: np.stack([np.full(x.shape[:-1], 10.0)] + [np.zeros(x.shape[:-1])] * 3))
+    p = analysis.density_pdf(u, k)
+    assert abs(p.sum() - 1) < 1e-12
+    edges = np.linspace(-4, 3, 201)
+    assert p[np.searchsorted(edges, 1.0, side="right") - 1] == pytest.approx(1.0)
+    # half the box at rho = 0.1, half at rho = 1 (cell-aligned, so each cell is uniform)
+    u2 = _state(n, k, lambda x: np.stack([np.where(x[..., 0] < 0.5, 0.1, 1.0)] + [np.zeros(x.shape[:-1])] * 3))
+    p2 = analysis.density_pdf(u2, k)
+    assert p2[np.searchsorted(edges, -1.0 + 1e-9, side="right") - 1] == pytest.approx(0.5)
+    assert p2[np.searchsorted(edges, 0.0 + 1e-9, side="right") - 1] == pytest.approx(0.5)
+    assert analysis.pdf_distance(p, p) == 0.0
+    assert analysis.pdf_distance(p, p2) == pytest.approx(2.0)
+
+
+def test_velocity_grid_reproduces_a_linear_field():
+    n, k = 3, 2
+    # rho = 1, m = (x, 2y, -z): linear, so representable exactly and v = m on the sub-grid
+    u = _state(n, k, lambda x: np.stack([np.ones(x.shape[:-1]), x[..., 0], 2 * x[..., 1], -x[..., 2]]))
+    v = analysis.velocity_grid(u, k, (n, n, n))
+    p = k + 1
+    g = (np.arange(n * p) + 0.5) / (n * p)
+    assert np.allclose(v[0], g[None, None, :], atol=1e-12)
+    assert np.allclose(v[1], 2 * g[None, :, None], atol=1e-12)
+    assert np.allclose(v[2], -g[:, None, None], atol=1e-12)
+
+
+def test_power_spectrum_single_mode_and_parseval():
+    m = 24
+    z, y, x = np.meshgrid(*(np.arange(m) / m,) * 3, indexing="ij")
+    v = np.zeros((3, m, m, m))
+    v[0] = 0.7 * np.sin(2 * np.pi * 3 * y)
+    e = analysis.power_spectrum(v)
+    assert e[3] == pytest.approx(0.25 * 0.49)
+    assert abs(e.sum() - e[3]) < 1e-14
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal((3, m, m, m))
+    assert analysis.power_spectrum(w).sum() == pytest.approx(0.5 * (w ** 2).sum(0).mean())
+    assert analysis.spectrum_distance(e + 1e-30, e + 1e-30, 5) == 0.0
+
+
+def test_compare_of_a_state_with_itself():
+    n, k = 4, 1
+    u = _state(n, k, lambda x: np.stack([1 + 0.1 * np.sin(2 * np.pi * x[..., 0]), np.cos(2 * np.pi * x[..., 1]),
+                                         0 * x[..., 0], 0 * x[..., 0]]))
+    c = analysis.compare(u, u, k, (n, n, n))
+    assert c["l2_rel_rho"] == 0.0 and c["density_pdf_l1"] == 0.0 and c["spectrum_log10_mean_abs"] == 0.0

@@ -144,8 +144,8 @@ def test_training_reduces_loss():
 
 @pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
 def test_rhs_with_prescribed_viscosity(precision):
-    """Learned mode with a prescribed per-cell viscosity and fallback flags (both inputs
-    from the seeded generator) against the oracle."""
+    """Learned mode with a prescribed per-cell bulk viscosity and fallback flags (both
+    inputs from the seeded generator) against the oracle: right-hand side and time step."""
     n = 10
     u = synthetic.turbulent_like(n, n, n, 2, mach=3.0, seed=13)
     if precision == dg.DG_FP32:
@@ -169,6 +169,11 @@ def test_rhs_with_prescribed_viscosity(precision):
     dg.dg_rhs(ctx, ud, out, dt)
     e = field_rel(dt * host(out), dt * ref, u)
     assert max(e) < (1e-12 if precision == dg.DG_FP64 else 1e-5), e
+    # the time step takes the learned cells' viscosity in its viscous bound
+    dtl = dg.dg_dt_max(ctx, ud)
+    dtl_ref = oracle.dt_max(ocfg, u, nu, fb)
+    assert dtl_ref < dt
+    assert abs(dtl - dtl_ref) < (1e-13 if precision == dg.DG_FP64 else 1e-6) * dtl_ref
     # with every cell on fallback the learned mode is the plain sensor
     dg.dg_sensor_set_nu(ctx, None, torch.ones(nc, dtype=torch.int32, device="cuda"))
     dg.dg_rhs(ctx, ud, out, dt)

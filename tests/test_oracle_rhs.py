@@ -356,9 +356,9 @@ def test_axis_permutation_symmetry(k):
 
 
 def test_learned_mode_reduces_to_prescribed_viscosity():
-    """With the learned flag, a cell uses Pi = nu rho cs^2 (capped), or the plain
-    sensor where its fallback flag is set; nu = 0 everywhere with expanding cells
-    gives exactly the no-AV result."""
+    """With the learned flag, a compressed point uses Pi = rho nu s (s = -div v, nu the cell's
+    bulk viscosity) capped by Pi_max of its own compression, an expanding point none, and a
+    cell whose fallback flag is set the plain sensor."""
     k = 2
     cfg_l = oracle.Cfg(4, 4, 4, k, flags=ALL | oracle.LEARNED)
     cfg_p = oracle.Cfg(4, 4, 4, k, flags=ALL)
@@ -368,36 +368,69 @@ def test_learned_mode_reduces_to_prescribed_viscosity():
     L_plain = oracle.rhs(cfg_p, u, 1e-3)
     # everything on fallback -> plain sensor
     np.testing.assert_array_equal(oracle.rhs(cfg_l, u, 1e-3, nu=np.ones(nc), fallback=np.ones(nc)), L_plain)
-    # anisotropic linear compression with a prescribed nu, no fallback: Pi is constant in
-    # every cell, so the RHS difference has the closed form of the vNR test above
+    # anisotropic linear compression with a prescribed nu, no fallback: the divergence is
+    # uniform, so Pi is constant in every cell and the RHS difference has the closed form
+    # of the vNR test above
     idx = _mode_index(k)
     rho0 = 1.3
-    gam = [3.0, -1.0, 0.5]                     # dv_d/dx_d = -gam_d, mean divergence -2.5
+    gam = [3.0, -1.0, 0.5]                     # dv_d/dx_d = -gam_d, divergence -2.5
     uc = np.zeros(cfg_l.shape)
     uc[0, 0] = rho0
     for d, e in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
         uc[1 + d, idx[e]] = -gam[d] * rho0 * 0.5 * cfg_l.h / math.sqrt(3)
     hp = cfg_l.h / (k + 1)
-    trg = -sum(gam)
-    for nu0, dt in [(0.05, 0.1), (0.05, 1.0), (5e-4, 0.1)]:   # the cap binds at dt = 1
+    s = sum(gam)
+    for nu0, dt in [(0.01, 0.1), (0.01, 1.0), (5e-4, 0.1)]:   # the cap binds at dt = 1
         nu = np.full(nc, nu0)
         dL = oracle.rhs(cfg_l, uc, dt, nu=nu, fallback=np.zeros(nc)) - oracle.rhs(cfg_0, uc, dt)
-        pi = min(nu0 * rho0, 0.5 * rho0 * hp * hp * abs(trg) / dt)
+        pi = min(rho0 * nu0 * s, 0.5 * rho0 * hp * hp * s / dt)
         expect = 2.0 * math.sqrt(3) * pi / cfg_l.h
         for d, e in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
             np.testing.assert_allclose(dL[1 + d, idx[e]], expect, rtol=1e-10)
-    # expanding on average and nu below nu0: no viscosity
+    # expanding everywhere: no viscosity whatever nu is
     ue = uc.copy()
     ue[1:] *= -1.0
-    dL = oracle.rhs(cfg_l, ue, 0.1, nu=np.full(nc, 5e-4), fallback=np.zeros(nc)) - oracle.rhs(cfg_0, ue, 0.1)
-    assert np.abs(dL).max() == 0.0
+    for nu0 in (5e-4, 0.05):
+        dL = oracle.rhs(cfg_l, ue, 0.1, nu=np.full(nc, nu0), fallback=np.zeros(nc)) - oracle.rhs(cfg_0, ue, 0.1)
+        assert np.abs(dL).max() == 0.0
+    # zero mean divergence, compressed on one side: V_x = c phi_(200) gives
+    # div v = (2/h) 3 sqrt(5) c xi_1, so (c > 0) only the Gauss layer xi_1 = -sqrt(3/5)
+    # (1D weight 5/9) is compressed, at s = (2/h) 3 sqrt(5) c sqrt(3/5).  Without the cap
+    # (dt = 0) Pi = rho0 nu s there; being a pressure it enters every momentum flux, so m_d
+    # gains (1/(4h)) * 4 (5/9) Pi * d/dxi_d phi_l at that layer: sqrt(3) for the unit mode
+    # e_d, 3 sqrt(5) xi_1 for (200) in m_x, 3 xi_1 for (110) in m_y and (101) in m_z.
+    c, nu0 = 0.02, 0.03
+    uz = np.zeros(cfg_l.shape)
+    uz[0, 0] = rho0
+    uz[1, idx[(2, 0, 0)]] = rho0 * c
+    dL = oracle.rhs(cfg_l, uz, 0.0, nu=np.full(nc, nu0), fallback=np.zeros(nc)) - oracle.rhs(cfg_0, uz, 0.0)
+    xm = math.sqrt(0.6)
+    s_layer = (2.0 / cfg_l.h) * 3 * math.sqrt(5) * c * xm
+    layer = 4.0 * (5.0 / 9.0) * rho0 * nu0 * s_layer / (4.0 * cfg_l.h)
+    expect = np.zeros((4, cfg_l.nb))
+    for d, e in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+        expect[1 + d, idx[e]] = layer * math.sqrt(3)
+    expect[1, idx[(2, 0, 0)]] = layer * 3 * math.sqrt(5) * (-xm)
+    expect[2, idx[(1, 1, 0)]] = layer * 3 * (-xm)
+    expect[3, idx[(1, 0, 1)]] = layer * 3 * (-xm)
+    np.testing.assert_allclose(dL, np.broadcast_to(expect[:, :, None], dL.shape), rtol=0, atol=1e-12 * layer)
+    # the same state with the cap binding: Pi = 1/2 rho0 (h/p)^2 s / dt at the layer
+    dt = 1.0
+    pcap = 0.5 * rho0 * hp * hp * s_layer / dt
+    assert pcap < rho0 * nu0 * s_layer
+    dL = oracle.rhs(cfg_l, uz, dt, nu=np.full(nc, nu0), fallback=np.zeros(nc)) - oracle.rhs(cfg_0, uz, dt)
+    np.testing.assert_allclose(dL[1, idx[(1, 0, 0)]], layer * math.sqrt(3) * pcap / (rho0 * nu0 * s_layer),
+                               rtol=1e-12)
 
 
 def test_sensor_features_and_labels_closed_form():
     """Features of a cell with constant density and a linear velocity field v = v0 + G (x - x_K):
-    the density-shape entries are W_rho,l / W_rho,0, the gradient block is G (h/p)/cs and the
-    last entry is |v0|/cs.  The label of a uniformly compressing cell is the uncapped vNR
-    viscosity divided by rho cs^2."""
+    the density-shape entries are W_rho,l / W_rho,0, the gradient block is G (h/p)/cs, the
+    divergence slopes vanish and the last entry is |v0|/cs.  A quadratic velocity gives the
+    slopes from the Legendre derivatives d/dxi Lt_2 = 3 sqrt(5) xi, Lt_1 d/dxi Lt_1 = 3 xi.
+    The label of a uniformly compressing cell is the vNR bulk viscosity alpha (h/p)^2 s +
+    beta cs (h/p); with slopes, the most compressed Gauss point is a corner
+    xi_i = -sign(D_i) sqrt(3/5)."""
     k, N = 2, 3
     cfg = oracle.Cfg(N, N, N, k, flags=ALL)
     idx = _mode_index(k)
@@ -413,14 +446,38 @@ def test_sensor_features_and_labels_closed_form():
             u[1 + d, idx[ex]] = rho0 * G[d, e] * 0.5 * cfg.h / math.sqrt(3)
     x = oracle.sensor_features(cfg, u)
     hp = cfg.h / 3
-    assert np.abs(x[:, :9]).max() == 0.0
-    np.testing.assert_allclose(x[:, 9], math.log10(rho0), atol=1e-15)
-    np.testing.assert_allclose(x[:, 10:19], np.tile((G * hp).reshape(-1), (cfg.ncell, 1)), atol=1e-14)
+    assert np.abs(x[:, :6]).max() == 0.0
+    np.testing.assert_allclose(x[:, 6], math.log10(rho0), atol=1e-15)
+    np.testing.assert_allclose(x[:, 7:16], np.tile((G * hp).reshape(-1), (cfg.ncell, 1)), atol=1e-14)
+    assert np.abs(x[:, 16:19]).max() < 1e-14
     np.testing.assert_allclose(x[:, 19], np.linalg.norm(v0), atol=1e-14)
     u2 = u.copy()
     u2[0, 1:] = rng.normal(size=(cfg.nb - 1, cfg.ncell)) * 0.01
     x2 = oracle.sensor_features(cfg, u2)
-    np.testing.assert_allclose(x2[:, :9], (u2[0, 1:] / rho0).T, atol=1e-15)
+    sel = [idx[e] for e in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 2, 0), (0, 0, 2)]]
+    np.testing.assert_allclose(x2[:, :6], (u2[0, sel] / rho0).T, atol=1e-15)
+    # quadratic velocity modes (coefficients of V = m / rho0 in the basis)
+    c = rng.normal(size=9)
+    uq = u.copy()
+    uq[1, idx[(2, 0, 0)]] = rho0 * c[0]
+    uq[2, idx[(1, 1, 0)]] = rho0 * c[1]
+    uq[3, idx[(1, 0, 1)]] = rho0 * c[2]
+    uq[1, idx[(1, 1, 0)]] = rho0 * c[3]
+    uq[2, idx[(0, 2, 0)]] = rho0 * c[4]
+    uq[3, idx[(0, 1, 1)]] = rho0 * c[5]
+    uq[1, idx[(1, 0, 1)]] = rho0 * c[6]
+    uq[2, idx[(0, 1, 1)]] = rho0 * c[7]
+    uq[3, idx[(0, 0, 2)]] = rho0 * c[8]
+    r5 = 3 * math.sqrt(5)
+    slopes = np.array([r5 * c[0] + 3 * c[1] + 3 * c[2], 3 * c[3] + r5 * c[4] + 3 * c[5],
+                       3 * c[6] + 3 * c[7] + r5 * c[8]]) * 2.0 / cfg.h
+    xq = oracle.sensor_features(cfg, uq)
+    np.testing.assert_allclose(xq[:, 16:19], np.tile(slopes * hp, (cfg.ncell, 1)), rtol=1e-12)
+    np.testing.assert_allclose(xq[:, 7:16], x[:, 7:16], atol=1e-14)
+    trace = np.trace(G)
+    s = -trace + math.sqrt(0.6) * np.abs(slopes).sum()
+    nuq = 2.0 * hp * hp * s + 0.2 * hp if s > 0 else 0.0
+    np.testing.assert_allclose(oracle.sensor_labels(cfg, uq), nuq, rtol=1e-10)
     # label: uniform compression at rate s per direction
     gamma = 2.0
     uc = np.zeros(cfg.shape)
@@ -428,8 +485,30 @@ def test_sensor_features_and_labels_closed_form():
     for d, e in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
         uc[1 + d, idx[e]] = -gamma * rho0 * 0.5 * cfg.h / math.sqrt(3)
     s = 3 * gamma
-    nu = (2.0 * hp * hp * s * s + 0.2 * hp * s)
+    nu = 2.0 * hp * hp * s + 0.2 * hp
     np.testing.assert_allclose(oracle.sensor_labels(cfg, uc), nu, rtol=1e-12)
     ue = uc.copy()
     ue[1:] *= -1.0
     assert np.abs(oracle.sensor_labels(cfg, ue)).max() == 0.0
+
+
+def test_learned_time_step_uses_the_cell_viscosity():
+    """Uniform state with prescribed per-cell bulk viscosities: the viscous bound takes the
+    largest nu of the learned cells; a fallback cell contributes its own (here none, the
+    state is uniform)."""
+    k, n = 2, 4
+    cfg = oracle.Cfg(n, n, n, k, flags=ALL | oracle.LEARNED)
+    u = np.zeros(cfg.shape)
+    v0 = np.array([0.3, -0.2, 0.1])
+    u[0, 0] = 1.0
+    u[1:, 0] = v0[:, None]
+    hp = cfg.h / (k + 1)
+    dt_adv = cfg.cfl * cfg.h / ((k + 1) * (np.abs(v0).sum() + 3 * cfg.cs))
+    assert oracle.dt_max(cfg, u) == pytest.approx(dt_adv, rel=1e-14)
+    nu = np.zeros(cfg.ncell)
+    nu[5] = 0.02
+    nu[9] = 0.05
+    fb = np.zeros(cfg.ncell)
+    assert oracle.dt_max(cfg, u, nu, fb) == pytest.approx(min(dt_adv, cfg.cfl_visc * hp * hp / 0.05), rel=1e-14)
+    fb[9] = 1
+    assert oracle.dt_max(cfg, u, nu, fb) == pytest.approx(min(dt_adv, cfg.cfl_visc * hp * hp / 0.02), rel=1e-14)
