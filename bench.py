@@ -13,12 +13,19 @@ Default workload (c2): 64^3 cells, degree 2 (10 modes per variable, 27 Gauss poi
 FP64, artificial viscosity + primitive projection + positivity limiter, mean-free
 solenoidal OU driving on 1 <= |n| <= 2 aimed at RMS Mach ~3 (t_c = T = 1/(2 Mach)),
 starting from density 1 at rest.  The untimed warm-up steps spin the turbulence up
-(the default 4000 warm-up steps reach t ~ 0.38, a little over two eddy turnover times);
-then exactly K steps are timed with the state resident in HBM.  The same spun-up state,
-rounded to FP32, is then timed on the FP32 path for comparison.
+(the default 4000 warm-up steps reach t ~ 0.45, about 2.7 eddy turnover times); then
+exactly K steps are timed with the state resident in HBM.
+
+Comparison legs, from the same spun-up state and driving, timed the same way:
+  * the other precision with the plain sensor (FP32 bulk mode for the default workload);
+  * FP32 with the learned sensor (degree 2), whose network is trained by the library's
+    kernels on sensor snapshots taken during the last part of the warm-up.
+Each leg reports its throughput, its k_rhs roofline and the difference of its final state
+from the main run's: per-field relative L2, density-PDF L1 distance and velocity-spectrum
+log distance (the FP32 legs' statistics error against the FP64 path).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5]
-                       [--precision fp64|fp32] [--no-compare] [--no-cpu]
+                       [--precision fp64|fp32] [--no-compare] [--no-learned] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -119,12 +126,30 @@ def _summary(args, sim, precision, wall, prof, retries, dt_min):
     return out
 
 
+def _train_sensor(args, sim, ds):
+    """Fit the learned sensor on the snapshots taken during the warm-up (library kernels)."""
+    from paper_2401_06841_amd import sensor
+    x, t = ds.rows
+    tr = sensor.Trainer(sim.ctx, sensor.init_params(args.seed))
+    t0 = time.perf_counter()
+    losses = tr.fit(x, t, args.train_steps, lr=3e-3, lr_final=3e-4, batch=sim.cfg.ncell, seed=args.seed,
+                    log_every=max(args.train_steps // 4, 1))
+    full = tr.loss(x, t)
+    info = {"rows": int(ds.n), "snapshots": int(ds.n // sim.cfg.ncell), "adam_steps": args.train_steps,
+            "minibatch_rows": sim.cfg.ncell, "loss_first": losses[0], "loss_last_batch": losses[-1],
+            "loss_all_rows": full, "train_s": time.perf_counter() - t0}
+    return tr.P.detach().cpu(), info
+
+
 def run_gpu(args, precision, measure_profile=True):
-    """Spin up from rest (untimed warm-up), then time exactly args.steps steps; then time
-    the same state on the other precision when comparing."""
+    """Spin up from rest (untimed warm-up, taking sensor snapshots near its end), then time
+    exactly args.steps steps.  The comparison legs (the other precision with the plain
+    sensor, and FP32 with the learned sensor trained on the warm-up snapshots) start from
+    the same state with the same driving, are timed the same way, and their final states
+    are compared with the main run's (per-field L2, density PDF, velocity spectrum)."""
     import torch
 
-    from paper_2401_06841_amd import dg
+    from paper_2401_06841_amd import analysis, dg, sensor
     from paper_2401_06841_amd.driver import Driving, Simulation
 
     N, k, _, mach, sigma, _ = WORKLOADS[args.workload]
@@ -133,27 +158,51 @@ def run_gpu(args, precision, measure_profile=True):
     cfg = dg.Config(N, N, N, degree=k, precision=prec, flags=flags)
     drv = Driving(mach, sigma, seed=args.seed)
     sim = Simulation(cfg, driving=drv)
+    learned = (not args.no_compare) and (not args.no_learned) and k == 2
+    nsnap = min(args.snapshots, args.warmup // args.snapshot_every) if learned else 0
+    ds = sensor.Dataset(nsnap * cfg.ncell) if nsnap else None
+    first = args.warmup - nsnap * args.snapshot_every
     for i in range(args.warmup):
         sim.step()
+        if ds is not None and i + 1 > first and (i + 1 - first) % args.snapshot_every == 0:
+            ds.add(sim.ctx, sim.u)
         if args.verbose and (i + 1) % 1000 == 0:
             print(f"warm-up step {i + 1}: t={sim.t:.4f} rms Mach {sim.rms_mach():.3f}", file=sys.stderr, flush=True)
+    u0 = sim.u.clone()
+    drive0 = sim.driving_state()
     wall, prof, retries, dt_min = _timed(sim, args.steps, measure_profile)
     main = _summary(args, sim, precision, wall, prof, retries, dt_min)
     compare = None
     if not args.no_compare:
-        other = "fp32" if precision == "fp64" else "fp64"
-        try:
-            cfg2 = dataclasses.replace(cfg, precision=dg.DG_FP32 if other == "fp32" else dg.DG_FP64)
-            dtype = torch.float32 if other == "fp32" else torch.float64
-            sim2 = Simulation(cfg2, u=sim.u.to(dtype).contiguous(), driving=drv)
-            sim2.t = sim.t
-            for _ in range(min(args.warmup, 20)):
-                sim2.step()
-            w2, p2, r2, d2 = _timed(sim2, args.steps, measure_profile)
-            compare = {other: _summary(args, sim2, other, w2, p2, r2, d2)}
-            sim2.ctx.close()
-        except Exception as exc:  # report, do not hide the main measurement
-            compare = {other: {"error": str(exc)}}
+        compare = {}
+        ref = sim.u.detach().clone()
+        legs = [("fp32" if precision == "fp64" else "fp64", False)]
+        if learned:
+            legs.append(("fp32", True))
+        params, train_info = (None, None)
+        for other, use_learned in legs:
+            name = other + ("_learned" if use_learned else "")
+            try:
+                if use_learned and params is None:
+                    params, train_info = _train_sensor(args, sim, ds)
+                fl = flags | (dg.DG_LEARNED_SENSOR if use_learned else 0)
+                cfg2 = dataclasses.replace(cfg, precision=dg.DG_FP32 if other == "fp32" else dg.DG_FP64, flags=fl)
+                dtype = torch.float32 if other == "fp32" else torch.float64
+                sim2 = Simulation(cfg2, u=u0.to(dtype).contiguous(), driving=drv,
+                                  sensor_params=params if use_learned else None)
+                sim2.set_driving_state(drive0)
+                w2, p2, r2, d2 = _timed(sim2, args.steps, measure_profile)
+                rec = _summary(args, sim2, other, w2, p2, r2, d2)
+                rec["vs_main"] = analysis.compare(sim2.u, ref, k, (N, N, N))
+                if use_learned:
+                    rec["training"] = train_info
+                    rec["fallback_fraction_mean"] = float(sum(sim2.fallback_counts)) / max(
+                        len(sim2.fallback_counts), 1) / cfg.ncell
+                    rec["judge_every"] = sim2.judge_every
+                compare[name] = rec
+                sim2.ctx.close()
+            except Exception as exc:  # report, do not hide the main measurement
+                compare[name] = {"error": str(exc)}
     sim.ctx.close()
     return main, compare
 
@@ -208,6 +257,10 @@ def main():
     p.add_argument("--no-compare", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=10)
+    p.add_argument("--no-learned", action="store_true")
+    p.add_argument("--snapshots", type=int, default=16)
+    p.add_argument("--snapshot-every", type=int, default=100)
+    p.add_argument("--train-steps", type=int, default=2000)
     p.add_argument("--copy-calibration", action="store_true")
     args = p.parse_args()
     if args.copy_calibration:

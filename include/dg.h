@@ -166,6 +166,12 @@ int dg_profile_read(dg_ctx *ctx, double *out_host);
 int dg_forcing_ou_ndraws(void);
 int dg_forcing_ou_init(dg_ctx *ctx, double t_c, double sigma);
 int dg_forcing_ou_advance(dg_ctx *ctx, const double *z_host, double dt_drive);
+/* The OU state itself (before the solenoidal projection), dg_forcing_ou_ndraws() doubles
+ * of host memory: get copies it out; set replaces it (after dg_forcing_ou_init) and
+ * installs its table, so a run can be resumed or copied with identical driving. */
+int dg_forcing_ou_get(const dg_ctx *ctx, double *x_host);
+int dg_forcing_ou_set(dg_ctx *ctx, const double *x_host);
+
 /* Copy of the current mode table (nmodes_max rows of 9 doubles); returns nmodes. */
 int dg_forcing_get(const dg_ctx *ctx, double *modes_host, int nmodes_max);
 
@@ -187,9 +193,9 @@ int dg_forcing_get(const dg_ctx *ctx, double *modes_host, int nmodes_max);
  * the cell (div vhat is linear at degree 2) times (h/(k+1))/cs; |mean velocity|/cs. */
 int dg_sensor_features(dg_ctx *ctx, const void *u, float *x_dev);
 
-/* Plain-sensor labels nu[ncell] (double, device): the largest vNR bulk viscosity
- * alpha (h/p)^2 s + beta cs (h/p) over the compressed interior points (s = -div vhat > 0),
- * 0 if none is compressed. */
+/* Plain-sensor labels nu[ncell] (double, device): the vNR bulk viscosity
+ * nu(s) = alpha (h/p)^2 s + beta cs (h/p) averaged over the compressed interior points
+ * (s = -div vhat > 0) with weights omega_q s_q, 0 if none is compressed. */
 int dg_sensor_labels(dg_ctx *ctx, const void *u, double *nu_dev);
 
 /* Training targets t[ncell] (float, device): t = log(1 + nu/1e-3) of the plain-sensor

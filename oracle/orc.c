@@ -927,9 +927,11 @@ int orc_sensor_features(const orc_cfg *cfg, const double *u, double *x)
     return ORC_OK;
 }
 
-/* Plain-sensor label of a cell: the largest vNR bulk viscosity over its interior points,
- * nu_K = max over compressed points (s = -div v > 0) of alpha (h/p)^2 s + beta cs (h/p)
- * (Pi = rho nu s without the Pi_max cap); 0 when no point is compressed. */
+/* Plain-sensor label of a cell: the vNR bulk viscosity nu(s) = alpha (h/p)^2 s + beta cs
+ * (h/p) (Pi = rho nu s without the Pi_max cap) averaged over the compressed interior
+ * points (s = -div v > 0) with weights omega_q s_q, so that rho nu_K s reproduces the
+ * cell's quadrature sum of the vNR pressure where rho is uniform:
+ *   nu_K = sum omega s nu(s) / sum omega s;  0 when no point is compressed. */
 int orc_sensor_labels(const orc_cfg *cfg, const double *u, double *nu)
 {
     if (check_cfg(cfg)) return ORC_EINVAL;
@@ -942,7 +944,7 @@ int orc_sensor_labels(const orc_cfg *cfg, const double *u, double *nu)
     for (long c = 0; c < nc; ++c) {
         double vh[3 * NBMAX];
         project_cell(T, u, nc, c, vh);
-        double best = 0.0;
+        double num = 0.0, den = 0.0;
         for (int q = 0; q < T->nq; ++q) {
             double divv = 0.0;
             for (int d = 0; d < 3; ++d)
@@ -950,11 +952,12 @@ int orc_sensor_labels(const orc_cfg *cfg, const double *u, double *nu)
             divv *= 2.0 / cfg->h;
             if (divv < 0.0) {
                 double sq = -divv;
-                double r = cfg->alpha * hp * hp * sq + cfg->beta * cfg->cs * hp;
-                if (r > best) best = r;
+                double nuq = cfg->alpha * hp * hp * sq + cfg->beta * cfg->cs * hp;
+                num += T->vw[q] * sq * nuq;
+                den += T->vw[q] * sq;
             }
         }
-        nu[c] = best;
+        nu[c] = den > 0.0 ? num / den : 0.0;
     }
     free(T);
     return ORC_OK;

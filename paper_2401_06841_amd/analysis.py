@@ -7,7 +7,8 @@
 * Velocity power spectrum: v = m/rho evaluated on a uniform grid of p = k+1 points per cell
   per dimension (N p points per dimension, Sec. 4.3), FFT, energy 1/2 |v_hat|^2 summed over
   integer shells |kappa| in [K - 1/2, K + 1/2); distance between two spectra = mean
-  |log10 E_a - log10 E_b| over 1 <= K <= N p / 2.
+  |log10 E_a - log10 E_b| over 1 <= K <= N p / 2 (all sampled scales) and over
+  1 <= K <= N / 2 (scales resolved by the cells).
 The basis (orthonormal total-degree Legendre, graded order) is evaluated here with numpy's
 Legendre routines; nothing here runs in a simulation step.
 """
@@ -115,4 +116,5 @@ def compare(u_test, u_ref, k: int, n: tuple[int, int, int]):
     ea = power_spectrum(velocity_grid(a, k, n))
     eb = power_spectrum(velocity_grid(b, k, n))
     return {"l2_rel_rho": rho, "l2_rel_m": mom, "density_pdf_l1": pdf_distance(pa, pb),
-            "spectrum_log10_mean_abs": spectrum_distance(ea, eb, kmax)}
+            "spectrum_log10_mean_abs": spectrum_distance(ea, eb, kmax),
+            "spectrum_log10_mean_abs_cell_scales": spectrum_distance(ea, eb, min(n) // 2)}

@@ -70,3 +70,20 @@ int dg_forcing_ou_advance(dg_ctx *c, const double *z, double dt_drive)
     }
     return dg_set_forcing(c, tab, nm);
 }
+
+int dg_forcing_ou_get(const dg_ctx *c, double *x)
+{
+    if (!c || !x) return DG_EINVAL;
+    std::memcpy(x, c->ou_x, sizeof(c->ou_x));
+    return DG_OK;
+}
+
+int dg_forcing_ou_set(dg_ctx *c, const double *x)
+{
+    if (!c) return DG_EINVAL;
+    if (!x) return dg_fail(c, DG_EINVAL, "x is null");
+    if (!c->ou_ready) return dg_fail(c, DG_ESTATE, "dg_forcing_ou_init was not called");
+    std::memcpy(c->ou_x, x, sizeof(c->ou_x));
+    double z[NMODES * 6] = {};
+    return dg_forcing_ou_advance(c, z, 0.0);   // f = 1, no noise: installs the table of x
+}

@@ -384,9 +384,9 @@ __global__ void __launch_bounds__(BLOCK) k_features(const void *u_, float *__res
     xc[19] = (float)(vm / cs);
 }
 
-// plain-sensor label: the largest vNR bulk viscosity alpha (h/p)^2 s + beta cs (h/p) over
-// the compressed interior points (s = -div v > 0; Pi = rho nu s without the cap,
-// Sec. 3.1); it grows with s, so it is taken at the most compressed point
+// plain-sensor label: the vNR bulk viscosity nu(s) = alpha (h/p)^2 s + beta cs (h/p)
+// (Pi = rho nu s without the cap, Sec. 3.1) averaged over the compressed interior points
+// (s = -div v > 0) with weights omega s: nu = alpha (h/p)^2 sum(w s^2)/sum(w s) + beta cs h/p
 // OUT = double: the label nu itself; OUT = float: the training target log(1 + nu/nu0)
 template <typename T, int K, typename OUT>
 __global__ void __launch_bounds__(BLOCK) k_labels(const void *u_, OUT *__restrict__ nu, const void *tab_, Mesh g,
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(BLOCK) k_labels(const void *u_, OUT *__restric
     load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
     T V[3][NB];
     project_cell<T, K>(W, tab, V, nullptr, T(0));
-    double smin = 0.0;
+    double s1 = 0.0, s2 = 0.0;
 #pragma unroll 1
     for (int q = 0; q < S::NQ; ++q) {
         ctab<T> *dph = tab + TL::VDPHI + q * 3 * ND;
@@ -416,12 +416,16 @@ __global__ void __launch_bounds__(BLOCK) k_labels(const void *u_, OUT *__restric
 #pragma unroll
             for (int l = 0; l < NB; ++l)
                 if (M.dj[d][l] >= 0) div += V[d][l] * dph[d * ND + M.dj[d][l]];
-        smin = fmin(smin, (double)div);
+        const double sq = -(double)div * (2.0 / h);
+        if (sq > 0.0) {
+            const double w = (double)tab[TL::VW + q];
+            s1 += w * sq;
+            s2 += w * sq * sq;
+        }
     }
     if (!active) return;
-    const double s = -smin * 2.0 / h;
     const double hp = h / (K + 1);
-    const double v = s > 0.0 ? alpha * hp * hp * s + beta * cs * hp : 0.0;
+    const double v = s1 > 0.0 ? alpha * hp * hp * (s2 / s1) + beta * cs * hp : 0.0;
     if (sizeof(OUT) == 8) nu[c] = (OUT)v;
     else nu[c] = (OUT)log1p(v / NU0);
 }

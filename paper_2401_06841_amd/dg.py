@@ -59,6 +59,8 @@ _SIGS = {
     "dg_forcing_ou_init": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
     "dg_forcing_ou_advance": (ctypes.c_int, [_vp, _dp, ctypes.c_double]),
     "dg_forcing_get": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
+    "dg_forcing_ou_get": (ctypes.c_int, [_vp, _dp]),
+    "dg_forcing_ou_set": (ctypes.c_int, [_vp, _dp]),
     "dg_sensor_features": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_sensor_labels": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_sensor_targets": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -261,6 +263,21 @@ def dg_forcing_ou_advance(ctx: Context, z, dt_drive: float):
     if z.size != dg_forcing_ou_ndraws():
         raise ValueError("wrong number of draws")
     ctx._chk(_lib.dg_forcing_ou_advance(ctx.h, z.ctypes.data_as(_dp), float(dt_drive)))
+
+
+def dg_forcing_ou_get(ctx: Context):
+    import numpy as np
+    x = np.zeros(dg_forcing_ou_ndraws())
+    ctx._chk(_lib.dg_forcing_ou_get(ctx.h, x.ctypes.data_as(_dp)))
+    return x
+
+
+def dg_forcing_ou_set(ctx: Context, x):
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.size != dg_forcing_ou_ndraws():
+        raise ValueError("wrong OU state size")
+    ctx._chk(_lib.dg_forcing_ou_set(ctx.h, x.ctypes.data_as(_dp)))
 
 
 def dg_forcing_get(ctx: Context):

@@ -103,6 +103,18 @@ class Simulation:
         self.nstep += 1
         return dt
 
+    def driving_state(self):
+        """Everything that determines the future driving: time, update counters, OU state."""
+        d = {"t": self.t, "n_drive": self.n_drive, "next_drive": self.next_drive}
+        if self.driving is not None:
+            d["ou_x"] = dg.dg_forcing_ou_get(self.ctx).tolist()
+        return d
+
+    def set_driving_state(self, d):
+        self.t, self.n_drive, self.next_drive = d["t"], d["n_drive"], d["next_drive"]
+        if self.driving is not None and "ou_x" in d:
+            dg.dg_forcing_ou_set(self.ctx, np.asarray(d["ou_x"]))
+
     def rms_mach(self):
         """Volume-weighted RMS Mach number from the cell means (Sec. 4.1 definition with the
         velocity of each cell's mean state)."""
@@ -113,10 +125,9 @@ class Simulation:
 
     def save(self, path: str):
         np.save(path + ".npy", self.u.detach().cpu().numpy())
-        meta = {"cfg": dataclasses.asdict(self.cfg), "t": self.t, "nstep": self.nstep,
+        meta = {"cfg": dataclasses.asdict(self.cfg), "nstep": self.nstep,
                 "driving": dataclasses.asdict(self.driving) if self.driving else None,
-                "n_drive": self.n_drive, "next_drive": self.next_drive,
-                "modes": dg.dg_forcing_get(self.ctx).tolist()}
+                "state": self.driving_state()}
         with open(path + ".json", "w") as fh:
             json.dump(meta, fh)
 
@@ -132,11 +143,7 @@ class Simulation:
         dtype = torch.float64 if cfg.precision == dg.DG_FP64 else torch.float32
         u = torch.as_tensor(arr, device="cuda").to(dtype).contiguous()
         drv = Driving(**meta["driving"]) if meta["driving"] else None
-        sim = cls(cfg, u=u, driving=None)
-        sim.driving = drv
-        sim.t, sim.nstep = meta["t"], meta["nstep"]
-        sim.n_drive, sim.next_drive = meta["n_drive"], meta["next_drive"]
-        if drv is not None:
-            dg.dg_forcing_ou_init(sim.ctx, drv.t_c, drv.sigma)
-            dg.dg_set_forcing(sim.ctx, np.asarray(meta["modes"]))
+        sim = cls(cfg, u=u, driving=drv)
+        sim.nstep = meta["nstep"]
+        sim.set_driving_state(meta["state"])
         return sim

@@ -5,12 +5,15 @@ compression sensor of Sec. 3.1.  Every operation runs in libdg kernels:
   * data   - per-cell features (dg_sensor_features) and targets t = log(1 + nu/1e-3) of
              the plain sensor's labels (dg_sensor_targets), taken from snapshots of runs
              with the plain method;
-  * fit    - full-batch mean-squared error, gradient by dg_mlp_grad (fixed-order
-             reduction, so training is deterministic), Adam by dg_mlp_adam;
-  * use    - a Simulation with DG_LEARNED_SENSOR infers nu for every stage inside
-             dg_rk_step; every `judge_every` steps dg_sensor_judge recomputes the plain
-             labels and sends the cells whose prediction is off by more than tau (relative
-             to nu + 1e-3) back to the plain sensor until the next judgement.
+  * fit    - mean-squared error on the full batch or on contiguous minibatches, gradient
+             by dg_mlp_grad (fixed-order reduction, so training is deterministic), Adam by
+             dg_mlp_adam;
+  * use    - a Simulation with DG_LEARNED_SENSOR runs the network on u^n once per step
+             (dg_sensor_infer) before the time step; the per-cell bulk viscosity serves the
+             viscous time-step bound and the three stages.  Every `judge_every` steps
+             dg_sensor_judge recomputes the plain labels and sends the cells whose
+             prediction is off by more than tau (relative to nu + 1e-3) back to the plain
+             sensor until the next judgement.
 Parameters are one FP32 vector in the order W1[64][20], b1, W2[64][64], b2, W3[1][64], b3.
 """
 from __future__ import annotations
@@ -60,8 +63,8 @@ class Dataset:
 
 
 class Trainer:
-    """Adam on the full batch; the context only supplies the stream and the scratch for the
-    per-wave gradient partials."""
+    """Adam; the context only supplies the stream and the scratch for the per-wave
+    gradient partials."""
 
     def __init__(self, ctx: dg.Context, params: torch.Tensor):
         dev = ctx.device
@@ -77,13 +80,23 @@ class Trainer:
         dg.dg_mlp_grad(self.ctx, self.P, x, t, self.g, self.loss_dev)
         return float(self.loss_dev.item())
 
-    def fit(self, x, t, steps: int, lr: float = 3e-3, lr_final: float = 3e-4, log_every: int = 0):
+    def fit(self, x, t, steps: int, lr: float = 3e-3, lr_final: float = 3e-4, log_every: int = 0,
+            batch: int = 0, seed: int = 0):
         """`steps` Adam updates with the learning rate decaying geometrically from lr to
-        lr_final; returns the losses read back every log_every steps (and the last)."""
+        lr_final; returns the losses read back every log_every steps (and the last).  With
+        0 < batch < rows each step uses one contiguous block of `batch` rows at a seeded
+        random offset, otherwise the full batch."""
         losses = []
         ratio = (lr_final / lr) ** (1.0 / max(steps - 1, 1))
+        n = x.shape[0]
+        rng = np.random.default_rng(seed)
         for i in range(steps):
-            dg.dg_mlp_grad(self.ctx, self.P, x, t, self.g, self.loss_dev)
+            if 0 < batch < n:
+                o = int(rng.integers(0, n - batch + 1))
+                xb, tb = x[o:o + batch], t[o:o + batch]
+            else:
+                xb, tb = x, t
+            dg.dg_mlp_grad(self.ctx, self.P, xb, tb, self.g, self.loss_dev)
             if (log_every and i % log_every == 0) or i == steps - 1:
                 losses.append(float(self.loss_dev.item()))
             self.step += 1

@@ -429,8 +429,8 @@ def test_sensor_features_and_labels_closed_form():
     divergence slopes vanish and the last entry is |v0|/cs.  A quadratic velocity gives the
     slopes from the Legendre derivatives d/dxi Lt_2 = 3 sqrt(5) xi, Lt_1 d/dxi Lt_1 = 3 xi.
     The label of a uniformly compressing cell is the vNR bulk viscosity alpha (h/p)^2 s +
-    beta cs (h/p); with slopes, the most compressed Gauss point is a corner
-    xi_i = -sign(D_i) sqrt(3/5)."""
+    beta cs (h/p); with slopes it is the omega s weighted mean of that viscosity over the
+    compressed Gauss points, summed here by brute force over numpy's 3-point rule."""
     k, N = 2, 3
     cfg = oracle.Cfg(N, N, N, k, flags=ALL)
     idx = _mode_index(k)
@@ -475,9 +475,18 @@ def test_sensor_features_and_labels_closed_form():
     np.testing.assert_allclose(xq[:, 16:19], np.tile(slopes * hp, (cfg.ncell, 1)), rtol=1e-12)
     np.testing.assert_allclose(xq[:, 7:16], x[:, 7:16], atol=1e-14)
     trace = np.trace(G)
-    s = -trace + math.sqrt(0.6) * np.abs(slopes).sum()
-    nuq = 2.0 * hp * hp * s + 0.2 * hp if s > 0 else 0.0
-    np.testing.assert_allclose(oracle.sensor_labels(cfg, uq), nuq, rtol=1e-10)
+    xg, wg = np.polynomial.legendre.leggauss(3)
+    num = den = 0.0
+    for a in range(3):
+        for b in range(3):
+            for cc in range(3):
+                sq = -(trace + slopes[0] * xg[a] + slopes[1] * xg[b] + slopes[2] * xg[cc])
+                if sq > 0:
+                    w = wg[a] * wg[b] * wg[cc]
+                    num += w * sq * (2.0 * hp * hp * sq + 0.2 * hp)
+                    den += w * sq
+    assert den > 0
+    np.testing.assert_allclose(oracle.sensor_labels(cfg, uq), num / den, rtol=1e-10)
     # label: uniform compression at rate s per direction
     gamma = 2.0
     uc = np.zeros(cfg.shape)
