@@ -138,6 +138,23 @@ void build_tables(std::vector<double> &t)
         t[TL::LEND + 2 * n + 0] = lt(n, -1.0);
         t[TL::LEND + 2 * n + 1] = lt(n, 1.0);
     }
+    // basis values on the faces: the face point r = r1 + (k+1) r2 has the tangential
+    // coordinates (g[r1], g[r2]) along the axes tan1(d) < tan2(d), and xi_d = -1 or +1
+    for (int d = 0; d < 3; ++d)
+        for (int s = 0; s < 2; ++s)
+            for (int r2 = 0; r2 < S::N1; ++r2)
+                for (int r1 = 0; r1 < S::N1; ++r1) {
+                    const int r = r1 + S::N1 * r2;
+                    double xi[3];
+                    xi[d] = s ? 1.0 : -1.0;
+                    xi[tan1(d)] = g[r1];
+                    xi[tan2(d)] = g[r2];
+                    for (int l = 0; l < S::NB; ++l) {
+                        const int *e = M.e[l];
+                        t[TL::PLIFT + ((d * 2 + s) * S::NF + r) * S::NB + l] =
+                            lt(e[0], xi[0]) * lt(e[1], xi[1]) * lt(e[2], xi[2]);
+                    }
+                }
 }
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }

@@ -63,6 +63,48 @@ constexpr Modes<K> make_modes()
     return M;
 }
 
+// position of the mode with exponents (a, b, c) in the graded order
+constexpr int idx3(int a, int b, int c)
+{
+    const int n = a + b + c;
+    return n * (n + 1) * (n + 2) / 6 + (n - a) * (n - a + 1) / 2 + c;
+}
+
+// Derivative of a basis function along one axis in the basis itself: from
+// P_n' = sum over j = n-1, n-3, ... >= 0 of (2j+1) P_j it follows that
+// d/dxi Lt_n = sum_j sqrt((2n+1)(2j+1)) Lt_j, so d/dxi_d phi_e is a combination of the
+// modes with e_d replaced by j; all of them have total degree < K.  The divergence of a
+// degree-K vector field is therefore a degree-(K-1) polynomial with NDIV coefficients,
+// the first NDIV modes of the graded order.
+template <int K>
+struct DivMap {
+    static constexpr int NDIV = K * (K + 1) * (K + 2) / 6;
+    static constexpr int MAXT = (K + 1) / 2;    // terms per derivative (j of the right parity)
+    int m[3][Shape<K>::NB][MAXT];               // target mode, or -1
+    int f[3][Shape<K>::NB][MAXT];               // (2n+1)(2j+1): the factor is its square root
+};
+
+template <int K>
+constexpr DivMap<K> make_divmap()
+{
+    DivMap<K> D{};
+    const Modes<K> M = make_modes<K>();
+    for (int d = 0; d < 3; ++d)
+        for (int l = 0; l < Shape<K>::NB; ++l) {
+            int t = 0;
+            for (int i = 0; i < DivMap<K>::MAXT; ++i) { D.m[d][l][i] = -1; D.f[d][l][i] = 0; }
+            const int n = M.e[l][d];
+            for (int j = n - 1; j >= 0; j -= 2) {
+                int e[3] = {M.e[l][0], M.e[l][1], M.e[l][2]};
+                e[d] = j;
+                D.m[d][l][t] = idx3(e[0], e[1], e[2]);
+                D.f[d][l][t] = (2 * n + 1) * (2 * j + 1);
+                ++t;
+            }
+        }
+    return D;
+}
+
 // Offsets (in elements) of the quadrature tables inside one contiguous device array.
 template <int K>
 struct TabLayout {
@@ -74,7 +116,9 @@ struct TabLayout {
     static constexpr int FW = F2 + S::NF * S::NB2;          // [NF]       face weights
     static constexpr int LEND = FW + S::NF;                 // [K+1][2]   Lt_n(-1), Lt_n(+1)
     static constexpr int VXI = LEND + 2 * (K + 1);          // [NQ][3]    reference coordinates
-    static constexpr int SIZE = VXI + 3 * S::NQ;
+    static constexpr int PLIFT = VXI + 3 * S::NQ;           // [3][2][NF][NB] phi_l at the face points of
+                                                            //   face (normal d, side s: 0 low, 1 high)
+    static constexpr int SIZE = PLIFT + 3 * 2 * S::NF * S::NB;
 };
 
 }  // namespace dg

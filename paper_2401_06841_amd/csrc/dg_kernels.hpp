@@ -331,11 +331,7 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
             // keep at most one variable's loads in flight (register pressure)
             if (l == S::NB - 1) __builtin_amdgcn_sched_barrier(0);
         }
-    T Dacc[4][S::NB2];
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int j = 0; j < S::NB2; ++j) Dacc[v][j] = T(0);
+    ctab<T> *plift = tab + TL::PLIFT + (D * 2 + s) * S::NF * S::NB;
 #pragma unroll 1
     for (int r = 0; r < S::NF; ++r) {
         ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
@@ -370,24 +366,27 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
         if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
         else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
         const T wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];   // outward normal
+        ctab<T> *pl = plift + r * S::NB;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const T g = wr * F[v];
 #pragma unroll
-            for (int j = 0; j < S::NB2; ++j) Dacc[v][j] += g * f2[j];
+            for (int l = 0; l < S::NB; ++l) L[v][l] += g * pl[l];
         }
     }
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-        for (int l = 0; l < S::NB; ++l) L[v][l] += Dacc[v][M.d2[D][l]] * lend[2 * M.e[l][D] + s];
 }
 
 // ------------------------------------------------------------------ RHS kernel
 // dw/dt = (1/(4h)) [ sum_q w_q grad_xi(phi) . F(q) - sum_faces +- sum_r w_r phi F*(r) ]
 //         + (1/8) sum_q w_q phi rho a (Sec. 2.2 weight evolution; Sec. 3.1; Sec. 4.2)
+// occupancy target (waves per SIMD) of the right-hand-side kernel: the register file
+// holds the 4 NB coefficients and 4 NB accumulators of a cell per lane, so FP64 fits two
+// waves and FP32 four (two at degree 3) without spilling
 template <typename T, int K>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_rhs(RhsArgs a)
+constexpr int rhs_waves() { return sizeof(T) == 8 ? 2 : (K <= 2 ? 4 : 2); }
+
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K>()))) k_rhs(RhsArgs a)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -417,8 +416,13 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
     T W[4][NB];
     load_field<T, K, 4>(U, bo, W);
 
-    // derivative-relevant coefficients of the projected velocity (divergence, Sec. 3.1)
-    T G[3][ND];
+    // divergence of the projected velocity (Sec. 3.1) as a degree-(K-1) polynomial:
+    // its NDIV modal coefficients from the exact derivatives of the Legendre basis
+    constexpr DivMap<K> DM = make_divmap<K>();
+    constexpr int NDIV = DivMap<K>::NDIV;
+    T Dv[NDIV];
+#pragma unroll
+    for (int m = 0; m < NDIV; ++m) Dv[m] = T(0);
     bool learned = false;
     T nu = T(0);
     if (av) {
@@ -426,7 +430,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
         for (int d = 0; d < 3; ++d)
 #pragma unroll
             for (int l = 0; l < NB; ++l)
-                if (M.dj[d][l] >= 0) G[d][M.dj[d][l]] = VH.get(d, l, bo);
+                if (M.e[l][d] >= 1) {
+                    const T v = VH.get(d, l, bo);
+#pragma unroll
+                    for (int t = 0; t < DivMap<K>::MAXT; ++t)
+                        if (DM.m[d][l][t] >= 0) Dv[DM.m[d][l][t]] += v * T(__builtin_sqrt(double(DM.f[d][l][t])));
+                }
         if (a.flags & F_LEARNED) {
             learned = a.fb[c] == 0;
             nu = ((const T *)a.nu)[c];
@@ -443,8 +452,18 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
     const T half_h = (T)(0.5 * a.h);
 
     // ---- volume integral
+    // the driving acceleration of the next point is requested one iteration ahead, so
+    // its memory latency overlaps the arithmetic of the current point
+    T an0 = T(0), an1 = T(0), an2 = T(0);
+    if (force) { an0 = AP.get(0, 0, bo); an1 = AP.get(1, 0, bo); an2 = AP.get(2, 0, bo); }
 #pragma unroll 1
     for (int q = 0; q < S::NQ; ++q) {
+        const T ac0 = an0, ac1 = an1, ac2 = an2;
+        if (force && q + 1 < S::NQ) {
+            an0 = AP.get(0, q + 1, bo);
+            an1 = AP.get(1, q + 1, bo);
+            an2 = AP.get(2, q + 1, bo);
+        }
         ctab<T> *ph = tab + TL::VPHI + q * NB;
         ctab<T> *dph = tab + TL::VDPHI + q * 3 * ND;
         const T wq = tab[TL::VW + q];
@@ -461,9 +480,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
         if (av) {
             T div = T(0);
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int j = 0; j < ND; ++j) div += G[d][j] * dph[d * ND + j];
+            for (int m = 0; m < NDIV; ++m) div += Dv[m] * ph[m];
             div *= two_h;
             const T pv = vnr_pi<T>(rho, div, hp, alpha, beta, cs, inv_dt);
             // learned sensor: the cell's bulk viscosity nu in place of the vNR one,
@@ -495,9 +512,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
         }
         if (force) {
             const T rw = rho * wq;
-            const T s0 = rw * AP.get(0, q, bo);
-            const T s1 = rw * AP.get(1, q, bo);
-            const T s2 = rw * AP.get(2, q, bo);
+            const T s0 = rw * ac0;
+            const T s1 = rw * ac1;
+            const T s2 = rw * ac2;
             fs0 += s0; fs1 += s1; fs2 += s2;
             const T t0 = s0 * half_h, t1 = s1 * half_h, t2 = s2 * half_h;
 #pragma unroll
