@@ -277,6 +277,59 @@ __device__ __forceinline__ void project_cell(const T (&W)[4][Shape<K>::NB], ctab
     if (smax) *smax = sm;
 }
 
+// Component d of the projected velocity of one cell (Sec. 3.2), same arithmetic as
+// project_cell for that component; working one component at a time keeps only NB
+// accumulators live.
+template <typename T, int K>
+__device__ __forceinline__ void project_component(const T (&W)[4][Shape<K>::NB], ctab<T> *tab, int d,
+                                                  T (&V)[Shape<K>::NB])
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+#pragma unroll
+    for (int l = 0; l < S::NB; ++l) V[l] = T(0);
+#pragma unroll 1
+    for (int q = 0; q < S::NQ; ++q) {
+        ctab<T> *ph = tab + TL::VPHI + q * S::NB;
+        T rho = T(0), m = T(0);
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            const T p = ph[l];
+            rho += W[0][l] * p;
+            m += W[1 + d][l] * p;
+        }
+        const T a = T(0.125) * tab[TL::VW + q] * (m * rcp(rho));
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) V[l] += a * ph[l];
+    }
+}
+
+// FP64 kernels project one velocity component at a time (fewer live registers, four
+// waves per SIMD); FP32 ones have registers to spare and project all three at once
+template <typename T>
+constexpr bool split_projection() { return sizeof(T) == 8; }
+
+// projected velocity of one cell written straight to memory
+template <typename T, int K>
+__device__ __forceinline__ void project_store(const T (&W)[4][Shape<K>::NB], ctab<T> *tab,
+                                              const Field<T, 3> &out, unsigned bo, bool active)
+{
+    if constexpr (split_projection<T>()) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            T V[Shape<K>::NB];
+            project_component<T, K>(W, tab, d, V);
+            if (active)
+#pragma unroll
+                for (int l = 0; l < Shape<K>::NB; ++l) out.put(d, l, bo, V[l]);
+        }
+    } else {
+        T V[3][Shape<K>::NB];
+        project_cell<T, K>(W, tab, V, nullptr, T(0));
+        if (active) store_field<T, K, 3>(out, bo, V);
+    }
+}
+
 // isothermal Rusanov flux across a face with normal +e_D between the low (L) and high
 // (R) states; u = (rho, m), v = velocity (Sec. 2.2 numerical flux)
 template <int D, typename T>
@@ -652,11 +705,7 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
         }
     }
     if (active) store_field<T, K, 4>(Field<T, 4>(a.out, NB, nc), bo, U);
-    if (a.vh_out) {
-        T V[3][NB];
-        project_cell<T, K>(U, tab, V, nullptr, T(0));
-        if (active) store_field<T, K, 3>(Field<T, 3>(a.vh_out, NB, nc), bo, V);
-    }
+    if (a.vh_out) project_store<T, K>(U, tab, Field<T, 3>(a.vh_out, NB, nc), bo, active);
 }
 
 // ------------------------------------------------------------ projection kernel
@@ -690,25 +739,75 @@ __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, co
     ctab<T> *tab = as_tab<T>(tab_);
     T W[4][NB];
     load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
-    T V[3][NB];
     double sm = 0.0;
-    project_cell<T, K>(W, tab, V, part ? &sm : nullptr, (T)pa.cs);
-    if (vh_ && active) store_field<T, K, 3>(Field<T, 3>(vh_, NB, nc), bo, V);
+    if (part) {
+        // largest signal speed sum_d |v_d| + cs over the interior points
+#pragma unroll 1
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<T> *ph = tab + TL::VPHI + q * NB;
+            T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const T p = ph[l];
+                rho += W[0][l] * p;
+                m0 += W[1][l] * p;
+                m1 += W[2][l] * p;
+                m2 += W[3][l] * p;
+            }
+            const T ir = rcp(rho);
+            const double s = (double)fabs(m0 * ir) + (double)fabs(m1 * ir) + (double)fabs(m2 * ir) + 3.0 * pa.cs;
+            sm = fmax(sm, s);
+        }
+    }
+    // projected velocity, component by component: stored, and folded into the modal
+    // coefficients of its divergence (a degree-(K-1) polynomial) for the viscous bound
+    constexpr DivMap<K> DM = make_divmap<K>();
+    constexpr int NDIV = DivMap<K>::NDIV;
+    const bool visc = part && pa.visc;
+    T Dv[NDIV];
+#pragma unroll
+    for (int m = 0; m < NDIV; ++m) Dv[m] = T(0);
+    if (vh_ || visc) {
+        const Field<T, 3> VO(vh_ ? vh_ : u_, NB, nc);
+        auto fold = [&](int d, const T (&V)[NB]) {
+#pragma unroll
+            for (int l = 0; l < NB; ++l)
+                if (M.e[l][d] >= 1)
+#pragma unroll
+                    for (int t = 0; t < DivMap<K>::MAXT; ++t)
+                        if (DM.m[d][l][t] >= 0) Dv[DM.m[d][l][t]] += V[l] * T(__builtin_sqrt(double(DM.f[d][l][t])));
+        };
+        if constexpr (split_projection<T>()) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                T V[NB];
+                project_component<T, K>(W, tab, d, V);
+                if (vh_ && active)
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) VO.put(d, l, bo, V[l]);
+                if (visc) fold(d, V);
+            }
+        } else {
+            T V[3][NB];
+            project_cell<T, K>(W, tab, V, nullptr, T(0));
+            if (vh_ && active) store_field<T, K, 3>(VO, bo, V);
+            if (visc)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fold(d, V[d]);
+        }
+    }
     if (part) {
         double nm = 0.0;
-        if (pa.visc) {
+        if (visc) {
             // most negative divergence of the projected velocity over the interior points
             const double hp = pa.h / (K + 1);
             double smin = 0.0;
 #pragma unroll 1
             for (int q = 0; q < S::NQ; ++q) {
-                ctab<T> *dph = tab + TL::VDPHI + q * 3 * ND;
+                ctab<T> *ph = tab + TL::VPHI + q * NB;
                 T div = T(0);
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
-#pragma unroll
-                    for (int l = 0; l < NB; ++l)
-                        if (M.dj[d][l] >= 0) div += V[d][l] * dph[d * ND + M.dj[d][l]];
+                for (int m = 0; m < NDIV; ++m) div += Dv[m] * ph[m];
                 smin = fmin(smin, (double)div);
             }
             const double s = -smin * (2.0 / pa.h);
