@@ -127,6 +127,18 @@ int dg_rhs(dg_ctx *ctx, const void *u, void *dudt, double dt);
  * floor, i.e. the caller must retry with a smaller dt (Sec. 3.1). */
 int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
 
+/* The same step, also returning the time step of the new state: on DG_OK,
+ * *dt_next_host equals dg_dt_max of u^(n+1) (same definition and FP64 reduction, computed
+ * inside the last stage), and the projection of u^(n+1) is kept in the workspace.
+ * reuse = 1 states that u has not been modified since the previous dg_rk_step_next call
+ * on this context returned DG_OK for the same array; the step then starts from the kept
+ * projection.  The library additionally checks the array pointer and that no other
+ * state-changing call (dg_rhs, dg_rk_step, dg_limit, dg_set_workspace) came in between,
+ * and recomputes the projection otherwise; it cannot see writes made outside libdg.
+ * One synchronisation per call (status and dt_next in one read-back).  With
+ * DG_LEARNED_SENSOR: DG_EUNSUPPORTED (the next time step there needs the network). */
+int dg_rk_step_next(dg_ctx *ctx, void *u, double dt, int reuse, int *status_host, double *dt_next_host);
+
 /* Time step dt = min(dt_adv, dt_visc), reduced in FP64 over all cells and interior points:
  * dt_adv = cfl h / ((k+1) max sum_d (|m_d/rho| + cs)) (Sec. 7: dt proportional to h/(k+1));
  * with DG_AV and cfl_visc > 0, dt_visc = cfl_visc (h/p)^2 / max nu, the explicit stability

@@ -290,6 +290,7 @@ int dg_set_workspace(dg_ctx *c, void *ws, size_t bytes)
     if (bytes < c->ws_need)
         return dg_fail(c, DG_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, c->ws_need);
     c->ws = (char *)ws;
+    c->gen++;
     c->forcing_dirty = c->nmodes > 0;
     c->have_nu = false;
     if (c->cfg.flags & DG_LEARNED_SENSOR) return sensor_reset_flags(c);
@@ -399,10 +400,8 @@ static int launch_forcing_points(dg_ctx *c)
     return DG_OK;
 }
 
-template <typename T, int K>
-static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int *fail)
+static ProjArgs proj_args(const dg_ctx *c)
 {
-    const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
     ProjArgs pa;
     pa.cs = c->cfg.cs;
     pa.h = c->cfg.h;
@@ -412,6 +411,14 @@ static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int 
     const bool learned = (c->cfg.flags & DG_LEARNED_SENSOR) && (c->cfg.flags & DG_AV) && c->have_nu;
     pa.nu = learned ? c->wp(c->off.nu) : nullptr;
     pa.fb = learned ? (const int *)c->wp(c->off.fb) : nullptr;
+    return pa;
+}
+
+template <typename T, int K>
+static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int *fail)
+{
+    const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    const ProjArgs pa = proj_args(c);
     hipLaunchKernelGGL((k_project<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, vh, c->tab, g, pa,
                        part, fail);
     LAUNCHCHK(c);
@@ -419,7 +426,7 @@ static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int 
 }
 
 template <typename T, int K>
-static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt)
+static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt, int *fail_reset = nullptr)
 {
     if ((c->cfg.flags & DG_FORCING) && c->forcing_dirty) {
         int rc = launch_forcing_points<T, K>(c);
@@ -435,6 +442,7 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     a.nu = c->wp(c->off.nu);
     a.fb = (const int *)c->wp(c->off.fb);
     a.part = (double *)c->wp(c->off.part);
+    a.fail_reset = fail_reset;
     a.g = Mesh{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
     a.flags = c->cfg.flags;
     if (c->nmodes == 0) a.flags &= ~DG_FORCING;
@@ -465,7 +473,7 @@ static int launch_abar(dg_ctx *c)
 
 template <typename T, int K>
 static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
-                        void *un_copy, double ca, double cb, double dt, long long *nlim)
+                        void *un_copy, double ca, double cb, double dt, long long *nlim, double *part = nullptr)
 {
     StageArgs a;
     a.ui = ui;
@@ -478,6 +486,8 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.abar = (L && use_meanfree(c)) ? c->abar() : nullptr;
     a.fail = c->fail();
     a.nlim = nlim;
+    a.part = part;
+    a.pa = proj_args(c);
     a.g = Mesh{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
     a.flags = c->cfg.flags;
     a.ca = ca;
@@ -509,26 +519,53 @@ static int do_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
 }
 
 template <typename T, int K>
-static int do_step(dg_ctx *c, void *u, double dt, int *status_host)
+static int launch_dt_final(dg_ctx *c, double *dst)
+{
+    const double hp = c->cfg.h / (K + 1);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->nblk, 2,
+                       c->cfg.cfl * c->cfg.h / (K + 1), c->cfg.cfl_visc > 0.0 ? c->cfg.cfl_visc * hp * hp : 0.0,
+                       dst);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+// One SSP-RK3 step.  reuse: start from the projection kept by the previous step of this
+// context (when it is still valid); dt_next: also compute the time step of the new state
+// in the last stage (its projection is then kept in vh0).
+template <typename T, int K>
+static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, double *dt_next)
 {
     static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
     static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
     void *vh[2] = {c->wp(c->off.vh0), c->wp(c->off.vh1)};
     void *st[3] = {c->wp(c->off.stA), c->wp(c->off.stB), u};
-    int rc = launch_project<T, K>(c, u, vh[0], nullptr, c->fail());
-    if (rc) return rc;
+    const bool cached = reuse && c->vh_cache_u == u && c->vh_cache_gen == c->gen;
+    c->gen++;
+    c->vh_cache_u = nullptr;
+    int rc = DG_OK;
+    if (!cached) {
+        rc = launch_project<T, K>(c, u, vh[0], nullptr, c->fail());
+        if (rc) return rc;
+    }
     const void *ui = u;
     for (int s = 0; s < 3; ++s) {
-        rc = launch_rhs<T, K>(c, ui, vh[s & 1], c->wp(c->off.L), dt);
+        rc = launch_rhs<T, K>(c, ui, vh[s & 1], c->wp(c->off.L), dt, (s == 0 && cached) ? c->fail() : nullptr);
         if (rc) return rc;
         if (use_meanfree(c)) {
             rc = launch_abar(c);
             if (rc) return rc;
         }
-        rc = launch_stage<T, K>(c, ui, u, c->wp(c->off.L), st[s], s < 2 ? vh[(s + 1) & 1] : nullptr,
-                                s == 0 ? c->wp(c->off.un_copy) : nullptr, CA[s], CB[s], dt, nullptr);
+        void *vnext = s < 2 ? vh[(s + 1) & 1] : (dt_next ? vh[0] : nullptr);
+        double *part = (s == 2 && dt_next) ? (double *)c->wp(c->off.part) : nullptr;
+        rc = launch_stage<T, K>(c, ui, u, c->wp(c->off.L), st[s], vnext, s == 0 ? c->wp(c->off.un_copy) : nullptr,
+                                CA[s], CB[s], dt, nullptr, part);
         if (rc) return rc;
         ui = st[s];
+    }
+    if (dt_next) {
+        rc = launch_dt_final<T, K>(c, c->scal() + 8);
+        if (rc) return rc;
+        HIPCHK(c, hipMemcpyAsync(c->pinned + 1, c->scal() + 8, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
     HIPCHK(c, hipMemcpyAsync(c->pinned, c->fail(), sizeof(int), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -538,6 +575,11 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host)
         const size_t bytes = 4 * (size_t)c->nb * c->nc * c->es;
         HIPCHK(c, hipMemcpyAsync(u, c->wp(c->off.un_copy), bytes, hipMemcpyDeviceToDevice, c->stream));
         return DG_RETRY;
+    }
+    if (dt_next) {
+        *dt_next = ((volatile double *)c->pinned)[1];
+        c->vh_cache_u = u;
+        c->vh_cache_gen = c->gen;
     }
     return DG_OK;
 }
@@ -563,6 +605,7 @@ int dg_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
     int rc;
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u")) || (rc = check_ptr(c, dudt, "dudt"))) return rc;
     if ((rc = learned_ready(c))) return rc;
+    c->gen++;
     return DISPATCH(c, do_rhs, c, u, dudt, dt);
 }
 
@@ -573,7 +616,20 @@ int dg_rk_step(dg_ctx *c, void *u, double dt, int *status_host)
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
     if ((rc = learned_ready(c))) return rc;
-    return DISPATCH(c, do_step, c, u, dt, status_host);
+    return DISPATCH(c, do_step, c, u, dt, status_host, false, (double *)nullptr);
+}
+
+int dg_rk_step_next(dg_ctx *c, void *u, double dt, int reuse, int *status_host, double *dt_next_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
+    if (!dt_next_host) return dg_fail(c, DG_EINVAL, "dt_next_host is null");
+    if (c->cfg.flags & DG_LEARNED_SENSOR)
+        return dg_fail(c, DG_EUNSUPPORTED, "the next time step of a learned-sensor run depends on the network: "
+                                           "use dg_sensor_infer, dg_dt_max and dg_rk_step");
+    return DISPATCH(c, do_step, c, u, dt, status_host, reuse != 0, dt_next_host);
 }
 
 template <typename T, int K>
@@ -583,11 +639,8 @@ static int do_dt(dg_ctx *c, const void *u, double *dt_out, int on_host)
     int rc = launch_project<T, K>(c, u, nullptr, part, nullptr);
     if (rc) return rc;
     double *dst = on_host ? c->scal() + 8 : dt_out;
-    const double hp = c->cfg.h / (K + 1);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 2,
-                       c->cfg.cfl * c->cfg.h / (K + 1), c->cfg.cfl_visc > 0.0 ? c->cfg.cfl_visc * hp * hp : 0.0,
-                       dst);
-    LAUNCHCHK(c);
+    rc = launch_dt_final<T, K>(c, dst);
+    if (rc) return rc;
     if (on_host) {
         HIPCHK(c, hipMemcpyAsync(c->pinned, dst, sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -644,6 +697,7 @@ int dg_limit(dg_ctx *c, void *u, long *nfail_host)
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
     const int saved = c->cfg.flags;
     c->cfg.flags |= DG_POS_LIMITER;
+    c->gen++;
     rc = DISPATCH(c, do_limit, c, u, nfail_host);
     c->cfg.flags = saved;
     return rc;

@@ -42,6 +42,11 @@ struct dg_ctx {
     double prof_ms[2] = {0.0, 0.0};
     long prof_n[2] = {0, 0};
     char err[512] = {0};
+    // projection of the state left in vh0 by the last dg_rk_step_next (valid while no other
+    // state-changing call has been made: gen counts such calls)
+    unsigned long gen = 0;
+    const void *vh_cache_u = nullptr;
+    unsigned long vh_cache_gen = 0;
 
     void *wp(size_t o) const { return ws + o; }
     double *scal() const { return (double *)(ws + off.scal); }

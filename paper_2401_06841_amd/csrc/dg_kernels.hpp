@@ -195,9 +195,18 @@ struct RhsArgs {
     const void *nu;         // [nc] learned viscosity
     const int *fb;          // [nc] fallback flags
     double *part;           // [nblocks][4] driving partial sums (mode-0 source, mass)
+    int *fail_reset;        // positivity failure flag to clear before the stages, or NULL
     Mesh g;
     int flags;
     double h, cs, alpha, beta, dt;
+};
+
+// time-step bound inputs shared by the projection and stage kernels
+struct ProjArgs {
+    double cs, h, alpha, beta;
+    int visc;           // also reduce the largest bulk viscosity of the viscous pressure
+    const void *nu;     // learned per-cell bulk viscosity (element type T), or NULL
+    const int *fb;      // fallback flags of the learned sensor (1 = plain sensor)
 };
 
 struct StageArgs {
@@ -211,6 +220,8 @@ struct StageArgs {
     const double *abar;     // removed mean acceleration (3), or NULL
     int *fail;              // positivity failure flag
     long long *nlim;        // count of failing cells (may be NULL)
+    double *part;           // with vh_out: per-block time-step maxima of u^(i+1), or NULL
+    ProjArgs pa;
     Mesh g;
     int flags;
     double ca, cb, dt, rho_floor, rho_floor_rel;
@@ -308,27 +319,6 @@ __device__ __forceinline__ void project_component(const T (&W)[4][Shape<K>::NB],
 // waves per SIMD); FP32 ones have registers to spare and project all three at once
 template <typename T>
 constexpr bool split_projection() { return sizeof(T) == 8; }
-
-// projected velocity of one cell written straight to memory
-template <typename T, int K>
-__device__ __forceinline__ void project_store(const T (&W)[4][Shape<K>::NB], ctab<T> *tab,
-                                              const Field<T, 3> &out, unsigned bo, bool active)
-{
-    if constexpr (split_projection<T>()) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            T V[Shape<K>::NB];
-            project_component<T, K>(W, tab, d, V);
-            if (active)
-#pragma unroll
-                for (int l = 0; l < Shape<K>::NB; ++l) out.put(d, l, bo, V[l]);
-        }
-    } else {
-        T V[3][Shape<K>::NB];
-        project_cell<T, K>(W, tab, V, nullptr, T(0));
-        if (active) store_field<T, K, 3>(out, bo, V);
-    }
-}
 
 // isothermal Rusanov flux across a face with normal +e_D between the low (L) and high
 // (R) states; u = (rho, m), v = velocity (Sec. 2.2 numerical flux)
@@ -452,6 +442,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const int c0 = blk * BLOCK + threadIdx.x;
     const bool active = c0 < nc;
     const int c = active ? c0 : 0;
+    if (a.fail_reset && blockIdx.x == 0 && threadIdx.x == 0) *a.fail_reset = 0;
 
     const bool av = a.flags & F_AV;
     const bool prim = a.flags & F_PRIM;
@@ -613,6 +604,106 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     }
 }
 
+// Projected velocity of one cell (Sec. 3.2; stored when vh is not null) and, when part is
+// not null, the per-block maxima for the time step: signal speed sum_d |v_d| + cs over the
+// interior points, and bulk viscosity alpha (h/p)^2 |div v| + beta cs h/p at compressing
+// points (or the learned cell viscosity where the learned sensor is in use), written to
+// part[2 blk] and part[2 blk + 1].  With part set every thread of the block must call it.
+template <typename T, int K>
+__device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB], ctab<T> *tab, void *vh, int nc,
+                                                   unsigned bo, int c, bool active, const ProjArgs &pa,
+                                                   double *part, int blk, double *lds)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    constexpr int NB = S::NB;
+    double sm = 0.0;
+    if (part) {
+        // largest signal speed sum_d |v_d| + cs over the interior points
+#pragma unroll 1
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<T> *ph = tab + TL::VPHI + q * NB;
+            T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const T p = ph[l];
+                rho += W[0][l] * p;
+                m0 += W[1][l] * p;
+                m1 += W[2][l] * p;
+                m2 += W[3][l] * p;
+            }
+            const T ir = rcp(rho);
+            const double s = (double)fabs(m0 * ir) + (double)fabs(m1 * ir) + (double)fabs(m2 * ir) + 3.0 * pa.cs;
+            sm = fmax(sm, s);
+        }
+    }
+    // projected velocity, component by component: stored, and folded into the modal
+    // coefficients of its divergence (a degree-(K-1) polynomial) for the viscous bound
+    constexpr DivMap<K> DM = make_divmap<K>();
+    constexpr int NDIV = DivMap<K>::NDIV;
+    const bool visc = part && pa.visc;
+    T Dv[NDIV];
+#pragma unroll
+    for (int m = 0; m < NDIV; ++m) Dv[m] = T(0);
+    if (vh || visc) {
+        const Field<T, 3> VO(vh ? vh : (const void *)tab, NB, nc);
+        auto fold = [&](int d, const T (&V)[NB]) {
+#pragma unroll
+            for (int l = 0; l < NB; ++l)
+                if (M.e[l][d] >= 1)
+#pragma unroll
+                    for (int t = 0; t < DivMap<K>::MAXT; ++t)
+                        if (DM.m[d][l][t] >= 0) Dv[DM.m[d][l][t]] += V[l] * T(__builtin_sqrt(double(DM.f[d][l][t])));
+        };
+        if constexpr (split_projection<T>()) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                T V[NB];
+                project_component<T, K>(W, tab, d, V);
+                if (vh && active)
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) VO.put(d, l, bo, V[l]);
+                if (visc) fold(d, V);
+            }
+        } else {
+            T V[3][NB];
+            project_cell<T, K>(W, tab, V, nullptr, T(0));
+            if (vh && active) store_field<T, K, 3>(VO, bo, V);
+            if (visc)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) fold(d, V[d]);
+        }
+    }
+    if (part) {
+        double nm = 0.0;
+        if (visc) {
+            // most negative divergence of the projected velocity over the interior points
+            const double hp = pa.h / (K + 1);
+            double smin = 0.0;
+#pragma unroll 1
+            for (int q = 0; q < S::NQ; ++q) {
+                ctab<T> *ph = tab + TL::VPHI + q * NB;
+                T div = T(0);
+#pragma unroll
+                for (int m = 0; m < NDIV; ++m) div += Dv[m] * ph[m];
+                smin = fmin(smin, (double)div);
+            }
+            const double s = -smin * (2.0 / pa.h);
+            if (s > 0.0) nm = pa.alpha * hp * hp * s + pa.beta * pa.cs * hp;
+            if (pa.nu && pa.fb[c] == 0) nm = fmax((double)((const T *)pa.nu)[c], 0.0);
+        }
+        __syncthreads();
+        sm = block_max(active ? sm : 0.0, lds);
+        __syncthreads();
+        nm = block_max(active ? nm : 0.0, lds);
+        if (threadIdx.x == 0) {
+            part[2 * blk] = sm;
+            part[2 * blk + 1] = nm;
+        }
+    }
+}
+
 // --------------------------------------------------------------- stage kernel
 // out = ca*un + cb*(ui + dt*(L - abar W_rho)) (Shu-Osher SSP-RK3 stage), then the
 // positivity limiter (Sec. 3.1; target minimum max(floor, rel * mean)) with FP64
@@ -705,29 +796,18 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
         }
     }
     if (active) store_field<T, K, 4>(Field<T, 4>(a.out, NB, nc), bo, U);
-    if (a.vh_out) project_store<T, K>(U, tab, Field<T, 3>(a.vh_out, NB, nc), bo, active);
+    if (a.vh_out) project_and_bounds<T, K>(U, tab, a.vh_out, nc, bo, c, active, a.pa, a.part, blk, lds);
 }
 
 // ------------------------------------------------------------ projection kernel
-struct ProjArgs {
-    double cs, h, alpha, beta;
-    int visc;           // also reduce the largest bulk viscosity of the viscous pressure
-    const void *nu;     // learned per-cell bulk viscosity (element type T), or NULL
-    const int *fb;      // fallback flags of the learned sensor (1 = plain sensor)
-};
 
-// vhat of u (Sec. 3.2) and, optionally, per-block maxima for the time step (signal speed
-// sum_d |v_d| + cs; viscosity alpha (h/p)^2 |div v| + beta cs h/p at compressing points,
-// or the learned cell viscosity where the learned sensor is in use) and a reset of the
-// failure flag.
+// vhat of u and, optionally, the per-block time-step maxima and a reset of the failure flag
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, const void *tab_, Mesh g, ProjArgs pa,
                                                    double *part, int *fail)
 {
     using S = Shape<K>;
-    using TL = TabLayout<K>;
-    constexpr Modes<K> M = make_modes<K>();
-    constexpr int NB = S::NB, ND = S::ND;
+    constexpr int NB = S::NB;
     __shared__ double lds[4];
     const int nc = g.nc;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -739,89 +819,7 @@ __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, co
     ctab<T> *tab = as_tab<T>(tab_);
     T W[4][NB];
     load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
-    double sm = 0.0;
-    if (part) {
-        // largest signal speed sum_d |v_d| + cs over the interior points
-#pragma unroll 1
-        for (int q = 0; q < S::NQ; ++q) {
-            ctab<T> *ph = tab + TL::VPHI + q * NB;
-            T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
-#pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                const T p = ph[l];
-                rho += W[0][l] * p;
-                m0 += W[1][l] * p;
-                m1 += W[2][l] * p;
-                m2 += W[3][l] * p;
-            }
-            const T ir = rcp(rho);
-            const double s = (double)fabs(m0 * ir) + (double)fabs(m1 * ir) + (double)fabs(m2 * ir) + 3.0 * pa.cs;
-            sm = fmax(sm, s);
-        }
-    }
-    // projected velocity, component by component: stored, and folded into the modal
-    // coefficients of its divergence (a degree-(K-1) polynomial) for the viscous bound
-    constexpr DivMap<K> DM = make_divmap<K>();
-    constexpr int NDIV = DivMap<K>::NDIV;
-    const bool visc = part && pa.visc;
-    T Dv[NDIV];
-#pragma unroll
-    for (int m = 0; m < NDIV; ++m) Dv[m] = T(0);
-    if (vh_ || visc) {
-        const Field<T, 3> VO(vh_ ? vh_ : u_, NB, nc);
-        auto fold = [&](int d, const T (&V)[NB]) {
-#pragma unroll
-            for (int l = 0; l < NB; ++l)
-                if (M.e[l][d] >= 1)
-#pragma unroll
-                    for (int t = 0; t < DivMap<K>::MAXT; ++t)
-                        if (DM.m[d][l][t] >= 0) Dv[DM.m[d][l][t]] += V[l] * T(__builtin_sqrt(double(DM.f[d][l][t])));
-        };
-        if constexpr (split_projection<T>()) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                T V[NB];
-                project_component<T, K>(W, tab, d, V);
-                if (vh_ && active)
-#pragma unroll
-                    for (int l = 0; l < NB; ++l) VO.put(d, l, bo, V[l]);
-                if (visc) fold(d, V);
-            }
-        } else {
-            T V[3][NB];
-            project_cell<T, K>(W, tab, V, nullptr, T(0));
-            if (vh_ && active) store_field<T, K, 3>(VO, bo, V);
-            if (visc)
-#pragma unroll
-                for (int d = 0; d < 3; ++d) fold(d, V[d]);
-        }
-    }
-    if (part) {
-        double nm = 0.0;
-        if (visc) {
-            // most negative divergence of the projected velocity over the interior points
-            const double hp = pa.h / (K + 1);
-            double smin = 0.0;
-#pragma unroll 1
-            for (int q = 0; q < S::NQ; ++q) {
-                ctab<T> *ph = tab + TL::VPHI + q * NB;
-                T div = T(0);
-#pragma unroll
-                for (int m = 0; m < NDIV; ++m) div += Dv[m] * ph[m];
-                smin = fmin(smin, (double)div);
-            }
-            const double s = -smin * (2.0 / pa.h);
-            if (s > 0.0) nm = pa.alpha * hp * hp * s + pa.beta * pa.cs * hp;
-            if (pa.nu && pa.fb[c] == 0) nm = fmax((double)((const T *)pa.nu)[c], 0.0);
-        }
-        sm = block_max(active ? sm : 0.0, lds);
-        __syncthreads();
-        nm = block_max(active ? nm : 0.0, lds);
-        if (threadIdx.x == 0) {
-            part[2 * blk] = sm;
-            part[2 * blk + 1] = nm;
-        }
-    }
+    project_and_bounds<T, K>(W, tab, vh_, nc, bo, c, active, pa, part, blk, lds);
 }
 
 // driving acceleration a(x) = sum_m Re[a_m exp(2 pi i n_m.x)] at every volume point (Sec. 4.2)

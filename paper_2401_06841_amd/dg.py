@@ -50,6 +50,7 @@ _SIGS = {
     "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double]),
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _ip]),
     "dg_dt_max": (ctypes.c_int, [_vp, _vp, _dp, ctypes.c_int]),
+    "dg_rk_step_next": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]),
     "dg_project_primitive": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_limit": (ctypes.c_int, [_vp, _vp, _lp]),
     "dg_conserved_sums": (ctypes.c_int, [_vp, _vp, _dp]),
@@ -206,6 +207,17 @@ def dg_rk_step(ctx: Context, u, dt: float) -> int:
     ctx._check_state(u)
     st = ctypes.c_int(0)
     return ctx._chk(_lib.dg_rk_step(ctx.h, _ptr(u), float(dt), ctypes.byref(st)), ok=(DG_OK, DG_RETRY))
+
+
+def dg_rk_step_next(ctx: Context, u, dt: float, reuse: bool):
+    """One SSP-RK3 step in place that also returns the next time step; returns
+    (DG_OK, dt_next) or (DG_RETRY, None) with u restored."""
+    ctx._check_state(u)
+    st = ctypes.c_int(0)
+    dn = ctypes.c_double(0.0)
+    rc = ctx._chk(_lib.dg_rk_step_next(ctx.h, _ptr(u), float(dt), 1 if reuse else 0, ctypes.byref(st),
+                                       ctypes.byref(dn)), ok=(DG_OK, DG_RETRY))
+    return rc, (dn.value if rc == DG_OK else None)
 
 
 def dg_dt_max(ctx: Context, u, out_dev=None) -> float:

@@ -1,7 +1,8 @@
 """Time-stepping driver around libdg (host control flow only; all arithmetic on the GPU).
 
-One driver step: CFL time step from dg_dt_max (FP64 reduction on the GPU, one 8-byte
-read-back), Ornstein-Uhlenbeck driving updates on the host whenever the simulation time
+One driver step: CFL time step (FP64 reduction on the GPU: dg_dt_max, or for the plain
+sensor the value dg_rk_step_next returned with the previous step, so that a step costs
+one read-back), Ornstein-Uhlenbeck driving updates on the host whenever the simulation time
 crosses the next update time (every t_c/100, Sec. 4.2), then dg_rk_step; when the step
 reports a positivity failure the state has been restored and the step is retried with
 half the time step (Sec. 3.1).  With the learned sensor the network runs on u^n before the
@@ -62,6 +63,9 @@ class Simulation:
             self._drive(1e30)                       # start from the stationary distribution
             self.next_drive = driving.dt_drive
         self._torch = torch
+        # next time step returned by the fused step (plain sensor), valid while u is unchanged
+        self._dt_next = None
+        self._u_version = None
         # learned sensor (DG_LEARNED_SENSOR): network parameters, judge cadence and threshold
         self.learned = bool(cfg.flags & dg.DG_LEARNED_SENSOR)
         self.judge_every = judge_every
@@ -77,7 +81,13 @@ class Simulation:
         dg.dg_forcing_ou_advance(self.ctx, z, dt_drive)
         self.n_drive += 1
 
+    def invalidate(self):
+        """Forget the time step and projection kept from the last step (call after writing
+        to self.u by other means than torch in-place operations, which are detected)."""
+        self._dt_next = None
+
     def step(self):
+        fused = not self.learned
         if self.learned:
             # the network's viscosity of u^n serves the time step and the three stages; the
             # judge (which also runs the network) refreshes the fallback flags
@@ -85,7 +95,8 @@ class Simulation:
                 self.fallback_counts.append(dg.dg_sensor_judge(self.ctx, self.u, self.tau))
             else:
                 dg.dg_sensor_infer(self.ctx, self.u)
-        dt = dg.dg_dt_max(self.ctx, self.u)
+        reuse = fused and self._dt_next is not None and self._u_version == self.u._version
+        dt = self._dt_next if reuse else dg.dg_dt_max(self.ctx, self.u)
         if not (dt > 0.0 and np.isfinite(dt)):
             raise RuntimeError(f"invalid time step {dt} at step {self.nstep}")
         if self.driving is not None:
@@ -93,12 +104,22 @@ class Simulation:
                 self._drive(self.driving.dt_drive)
                 self.next_drive += self.driving.dt_drive
         tries = 0
-        while dg.dg_rk_step(self.ctx, self.u, dt) == dg.DG_RETRY:
+        self._dt_next = None
+        while True:
+            if fused:
+                rc, dt_next = dg.dg_rk_step_next(self.ctx, self.u, dt, reuse)
+            else:
+                rc, dt_next = dg.dg_rk_step(self.ctx, self.u, dt), None
+            if rc == dg.DG_OK:
+                break
             self.retries += 1
             tries += 1
             if tries > self.retry_limit:
                 raise RuntimeError(f"positivity retries exhausted at step {self.nstep}")
             dt *= 0.5
+            reuse = False
+        self._dt_next = dt_next
+        self._u_version = self.u._version
         self.t += dt
         self.nstep += 1
         return dt

@@ -1,4 +1,5 @@
-"""The host time loop: checkpoint and resume, and copying a run's driving state.
+"""The host time loop: checkpoint and resume, copying a run's driving state, and the fused
+step that returns the next time step (one read-back per step).
 
 A driven run interrupted by a checkpoint and resumed in a fresh context must continue
 bitwise identically to the uninterrupted run (same OU state, same update counters, same
@@ -9,6 +10,8 @@ import numpy as np
 import pytest
 import torch
 
+import synthetic
+from gpu_util import dev, make
 from paper_2401_06841_amd import dg
 from paper_2401_06841_amd.driver import Driving, Simulation
 
@@ -48,3 +51,99 @@ def test_driving_state_copy_gives_identical_runs():
         a.step()
         b.step()
     assert torch.equal(a.u, b.u)
+
+
+# ------------------------------------------------- fused next time step and reuse
+
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+def test_fused_next_time_step_equals_dt_max(precision):
+    n, k = 12, 2
+    flags = FLAGS
+    ctx = make(n, n, n, k, flags, precision)
+    dg.dg_set_forcing(ctx, synthetic.forcing_table(3, amp=2.0))
+    u = dev(synthetic.turbulent_like(n, n, n, k, mach=3.0, seed=5, high_amp=0.02, kmax_frac=0.125), ctx)
+    dt = dg.dg_dt_max(ctx, u)
+    for _ in range(3):
+        rc, dn = dg.dg_rk_step_next(ctx, u, dt, True)
+        assert rc == dg.DG_OK
+        assert dn == dg.dg_dt_max(ctx, u)        # same kernels' arithmetic, same reduction
+        dt = dn
+
+
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+def test_fused_steps_match_plain_steps_bitwise(precision):
+    n, k = 10, 2
+    u0 = synthetic.turbulent_like(n, n, n, k, mach=3.0, seed=8, high_amp=0.02, kmax_frac=0.125)
+    modes = synthetic.forcing_table(2, amp=2.0)
+    a, b = make(n, n, n, k, FLAGS, precision), make(n, n, n, k, FLAGS, precision)
+    for c in (a, b):
+        dg.dg_set_forcing(c, modes)
+    ua, ub = dev(u0, a), dev(u0, b)
+    dtb = dg.dg_dt_max(b, ub)
+    for i in range(8):
+        dta = dg.dg_dt_max(a, ua)
+        assert dg.dg_rk_step(a, ua, dta) == dg.DG_OK
+        assert dta == dtb
+        rc, dtb = dg.dg_rk_step_next(b, ub, dtb, i > 0)
+        assert rc == dg.DG_OK
+    assert torch.equal(ua, ub)
+
+
+def test_reuse_is_dropped_after_state_changes():
+    """After an intervening state-changing call the kept projection is not used: a state
+    perturbed in between and then passed through dg_limit (which invalidates) gives the
+    plain step's result."""
+    n, k = 8, 2
+    u0 = synthetic.turbulent_like(n, n, n, k, mach=2.0, seed=3, high_amp=0.02, kmax_frac=0.125)
+    a, b = make(n, n, n, k, FLAGS & ~dg.DG_FORCING), make(n, n, n, k, FLAGS & ~dg.DG_FORCING)
+    ua, ub = dev(u0, a), dev(u0, b)
+    rc, dn = dg.dg_rk_step_next(b, ub, dg.dg_dt_max(b, ub), False)
+    assert rc == dg.DG_OK
+    ua.copy_(ub)
+    for t in (ua, ub):
+        t[1:, 1] += 0.01                          # perturb the momentum's linear x mode
+    dg.dg_limit(b, ub)                            # a state-changing library call
+    dg.dg_limit(a, ua)
+    rc, _ = dg.dg_rk_step_next(b, ub, dn, True)
+    assert rc == dg.DG_OK
+    assert dg.dg_rk_step(a, ua, dn) == dg.DG_OK
+    assert torch.equal(ua, ub)
+
+
+def test_fused_step_retry_restores_state():
+    k = 1
+    ctx = make(4, 3, 2, k, dg.DG_POS_LIMITER)
+    u = np.zeros((4, ctx.cfg.nb, ctx.cfg.ncell))
+    u[0, 0] = 5e-4
+    u[1, 0] = 2e-4
+    ud = dev(u, ctx)
+    rc, dn = dg.dg_rk_step_next(ctx, ud, 1e-3, False)
+    assert rc == dg.DG_RETRY and dn is None
+    assert np.array_equal(ud.cpu().numpy(), u)
+
+
+def test_driver_detects_torch_writes_between_steps():
+    n = 8
+    cfg = dg.Config(n, n, n, degree=2, precision=dg.DG_FP64, flags=FLAGS)
+    drv = Driving(3.0, 2.5, seed=6)
+    a = Simulation(cfg, driving=drv)
+    for _ in range(5):
+        a.step()
+    b = Simulation(cfg, u=a.u.clone(), driving=drv)
+    b.set_driving_state(a.driving_state())
+    a.u[1:, 2] += 1e-3                            # in-place torch write: the driver must notice
+    b.u[1:, 2] += 1e-3
+    b.invalidate()
+    for _ in range(3):
+        a.step()
+        b.step()
+    assert torch.equal(a.u, b.u)
+
+
+def test_learned_context_rejects_the_fused_step():
+    ctx = make(4, 4, 4, 2, FLAGS | dg.DG_LEARNED_SENSOR)
+    u = ctx.empty_state()
+    u.zero_()
+    u[0, 0] = 1.0
+    with pytest.raises(dg.DGError):
+        dg.dg_rk_step_next(ctx, u, 1e-3, False)
