@@ -5,10 +5,12 @@
   PDFs (Sec. 5); distance between two PDFs = L1 norm of the difference of the normalised
   histograms.
 * Velocity power spectrum: v = m/rho evaluated on a uniform grid of p = k+1 points per cell
-  per dimension (N p points per dimension, Sec. 4.3), FFT, energy 1/2 |v_hat|^2 summed over
+  per dimension (N p points per dimension, Sec. 4.3; rho clipped at the 1e-3 floor there,
+  since positivity is enforced only at the Gauss points), FFT, energy 1/2 |v_hat|^2 summed over
   integer shells |kappa| in [K - 1/2, K + 1/2); distance between two spectra = mean
   |log10 E_a - log10 E_b| over 1 <= K <= N p / 2 (all sampled scales) and over
-  1 <= K <= N / 2 (scales resolved by the cells).
+  1 <= K <= N / 2 (scales resolved by the cells).  On meshes above 85^3 cells p is reduced
+  so that the sampling grid has at most 256 points per dimension.
 The basis (orthonormal total-degree Legendre, graded order) is evaluated here with numpy's
 Legendre routines; nothing here runs in a simulation step.
 """
@@ -16,6 +18,8 @@ from __future__ import annotations
 
 import numpy as np
 from numpy.polynomial import legendre as npleg
+
+RHO_FLOOR = 1e-3    # density floor of the method (Sec. 3.1)
 
 
 def modes(k: int):
@@ -67,16 +71,18 @@ def pdf_distance(p, q) -> float:
     return float(np.abs(np.asarray(p) - np.asarray(q)).sum())
 
 
-def velocity_grid(u, k: int, n: tuple[int, int, int]):
-    """v = m / rho on the uniform sub-grid (k+1 points per cell per dimension, cell-centred
-    sub-cells); returns [3][nz p][ny p][nx p]."""
+def velocity_grid(u, k: int, n: tuple[int, int, int], p: int = 0):
+    """v = m / rho on the uniform sub-grid of p points per cell per dimension (default
+    k+1; cell-centred sub-cells); returns [3][nz p][ny p][nx p]."""
     u = _as_numpy(u)
     nx, ny, nz = n
-    p = k + 1
+    p = p or (k + 1)
     xi = -1.0 + (2.0 * np.arange(p) + 1.0) / p
     phi = _basis_tensor(k, xi)                                  # [nb][p^3], sub-point (a,b,c) x fastest
     vals = np.einsum("lq,vlc->vqc", phi, u)                     # [4][p^3][cells]
-    v = vals[1:] / vals[0][None]
+    # the limiter keeps rho positive at the Gauss points only; at the sampling points the
+    # density is clipped at the method's floor so that near-vacuum points cannot dominate
+    v = vals[1:] / np.maximum(vals[0], RHO_FLOOR)[None]
     v = v.reshape(3, p, p, p, nz, ny, nx)                       # [d][sz][sy][sx][cz][cy][cx]
     v = v.transpose(0, 4, 1, 5, 2, 6, 3).reshape(3, nz * p, ny * p, nx * p)
     return v
@@ -112,9 +118,13 @@ def compare(u_test, u_ref, k: int, n: tuple[int, int, int]):
     rho = float(np.linalg.norm(a[0] - b[0]) / np.linalg.norm(b[0]))
     mom = float(np.linalg.norm(a[1:] - b[1:]) / np.linalg.norm(b[1:]))
     pa, pb = density_pdf(a, k), density_pdf(b, k)
-    kmax = min(n) * (k + 1) // 2
-    ea = power_spectrum(velocity_grid(a, k, n))
-    eb = power_spectrum(velocity_grid(b, k, n))
+    # k+1 samples per cell (the paper's N p grid), fewer on large meshes so that the grid
+    # stays at most 256 points per dimension
+    p = max(1, min(k + 1, 256 // max(n)))
+    kmax = min(n) * p // 2
+    ea = power_spectrum(velocity_grid(a, k, n, p))
+    eb = power_spectrum(velocity_grid(b, k, n, p))
     return {"l2_rel_rho": rho, "l2_rel_m": mom, "density_pdf_l1": pdf_distance(pa, pb),
+            "spectrum_samples_per_cell": p,
             "spectrum_log10_mean_abs": spectrum_distance(ea, eb, kmax),
             "spectrum_log10_mean_abs_cell_scales": spectrum_distance(ea, eb, min(n) // 2)}

@@ -424,9 +424,11 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
 //         + (1/8) sum_q w_q phi rho a (Sec. 2.2 weight evolution; Sec. 3.1; Sec. 4.2)
 // occupancy target (waves per SIMD) of the right-hand-side kernel: the register file
 // holds the 4 NB coefficients and 4 NB accumulators of a cell per lane, so FP64 fits two
-// waves and FP32 four (two at degree 3) without spilling
+// waves and FP32 four (two at degree 3) without spilling.  FP64 at degree 3 (160 values
+// of coefficients and accumulators) cannot fit 256 VGPRs: one wave per SIMD lets the
+// compiler keep the overflow in accumulation registers instead of scratch memory.
 template <typename T, int K>
-constexpr int rhs_waves() { return sizeof(T) == 8 ? 2 : (K <= 2 ? 4 : 2); }
+constexpr int rhs_waves() { return sizeof(T) == 8 ? (K <= 2 ? 2 : 1) : (K <= 2 ? 4 : 2); }
 
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K>()))) k_rhs(RhsArgs a)
