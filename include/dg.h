@@ -52,7 +52,13 @@ enum dg_flags {
     DG_FORCING = 4,            /* driving acceleration source rho a in the momentum rows (Sec. 4.2) */
     DG_POS_LIMITER = 8,        /* positivity limiter after every stage (Sec. 3.1) */
     DG_LEARNED_SENSOR = 16,    /* viscosity from the learned per-cell sensor (not in the paper) */
-    DG_FORCE_MEANFREE = 32     /* remove the mass-weighted mean acceleration (exact momentum conservation) */
+    DG_FORCE_MEANFREE = 32,    /* remove the mass-weighted mean acceleration (exact momentum conservation) */
+    DG_HLLC = 64,              /* HLLC-type interface flux instead of Rusanov: the isothermal counterpart of
+                                  the HLLC solver of Sec. 2.2 (HLL for density and normal momentum,
+                                  tangential momentum carried by the mass flux, upwinded) */
+    DG_RK_BY_ORDER = 128       /* SSP Runge-Kutta scheme by degree (Sec. 7: k+1 stages per step): two stages
+                                  (second order) at degree 1, three at degree 2, five stages of fourth order
+                                  at degree 3; without it every degree uses three stages (third order) */
 };
 
 typedef struct dg_config {
@@ -116,7 +122,8 @@ int dg_set_forcing(dg_ctx *ctx, const double *modes_host, int nmodes);
  * Errors: DG_EINVAL, DG_ENOMEM (no workspace), DG_ESTATE. */
 int dg_rhs(dg_ctx *ctx, const void *u, void *dudt, double dt);
 
-/* One third-order SSP Runge-Kutta step in place (Shu-Osher form; with DG_LEARNED_SENSOR
+/* One SSP Runge-Kutta step in place (Shu-Osher form; three stages of third order, or the
+ * scheme chosen by DG_RK_BY_ORDER; with DG_LEARNED_SENSOR
  * the stored per-cell viscosity serves the three stages: call dg_sensor_infer on u^n
  * first, DG_ESTATE if none is stored), positivity limiter
  * after every stage when DG_POS_LIMITER is set (Sec. 3.1: all high-order weights of a cell

@@ -28,6 +28,8 @@ FORCING = 4
 POS_LIMITER = 8
 LEARNED = 16
 FORCE_MEANFREE = 32
+HLLC = 64
+RK_BY_ORDER = 128
 
 OK = 0
 RETRY = 1
@@ -63,6 +65,7 @@ def lib():
         L.orc_basis_eval.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.orc_accel.argtypes = [dp, ctypes.c_int, dp, dp]
         L.orc_rusanov.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp]
+        L.orc_hllc.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp, dp]
         L.orc_vnr_pi.argtypes = [cp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         L.orc_vnr_pi.restype = ctypes.c_double
         L.orc_project_primitive.argtypes = [cp, dp, dp]
@@ -76,8 +79,9 @@ def lib():
         L.orc_dt_max_learned.restype = ctypes.c_double
         L.orc_limit.argtypes = [cp, dp, dp]
         L.orc_limit.restype = ctypes.c_long
-        L.orc_ssprk3_linear.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
-        L.orc_ssprk3_linear.restype = ctypes.c_double
+        L.orc_rk_linear.argtypes = [cp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_rk_linear.restype = ctypes.c_double
+        L.orc_rk_stages.argtypes = [cp]
         L.orc_rk_step.argtypes = [cp, dp, ctypes.c_double, dp, ctypes.c_int, dp, ip]
         L.orc_conserved_sums.argtypes = [cp, dp, dp]
         L.orc_points.argtypes = [cp, ctypes.c_int, dp]
@@ -196,6 +200,12 @@ def rusanov(d: int, cs: float, uL, uR):
     return out
 
 
+def hllc(d: int, cs: float, uL, uR):
+    out = np.zeros(4)
+    lib().orc_hllc(d, cs, _d(_f64(uL)), _d(_f64(uR)), _d(out))
+    return out
+
+
 def vnr_pi(cfg: Cfg, rho: float, divv: float, dt: float) -> float:
     return lib().orc_vnr_pi(cfg.c(), rho, divv, dt)
 
@@ -271,8 +281,13 @@ def limit(cfg: Cfg, u):
     return u, nfail, theta
 
 
-def ssprk3_linear(lam: float, dt: float, u0: float) -> float:
-    return lib().orc_ssprk3_linear(lam, dt, u0)
+def rk_linear(cfg: Cfg, lam: float, dt: float, u0: float) -> float:
+    """One step of the configuration's Runge-Kutta scheme on du/dt = lam u."""
+    return lib().orc_rk_linear(cfg.c(), lam, dt, u0)
+
+
+def rk_stages(cfg: Cfg) -> int:
+    return lib().orc_rk_stages(cfg.c())
 
 
 def rk_step(cfg: Cfg, u, dt: float, modes=None, nu=None, fallback=None):

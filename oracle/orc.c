@@ -34,6 +34,8 @@
 #define ORC_POS_LIMITER   8
 #define ORC_LEARNED      16
 #define ORC_FORCE_MEANFREE 32
+#define ORC_HLLC         64
+#define ORC_RK_BY_ORDER  128
 
 #define ORC_OK      0
 #define ORC_RETRY   1
@@ -318,6 +320,36 @@ void orc_rusanov(int d, double cs, const double uL[NV], const double uR[NV], dou
     for (int v = 0; v < NV; ++v) Fh[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * lam * (uR[v] - uL[v]);
 }
 
+/* HLLC-type flux for the isothermal equations (the paper uses Toro's HLLC for the
+ * adiabatic equations, Sec. 2.2; isothermal gas has no contact in the normal subsystem, so
+ * the contact-resolving part concerns the shear waves): wave speeds S_L = min(v_L, v_R) - cs
+ * and S_R = max(v_L, v_R) + cs (v: normal velocity); density and normal momentum take the
+ * HLL flux (F_L if S_L >= 0, F_R if S_R <= 0, else (S_R F_L - S_L F_R + S_L S_R (u_R - u_L))
+ * / (S_R - S_L)); each tangential momentum is carried by that mass flux with the tangential
+ * velocity of the upwind side (left if the mass flux is >= 0). */
+void orc_hllc(int d, double cs, const double uL[NV], const double uR[NV], double Fh[NV])
+{
+    double FL[NV], FR[NV];
+    double mL[3] = {uL[1], uL[2], uL[3]}, mR[3] = {uR[1], uR[2], uR[3]};
+    flux(d, uL[0], mL, cs * cs * uL[0], FL);
+    flux(d, uR[0], mR, cs * cs * uR[0], FR);
+    double vL = uL[1 + d] / uL[0], vR = uR[1 + d] / uR[0];
+    double SL = (vL < vR ? vL : vR) - cs;
+    double SR = (vL > vR ? vL : vR) + cs;
+    int comp[2] = {0, 1 + d};                  /* density, normal momentum */
+    for (int i = 0; i < 2; ++i) {
+        int v = comp[i];
+        if (SL >= 0.0) Fh[v] = FL[v];
+        else if (SR <= 0.0) Fh[v] = FR[v];
+        else Fh[v] = (SR * FL[v] - SL * FR[v] + SL * SR * (uR[v] - uL[v])) / (SR - SL);
+    }
+    for (int t = 0; t < 3; ++t) {
+        if (t == d) continue;
+        double vt = Fh[0] >= 0.0 ? uL[1 + t] / uL[0] : uR[1 + t] / uR[0];
+        Fh[1 + t] = Fh[0] * vt;
+    }
+}
+
 /* von Neumann-Richtmyer viscous pressure (Sec. 3.1): for a compressing point
  * (div v < 0), Pi = alpha rho (h/p)^2 |div v|^2 + beta rho cs (h/p) |div v|, capped at
  * Pi_max = (1/2) rho (h/p)^2 |div v| / dt with p = k+1 the spatial order.  dt <= 0
@@ -468,8 +500,10 @@ static void rhs_cell(const rhs_ctx *R, long c, double *out)
                 double uin[NV], uout[NV], Fh[NV];
                 trace(cfg, T, u, nc, c, vh, T->fphi[d][s][r], uin);
                 trace(cfg, T, u, nc, nbc, vhn, T->fphi[d][1 - s][r], uout);
-                if (s) orc_rusanov(d, cfg->cs, uin, uout, Fh);
-                else   orc_rusanov(d, cfg->cs, uout, uin, Fh);
+                void (*riemann)(int, double, const double *, const double *, double *) =
+                    (cfg->flags & ORC_HLLC) ? orc_hllc : orc_rusanov;
+                if (s) riemann(d, cfg->cs, uin, uout, Fh);
+                else   riemann(d, cfg->cs, uout, uin, Fh);
                 for (int v = 0; v < NV; ++v)
                     for (int l = 0; l < nb; ++l)
                         out[v * nb + l] -= inv4h * T->fw[r] * T->fphi[d][s][r][l] * sign * Fh[v];
@@ -696,34 +730,75 @@ long orc_limit(const orc_cfg *cfg, double *u, double *theta)
     return nfail;
 }
 
-/* ------------------------------------------------------------- SSP-RK3 */
+/* ------------------------------------------------------- SSP Runge-Kutta */
 
-/* One Shu-Osher stage combination out = a*un + b*(ui + dt*L) (third-order SSP
- * Runge-Kutta, Sec. 2.2 and Sec. 7: three stages for third order). */
-static void combine(long n, double a, const double *un, double b, const double *ui,
-                    double dt, const double *L, double *out)
+/* Explicit strong-stability-preserving Runge-Kutta schemes in Shu-Osher form:
+ *   u(0) = u^n,  u(i) = sum_{j<i} ( alpha_ij u(j) + beta_ij dt L(u(j)) ),  u^{n+1} = u(S).
+ * Sec. 7 counts k+1 right-hand-side evaluations per step for degree k (Sec. 2.2: the
+ * time integrator matches the spatial order).  Without ORC_RK_BY_ORDER every degree uses
+ * the three-stage third-order scheme (Shu & Osher); with it, degree 1 uses the two-stage
+ * second-order scheme (Heun), degree 2 the three-stage one and degree 3 the five-stage
+ * fourth-order scheme of Spiteri & Ruuth (2002). */
+#define RK_SMAX 5
+typedef struct {
+    int stages;
+    double alpha[RK_SMAX][RK_SMAX];   /* alpha[i-1][j]: weight of u(j) in u(i) */
+    double beta[RK_SMAX][RK_SMAX];    /* beta[i-1][j]:  weight of dt L(u(j)) in u(i) */
+} rk_scheme;
+
+static const rk_scheme RK2 = {2, {{1.0}, {0.5, 0.5}}, {{1.0}, {0.0, 0.5}}};
+static const rk_scheme RK3 = {3, {{1.0}, {0.75, 0.25}, {1.0 / 3.0, 0.0, 2.0 / 3.0}},
+                              {{1.0}, {0.0, 0.25}, {0.0, 0.0, 2.0 / 3.0}}};
+static const rk_scheme RK54 = {5,
+    {{1.0},
+     {0.444370493651235, 0.555629506348765},
+     {0.620101851488403, 0.0, 0.379898148511597},
+     {0.178079954393132, 0.0, 0.0, 0.821920045606868},
+     {0.0, 0.0, 0.517231671970585, 0.096059710526147, 0.386708617503269}},
+    {{0.391752226571890},
+     {0.0, 0.368410593050371},
+     {0.0, 0.0, 0.251891774271694},
+     {0.0, 0.0, 0.0, 0.544974750228521},
+     {0.0, 0.0, 0.0, 0.063692468666290, 0.226007483236906}}};
+
+static const rk_scheme *scheme_of(const orc_cfg *cfg)
+{
+    if (!(cfg->flags & ORC_RK_BY_ORDER)) return &RK3;
+    return cfg->k == 1 ? &RK2 : (cfg->k == 2 ? &RK3 : &RK54);
+}
+
+/* stage i (1-based) of a scheme: out = sum_{j<i} alpha_ij X[j] + beta_ij dt LX[j] */
+static void stage_combination(const rk_scheme *R, int i, long n, double dt, double *const *X,
+                              double *const *LX, double *out)
 {
     #pragma omp parallel for schedule(static)
-    for (long i = 0; i < n; ++i) out[i] = a * un[i] + b * (ui[i] + dt * L[i]);
-}
-
-static const double RK_A[3] = {0.0, 0.75, 1.0 / 3.0};
-static const double RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
-
-/* SSP-RK3 on the scalar linear test equation du/dt = lambda u with the same stage
- * coefficients as orc_rk_step (used to pin the stage arithmetic). */
-double orc_ssprk3_linear(double lambda, double dt, double u0)
-{
-    double un = u0, ui = u0, out = 0.0;
-    for (int s = 0; s < 3; ++s) {
-        double L = lambda * ui;
-        combine(1, RK_A[s], &un, RK_B[s], &ui, dt, &L, &out);
-        ui = out;
+    for (long e = 0; e < n; ++e) {
+        double acc = 0.0;
+        for (int j = 0; j < i; ++j) acc += R->alpha[i - 1][j] * X[j][e] + R->beta[i - 1][j] * dt * LX[j][e];
+        out[e] = acc;
     }
-    return out;
 }
 
-/* One SSP-RK3 step in place with the positivity limiter after every stage
+/* The scheme of a configuration on the scalar linear test equation du/dt = lambda u,
+ * with the same stage arithmetic as orc_rk_step (used to pin the coefficients). */
+double orc_rk_linear(const orc_cfg *cfg, double lambda, double dt, double u0)
+{
+    const rk_scheme *R = scheme_of(cfg);
+    double xs[RK_SMAX + 1], ls[RK_SMAX + 1];
+    double *X[RK_SMAX + 1], *LX[RK_SMAX + 1];
+    for (int j = 0; j <= RK_SMAX; ++j) { X[j] = &xs[j]; LX[j] = &ls[j]; }
+    xs[0] = u0;
+    for (int i = 1; i <= R->stages; ++i) {
+        ls[i - 1] = lambda * xs[i - 1];
+        stage_combination(R, i, 1, dt, X, LX, &xs[i]);
+    }
+    return xs[R->stages];
+}
+
+/* Number of right-hand-side evaluations per step of a configuration. */
+int orc_rk_stages(const orc_cfg *cfg) { return scheme_of(cfg)->stages; }
+
+/* One Runge-Kutta step in place with the positivity limiter after every stage
  * (Sec. 3.1: positivity checked in all intermediate Runge-Kutta steps; dt too large
  * when a flat cell cannot be fixed).  Returns ORC_RETRY with u restored to u^n when
  * any cell mean fell to or below the floor. */
@@ -731,24 +806,24 @@ int orc_rk_step(const orc_cfg *cfg, double *u, double dt, const double *modes, i
                 const double *nu, const int *fallback)
 {
     if (check_cfg(cfg)) return ORC_EINVAL;
+    const rk_scheme *R = scheme_of(cfg);
     int nb = orc_nbasis(cfg->k);
     long n = (long)NV * nb * ncell_of(cfg);
-    double *un = malloc(sizeof(double) * n);
-    double *ui = malloc(sizeof(double) * n);
-    double *L = malloc(sizeof(double) * n);
-    memcpy(un, u, sizeof(double) * n);
-    memcpy(ui, u, sizeof(double) * n);
+    double *X[RK_SMAX + 1], *LX[RK_SMAX];
+    for (int j = 0; j <= R->stages; ++j) X[j] = malloc(sizeof(double) * n);
+    for (int j = 0; j < R->stages; ++j) LX[j] = malloc(sizeof(double) * n);
+    memcpy(X[0], u, sizeof(double) * n);
     int status = ORC_OK;
-    for (int s = 0; s < 3; ++s) {
-        orc_rhs(cfg, ui, L, dt, modes, nmodes, nu, fallback);
-        combine(n, RK_A[s], un, RK_B[s], ui, dt, L, ui);
+    for (int i = 1; i <= R->stages; ++i) {
+        orc_rhs(cfg, X[i - 1], LX[i - 1], dt, modes, nmodes, nu, fallback);
+        stage_combination(R, i, n, dt, X, LX, X[i]);
         if (cfg->flags & ORC_POS_LIMITER) {
-            if (orc_limit(cfg, ui, NULL) > 0) { status = ORC_RETRY; break; }
+            if (orc_limit(cfg, X[i], NULL) > 0) { status = ORC_RETRY; break; }
         }
     }
-    if (status == ORC_OK) memcpy(u, ui, sizeof(double) * n);
-    else memcpy(u, un, sizeof(double) * n);
-    free(un); free(ui); free(L);
+    if (status == ORC_OK) memcpy(u, X[R->stages], sizeof(double) * n);
+    for (int j = 0; j <= R->stages; ++j) free(X[j]);
+    for (int j = 0; j < R->stages; ++j) free(LX[j]);
     return status;
 }
 

@@ -172,6 +172,8 @@ static void layout(dg_ctx *c, size_t *total)
     c->off.un_copy = o; o += state;
     c->off.stA = o; o += state;
     c->off.stB = o; o += state;
+    // a third stage buffer for the five-stage scheme (degree 3 with DG_RK_BY_ORDER)
+    c->off.stC = o; o += ((c->cfg.flags & DG_RK_BY_ORDER) && c->k == 3) ? state : 0;
     c->off.L = o; o += state;
     c->off.vh0 = o; o += vh;
     c->off.vh1 = o; o += vh;
@@ -219,6 +221,9 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
     if (!(cfg->cs > 0.0) || !(cfg->cfl > 0.0) || cfg->alpha_visc < 0.0 || cfg->beta_visc < 0.0 ||
         !(cfg->rho_floor >= 0.0) || !(cfg->rho_floor_rel >= 0.0) || !(cfg->rho_floor_rel < 1.0))
         return DG_EINVAL;
+    const int known = DG_AV | DG_PRIM_PROJ | DG_FORCING | DG_POS_LIMITER | DG_LEARNED_SENSOR | DG_FORCE_MEANFREE |
+                      DG_HLLC | DG_RK_BY_ORDER;
+    if (cfg->flags & ~known) return DG_EINVAL;
     if ((cfg->flags & DG_LEARNED_SENSOR) && cfg->degree != 2) return DG_EUNSUPPORTED;
     {
         // each [var] block of nb mode planes is addressed through one buffer descriptor
@@ -473,7 +478,8 @@ static int launch_abar(dg_ctx *c)
 
 template <typename T, int K>
 static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
-                        void *un_copy, double ca, double cb, double dt, long long *nlim, double *part = nullptr)
+                        void *un_copy, const double (&coef)[3], double dt, long long *nlim, double *part = nullptr,
+                        void *w = nullptr, const double (&wcoef)[3] = {0.0, 0.0, 0.0})
 {
     StageArgs a;
     a.ui = ui;
@@ -490,8 +496,14 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.pa = proj_args(c);
     a.g = Mesh{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
     a.flags = c->cfg.flags;
-    a.ca = ca;
-    a.cb = cb;
+    a.ca = coef[0];
+    a.cb = coef[1];
+    a.cc = coef[2];
+    a.w_src = w;
+    a.w_out = w;
+    a.wa = wcoef[0];
+    a.wb = wcoef[1];
+    a.wc = wcoef[2];
     a.dt = dt;
     a.rho_floor = c->cfg.rho_floor;
     a.rho_floor_rel = c->cfg.rho_floor_rel;
@@ -529,16 +541,55 @@ static int launch_dt_final(dg_ctx *c, double *dst)
     return DG_OK;
 }
 
-// One SSP-RK3 step.  reuse: start from the projection kept by the previous step of this
-// context (when it is still valid); dt_next: also compute the time step of the new state
-// in the last stage (its projection is then kept in vh0).
+// SSP Runge-Kutta schemes in the compact Shu-Osher form the stage kernel evaluates:
+// stage s reads buffer `in` (u^(s)) and buffer `un` (u^n or an earlier side combination)
+// and writes out = a un + b in + c dt R(in); a stage may also write the side combination
+// w = wa w + wb in + wc dt R(in) into buffer `w` in place.  Buffers: 0 = the state array
+// (u^n until the last stage writes u^(n+1)), 1..3 = workspace stage buffers.
+struct StageSpec {
+    int in, un, out;
+    double coef[3];
+    int w;
+    double wcoef[3];
+};
+struct Scheme {
+    int stages;
+    StageSpec s[5];
+};
+// two stages, second order (Heun)
+static const Scheme SSPRK2 = {2, {{0, 0, 1, {0.0, 1.0, 1.0}, 0, {}}, {1, 0, 0, {0.5, 0.5, 0.5}, 0, {}}}};
+// three stages, third order (Shu & Osher)
+static const Scheme SSPRK3 = {3,
+                              {{0, 0, 1, {0.0, 1.0, 1.0}, 0, {}},
+                               {1, 0, 2, {0.75, 0.25, 0.25}, 0, {}},
+                               {2, 0, 0, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}, 0, {}}}};
+// five stages, fourth order (Spiteri & Ruuth 2002); its last stage combines u^(2), u^(3),
+// L(u^(3)), u^(4), L(u^(4)): the first three are folded into a side combination by the
+// fourth stage, written over u^(2)
+static const Scheme SSPRK54 = {
+    5,
+    {{0, 0, 1, {0.0, 1.0, 0.391752226571890}, 0, {}},
+     {1, 0, 2, {0.444370493651235, 0.555629506348765, 0.368410593050371}, 0, {}},
+     {2, 0, 1, {0.620101851488403, 0.379898148511597, 0.251891774271694}, 0, {}},
+     {1, 0, 3, {0.178079954393132, 0.821920045606868, 0.544974750228521}, 2,
+      {0.517231671970585, 0.096059710526147, 0.063692468666290}},
+     {3, 2, 0, {1.0, 0.386708617503269, 0.226007483236906}, 0, {}}}};
+
+static const Scheme &scheme_of(const dg_ctx *c)
+{
+    if (!(c->cfg.flags & DG_RK_BY_ORDER)) return SSPRK3;
+    return c->k == 1 ? SSPRK2 : (c->k == 2 ? SSPRK3 : SSPRK54);
+}
+
+// One Runge-Kutta step.  reuse: start from the projection kept by the previous step of
+// this context (when it is still valid); dt_next: also compute the time step of the new
+// state in the last stage (its projection is then kept in vh0).
 template <typename T, int K>
 static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, double *dt_next)
 {
-    static const double CA[3] = {0.0, 0.75, 1.0 / 3.0};
-    static const double CB[3] = {1.0, 0.25, 2.0 / 3.0};
+    const Scheme &S = scheme_of(c);
     void *vh[2] = {c->wp(c->off.vh0), c->wp(c->off.vh1)};
-    void *st[3] = {c->wp(c->off.stA), c->wp(c->off.stB), u};
+    void *buf[4] = {u, c->wp(c->off.stA), c->wp(c->off.stB), c->wp(c->off.stC)};
     const bool cached = reuse && c->vh_cache_u == u && c->vh_cache_gen == c->gen;
     c->gen++;
     c->vh_cache_u = nullptr;
@@ -547,20 +598,21 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
         rc = launch_project<T, K>(c, u, vh[0], nullptr, c->fail());
         if (rc) return rc;
     }
-    const void *ui = u;
-    for (int s = 0; s < 3; ++s) {
-        rc = launch_rhs<T, K>(c, ui, vh[s & 1], c->wp(c->off.L), dt, (s == 0 && cached) ? c->fail() : nullptr);
+    for (int s = 0; s < S.stages; ++s) {
+        const StageSpec &g = S.s[s];
+        const bool last = s == S.stages - 1;
+        rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], c->wp(c->off.L), dt, (s == 0 && cached) ? c->fail() : nullptr);
         if (rc) return rc;
         if (use_meanfree(c)) {
             rc = launch_abar(c);
             if (rc) return rc;
         }
-        void *vnext = s < 2 ? vh[(s + 1) & 1] : (dt_next ? vh[0] : nullptr);
-        double *part = (s == 2 && dt_next) ? (double *)c->wp(c->off.part) : nullptr;
-        rc = launch_stage<T, K>(c, ui, u, c->wp(c->off.L), st[s], vnext, s == 0 ? c->wp(c->off.un_copy) : nullptr,
-                                CA[s], CB[s], dt, nullptr, part);
+        void *vnext = !last ? vh[(s + 1) & 1] : (dt_next ? vh[0] : nullptr);
+        double *part = (last && dt_next) ? (double *)c->wp(c->off.part) : nullptr;
+        rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext,
+                                s == 0 ? c->wp(c->off.un_copy) : nullptr, g.coef, dt, nullptr, part,
+                                g.w ? buf[g.w] : nullptr, g.wcoef);
         if (rc) return rc;
-        ui = st[s];
     }
     if (dt_next) {
         rc = launch_dt_final<T, K>(c, c->scal() + 8);
@@ -682,7 +734,8 @@ static int do_limit(dg_ctx *c, void *u, long *nfail)
     std::memset(c->pinned + 8, 0, 16);
     HIPCHK(c, hipMemcpyAsync(cnt, c->pinned + 8, 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(fl, c->pinned + 8, 4, hipMemcpyHostToDevice, c->stream));
-    int rc = launch_stage<T, K>(c, u, u, nullptr, u, nullptr, nullptr, 0.0, 1.0, 0.0, cnt);
+    static const double plain[3] = {0.0, 1.0, 0.0};
+    int rc = launch_stage<T, K>(c, u, u, nullptr, u, nullptr, nullptr, plain, 0.0, cnt);
     if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(c->pinned, cnt, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -8,7 +8,7 @@
 #include "dg.h"
 
 struct dg_offsets {
-    size_t un_copy, stA, stB, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, scal, iflags;
+    size_t un_copy, stA, stB, stC, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, scal, iflags;
 };
 
 struct dg_ctx {

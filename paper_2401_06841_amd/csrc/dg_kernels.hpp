@@ -15,7 +15,7 @@
 
 namespace dg {
 
-enum : int { F_AV = 1, F_PRIM = 2, F_FORCE = 4, F_LIMIT = 8, F_LEARNED = 16, F_MEANFREE = 32 };
+enum : int { F_AV = 1, F_PRIM = 2, F_FORCE = 4, F_LIMIT = 8, F_LEARNED = 16, F_MEANFREE = 32, F_HLLC = 64 };
 
 constexpr int BLOCK = 256;
 
@@ -211,7 +211,7 @@ struct ProjArgs {
 
 struct StageArgs {
     const void *ui;         // stage input u^(i)
-    const void *un;         // u^n (may alias ui for stage 1)
+    const void *un;         // u^n, or the side combination of an earlier stage (may alias ui)
     const void *L;          // right-hand side of u^(i) (NULL: plain copy/limit of ui)
     void *out;              // u^(i+1) (may alias un)
     void *vh_out;           // projection of u^(i+1) for the next stage, or NULL
@@ -221,10 +221,13 @@ struct StageArgs {
     int *fail;              // positivity failure flag
     long long *nlim;        // count of failing cells (may be NULL)
     double *part;           // with vh_out: per-block time-step maxima of u^(i+1), or NULL
+    const void *w_src;      // side combination w = wa w_src + wb ui + wc dt R (w_out may alias w_src)
+    void *w_out;            //   written when not NULL
     ProjArgs pa;
     Mesh g;
     int flags;
-    double ca, cb, dt, rho_floor, rho_floor_rel;
+    double ca, cb, cc, dt, rho_floor, rho_floor_rel;
+    double wa, wb, wc;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -335,6 +338,32 @@ __device__ __forceinline__ void rusanov(T cs, T cs2, const T (&uL)[4], const T (
     F[1 + D] += T(0.5) * cs2 * (uL[0] + uR[0]);
 }
 
+// isothermal HLLC-type flux across a face with normal +e_D (the counterpart of the HLLC
+// solver of Sec. 2.2 for isothermal gas): wave speeds S_L = min(v_L, v_R) - cs and
+// S_R = max(v_L, v_R) + cs of the normal velocities; density and normal momentum take the
+// HLL flux, each tangential momentum is the mass flux times the upwind tangential velocity
+template <int D, typename T>
+__device__ __forceinline__ void hllc(T cs, T cs2, const T (&uL)[4], const T (&vL)[3], const T (&uR)[4],
+                                     const T (&vR)[3], T (&F)[4])
+{
+    const T SL = fmin(vL[D], vR[D]) - cs;
+    const T SR = fmax(vL[D], vR[D]) + cs;
+    const T FL0 = uL[1 + D], FR0 = uR[1 + D];
+    const T FLn = uL[1 + D] * vL[D] + cs2 * uL[0];
+    const T FRn = uR[1 + D] * vR[D] + cs2 * uR[0];
+    const T iw = rcp(SR - SL);
+    const T sLR = SL * SR;
+    T F0 = (SR * FL0 - SL * FR0 + sLR * (uR[0] - uL[0])) * iw;
+    T Fn = (SR * FLn - SL * FRn + sLR * (uR[1 + D] - uL[1 + D])) * iw;
+    F0 = SL >= T(0) ? FL0 : (SR <= T(0) ? FR0 : F0);
+    Fn = SL >= T(0) ? FLn : (SR <= T(0) ? FRn : Fn);
+    F[0] = F0;
+    F[1 + D] = Fn;
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+        if (t != D) F[1 + t] = F0 * (F0 >= T(0) ? vL[t] : vR[t]);
+}
+
 // von Neumann-Richtmyer viscous pressure at one point (Sec. 3.1)
 template <typename T>
 __device__ __forceinline__ T vnr_pi(T rho, T divv, T hp, T alpha, T beta, T cs, T inv_dt)
@@ -350,7 +379,8 @@ __device__ __forceinline__ T vnr_pi(T rho, T divv, T hp, T alpha, T beta, T cs, 
 // Surface integral of one face (normal axis D, side s: 0 = low, 1 = high) lifted into L.
 template <typename T, int K, int D>
 __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsigned bn, int s,
-                                     ctab<T> *tab, bool prim, T cs, T cs2, T (&L)[4][Shape<K>::NB])
+                                     ctab<T> *tab, bool prim, bool use_hllc, T cs, T cs2,
+                                     T (&L)[4][Shape<K>::NB])
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -406,8 +436,13 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
             }
         }
         T F[4];
-        if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
-        else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
+        if (use_hllc) {
+            if (s) hllc<D>(cs, cs2, uo, vo, un, vn, F);
+            else   hllc<D>(cs, cs2, un, vn, uo, vo, F);
+        } else {
+            if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
+            else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
+        }
         const T wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];   // outward normal
         ctab<T> *pl = plift + r * S::NB;
 #pragma unroll
@@ -449,6 +484,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const bool av = a.flags & F_AV;
     const bool prim = a.flags & F_PRIM;
     const bool force = a.flags & F_FORCE;
+    const bool use_hllc = a.flags & F_HLLC;
     const T cs = (T)a.cs, cs2 = (T)(a.cs * a.cs);
     const T hp = (T)(a.h / (K + 1));
     // dt <= 0: no Pi_max cap (a huge finite factor keeps 0 * cap = 0)
@@ -580,13 +616,13 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const Field<T, 4> SRC = prim ? Field<T, 4>(a.u, a.vh, NB, nc) : U;
 #pragma unroll 1
     for (int s = 0; s < 2; ++s)
-        face<T, K, 0>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * sizeof(T), s, tab, prim, cs, cs2, L);
+        face<T, K, 0>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L);
 #pragma unroll 1
     for (int s = 0; s < 2; ++s)
-        face<T, K, 1>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * sizeof(T), s, tab, prim, cs, cs2, L);
+        face<T, K, 1>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L);
 #pragma unroll 1
     for (int s = 0; s < 2; ++s)
-        face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, cs, cs2, L);
+        face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L);
 
     const T inv4h = (T)(0.25 / a.h);
     if (active) {
@@ -707,9 +743,11 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
 }
 
 // --------------------------------------------------------------- stage kernel
-// out = ca*un + cb*(ui + dt*(L - abar W_rho)) (Shu-Osher SSP-RK3 stage), then the
-// positivity limiter (Sec. 3.1; target minimum max(floor, rel * mean)) with FP64
-// comparisons, then the projected velocity of the result for the next stage.
+// out = ca*un + cb*ui + cc*dt*R with R = L - abar W_rho (one stage of an SSP Runge-Kutta
+// scheme in Shu-Osher form), optionally a side combination w = wa*w_src + wb*ui + wc*dt*R
+// of the same operands, then the positivity limiter (Sec. 3.1; target minimum
+// max(floor, rel * mean)) with FP64 comparisons, then the projected velocity of the
+// result for the next stage.
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
 {
@@ -732,18 +770,28 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
     if (a.L) {
         const Field<T, 4> LF(a.L, NB, nc);
         const Field<T, 4> UN(a.un, NB, nc);
-        const T ca = (T)a.ca, cb = (T)a.cb, dt = (T)a.dt;
+        const T ca = (T)a.ca, cb = (T)a.cb, cdt = (T)(a.cc * a.dt);
         T ab[3] = {T(0), T(0), T(0)};
         if (a.abar) { ab[0] = (T)a.abar[0]; ab[1] = (T)a.abar[1]; ab[2] = (T)a.abar[2]; }
         const bool use_un = a.ca != 0.0;
+        const bool side = a.w_out != nullptr;
+        const Field<T, 4> WS(side ? a.w_src : a.ui, NB, nc);
+        const Field<T, 4> WO(side ? a.w_out : a.ui, NB, nc);
+        const T wa = (T)a.wa, wb = (T)a.wb, wcdt = (T)(a.wc * a.dt);
+        // momentum first: the removed mean acceleration multiplies the input density
 #pragma unroll
         for (int v = 3; v >= 0; --v)
 #pragma unroll
             for (int l = 0; l < NB; ++l) {
                 T rhs = LF.get(v, l, bo);
                 if (v > 0) rhs -= ab[v - 1] * U[0][l];
-                const T x = U[v][l] + dt * rhs;
-                U[v][l] = use_un ? ca * UN.get(v, l, bo) + cb * x : cb * x;
+                const T ui = U[v][l];
+                if (side) {
+                    const T w = wa * WS.get(v, l, bo) + wb * ui + wcdt * rhs;
+                    if (active) WO.put(v, l, bo, w);
+                }
+                const T x = cb * ui + cdt * rhs;
+                U[v][l] = use_un ? ca * UN.get(v, l, bo) + x : x;
             }
     }
     if (a.flags & F_LIMIT) {

@@ -235,3 +235,101 @@ def test_c2_full_size_sampled(precision):
     scale = np.linalg.norm(u[:, :, cells].transpose(2, 0, 1).reshape(len(cells), 4, -1), axis=2)
     err = np.linalg.norm(dt * (g - ref), axis=2) / np.maximum(scale, 1e-30)
     assert err.max() < (1e-12 if precision == dg.DG_FP64 else 1e-5), err.max()
+
+
+# ------------------------------------------------------- HLLC-type interface flux
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("flags", [ALL | dg.DG_HLLC, dg.DG_POS_LIMITER | dg.DG_HLLC, FORCE | dg.DG_HLLC])
+def test_rhs_hllc(k, flags, precision):
+    print(f"rhs hllc k={k} flags={flags} p={precision}", flush=True)
+    modes = synthetic.forcing_table(4, amp=5.0) if flags & dg.DG_FORCING else None
+    e, got, ref, _ = _rhs_case(12, 10, 9, k, flags, precision, seed=40 + k, modes=modes)
+    assert max(e) < TOL[precision], e
+
+
+def test_rk_steps_hllc():
+    n, k = 8, 2
+    flags = FORCE | dg.DG_HLLC
+    modes = synthetic.forcing_table(6, amp=5.0)
+    u = synthetic.turbulent_like(n, n, n, k, mach=3.0, seed=17)
+    ocfg = _orc_cfg(n, n, n, k, flags)
+    ctx = make(n, n, n, k, flags)
+    dg.dg_set_forcing(ctx, modes)
+    ud = dev(u, ctx)
+    for _ in range(5):
+        dt = oracle.dt_max(ocfg, u)
+        u, st = oracle.rk_step(ocfg, u, dt, modes)
+        assert st == oracle.OK
+        assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_OK
+    e = field_rel(host(ud), u, u)
+    assert max(e) < TOL[dg.DG_FP64], e
+
+
+def test_stationary_shear_layer_is_steady_with_hllc():
+    n, k = 6, 2
+    ocfg = oracle.Cfg(n, n, 1, k)
+
+    def state(x):
+        out = np.zeros((4,) + x.shape[:-1])
+        out[0] = 1.3
+        out[2] = 1.3 * np.where(x[..., 0] < 0.5, 0.7, -0.4)
+        return out
+
+    u = oracle.project_function(ocfg, state)
+    for flags, steady in ((dg.DG_POS_LIMITER | dg.DG_HLLC, True), (dg.DG_POS_LIMITER, False)):
+        ctx = make(n, n, 1, k, flags)
+        ud = dev(u, ctx)
+        out = torch.empty_like(ud)
+        dg.dg_rhs(ctx, ud, out, 1e-3)
+        L = host(out)
+        assert (np.abs(L).max() < 1e-12) == steady
+
+
+# ----------------------------------------------- Runge-Kutta scheme chosen by degree
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_rk_by_order_steps(k, precision):
+    """Two stages at degree 1, three at 2, five (fourth order) at 3, against the oracle's
+    plain Shu-Osher sums; with driving, mean removal, viscosity and the limiter."""
+    print(f"rk by order k={k} p={precision}", flush=True)
+    n = 8
+    flags = FORCE | dg.DG_RK_BY_ORDER
+    modes = synthetic.forcing_table(9, amp=5.0)
+    u = synthetic.turbulent_like(n, n, n, k, mach=3.0, seed=23 + k)
+    if precision == dg.DG_FP32:
+        u = u.astype(np.float32).astype(np.float64)
+    ocfg = _orc_cfg(n, n, n, k, flags)
+    ctx = make(n, n, n, k, flags, precision)
+    dg.dg_set_forcing(ctx, modes)
+    ud = dev(u, ctx)
+    u0 = u.copy()
+    for i in range(4):
+        dt = oracle.dt_max(ocfg, u)
+        u, st = oracle.rk_step(ocfg, u, dt, modes)
+        assert st == oracle.OK
+        if i % 2 == 0:
+            assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_OK
+        else:
+            rc, _ = dg.dg_rk_step_next(ctx, ud, dt, False)
+            assert rc == dg.DG_OK
+    e = field_rel(host(ud), u, u)
+    assert max(e) < TOL[precision], e
+    # the scheme really differs from the default three-stage one at degrees 1 and 3
+    if k != 2:
+        ref3 = u0.copy()
+        o3 = _orc_cfg(n, n, n, k, FORCE)
+        for _ in range(4):
+            ref3, _ = oracle.rk_step(o3, ref3, oracle.dt_max(o3, ref3), modes)
+        assert max(field_rel(u, ref3, u)) > 1e-9
+
+
+def test_rk_by_order_retry_restores_state():
+    k = 3
+    ctx = make(4, 3, 2, k, dg.DG_POS_LIMITER | dg.DG_RK_BY_ORDER)
+    u = np.zeros((4, ctx.cfg.nb, ctx.cfg.ncell))
+    u[0, 0] = 5e-4
+    u[1, 0] = 2e-4
+    ud = dev(u, ctx)
+    assert dg.dg_rk_step(ctx, ud, 1e-3) == dg.DG_RETRY
+    assert np.array_equal(host(ud), u)

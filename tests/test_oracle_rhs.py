@@ -271,10 +271,37 @@ def test_dt_viscous_bound_closed_form(k, gamma):
 
 
 def test_ssprk3_stability_polynomial():
+    cfg = oracle.Cfg(4, 4, 4, 2)
+    assert oracle.rk_stages(cfg) == 3
+    for k in (1, 2, 3):                              # third order for every degree by default
+        assert oracle.rk_stages(oracle.Cfg(4, 4, 4, k)) == 3
     for lam in [-1.0, -7.3, 2.1, 0.0]:
         for dt in [0.01, 0.2, 0.4]:
             z = lam * dt
-            assert abs(oracle.ssprk3_linear(lam, dt, 1.3) - 1.3 * (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-14
+            assert abs(oracle.rk_linear(cfg, lam, dt, 1.3) - 1.3 * (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-14
+
+
+def test_rk_by_order_stability_polynomials():
+    """With the per-order choice (k+1 evaluations per step, Sec. 7): degree 1 uses a
+    two-stage scheme whose amplification factor is exactly 1 + z + z^2/2; degree 3 a
+    five-stage scheme of order four, so its factor agrees with exp(z) up to z^4 and the
+    remainder scales as z^5 (and is not zero: five stages cannot match exp(z) exactly)."""
+    c1 = oracle.Cfg(4, 4, 4, 1, flags=oracle.RK_BY_ORDER)
+    c2 = oracle.Cfg(4, 4, 4, 2, flags=oracle.RK_BY_ORDER)
+    c3 = oracle.Cfg(4, 4, 4, 3, flags=oracle.RK_BY_ORDER)
+    assert [oracle.rk_stages(c) for c in (c1, c2, c3)] == [2, 3, 5]
+    for z in [-0.9, -0.3, 0.05, 0.7]:
+        assert abs(oracle.rk_linear(c1, z, 1.0, 2.0) - 2.0 * (1 + z + z * z / 2)) < 1e-14
+        assert abs(oracle.rk_linear(c2, z, 1.0, 2.0) - 2.0 * (1 + z + z * z / 2 + z ** 3 / 6)) < 1e-14
+
+    def rem(z):
+        taylor4 = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+        return oracle.rk_linear(c3, z, 1.0, 1.0) - taylor4
+
+    for z in [0.02, -0.02, 0.05]:
+        ratio = rem(2 * z) / rem(z)
+        assert abs(ratio - 32.0) < 0.5, (z, ratio)           # remainder ~ c z^5
+    assert 1e-5 < abs(rem(0.05) / 0.05 ** 5) < 0.01
 
 
 # -------------------------------------------------------------------- limiter
