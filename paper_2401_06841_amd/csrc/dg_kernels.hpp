@@ -377,10 +377,12 @@ __device__ __forceinline__ T vnr_pi(T rho, T divv, T hp, T alpha, T beta, T cs, 
 
 // ---------------------------------------------------------------- face pass
 // Surface integral of one face (normal axis D, side s: 0 = low, 1 = high) lifted into L.
+// With share != nullptr the physical flux at every face point is also stored for the
+// neighbour across the face: share[(r * 4 + v) * BLOCK + threadIdx.x].
 template <typename T, int K, int D>
 __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsigned bn, int s,
                                      ctab<T> *tab, bool prim, bool use_hllc, T cs, T cs2,
-                                     T (&L)[4][Shape<K>::NB])
+                                     T (&L)[4][Shape<K>::NB], T *share = nullptr)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -443,11 +445,36 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
             if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
             else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
         }
+        if (share)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) share[(r * 4 + v) * BLOCK + threadIdx.x] = F[v];
         const T wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];   // outward normal
         ctab<T> *pl = plift + r * S::NB;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const T g = wr * F[v];
+#pragma unroll
+            for (int l = 0; l < S::NB; ++l) L[v][l] += g * pl[l];
+        }
+    }
+}
+
+// Surface integral of the high face (normal axis D) from the point fluxes the neighbour
+// across it stored in its low-face pass (slot = the neighbour's thread in this block): the
+// same flux values this cell would compute, lifted with the outward normal +e_D.
+template <typename T, int K, int D>
+__device__ __forceinline__ void face_shared(const T *share, int slot, ctab<T> *tab, T (&L)[4][Shape<K>::NB])
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    ctab<T> *plift = tab + TL::PLIFT + (D * 2 + 1) * S::NF * S::NB;
+#pragma unroll 1
+    for (int r = 0; r < S::NF; ++r) {
+        const T wr = -tab[TL::FW + r];
+        ctab<T> *pl = plift + r * S::NB;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T g = wr * share[(r * 4 + v) * BLOCK + slot];
 #pragma unroll
             for (int l = 0; l < S::NB; ++l) L[v][l] += g * pl[l];
         }
@@ -473,6 +500,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     constexpr Modes<K> M = make_modes<K>();
     constexpr int NB = S::NB, ND = S::ND;
     __shared__ double lds[4 * 4];
+    __shared__ T fsh[S::NF * 4 * BLOCK];        // point fluxes of the low faces, [r][v][thread]
     ctab<T> *tab = as_tab<T>(a.tab);
     const int nc = a.g.nc;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -614,12 +642,27 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     int nbr[6], ijk[3];
     neighbours(a.g, c, nbr, ijk);
     const Field<T, 4> SRC = prim ? Field<T, 4>(a.u, a.vh, NB, nc) : U;
+    // Each face flux is needed by both cells.  Every cell computes its low x and y faces
+    // and leaves the point fluxes in LDS; a wave whose high-side neighbours all belong to
+    // this block (whole x lines per block, and y lines of the block but the last) lifts
+    // those instead of recomputing the face.  The decision is a wave vote, so the branch
+    // is uniform; the stored values are exactly those the cell would compute itself.
+    const int base = blk * BLOCK;
+    const bool xsh = __all((unsigned)(nbr[1] - base) < (unsigned)BLOCK);
+    const bool ysh = __all((unsigned)(nbr[3] - base) < (unsigned)BLOCK);
 #pragma unroll 1
-    for (int s = 0; s < 2; ++s)
-        face<T, K, 0>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L);
+    for (int s = 0; s < (xsh ? 1 : 2); ++s)
+        face<T, K, 0>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L,
+                      s == 0 ? fsh : nullptr);
+    __syncthreads();
+    if (xsh) face_shared<T, K, 0>(fsh, nbr[1] - base, tab, L);
+    __syncthreads();                // the y pass overwrites the stored fluxes
 #pragma unroll 1
-    for (int s = 0; s < 2; ++s)
-        face<T, K, 1>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L);
+    for (int s = 0; s < (ysh ? 1 : 2); ++s)
+        face<T, K, 1>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L,
+                      s == 0 ? fsh : nullptr);
+    __syncthreads();
+    if (ysh) face_shared<T, K, 1>(fsh, nbr[3] - base, tab, L);
 #pragma unroll 1
     for (int s = 0; s < 2; ++s)
         face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L);
