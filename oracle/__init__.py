@@ -90,6 +90,17 @@ def lib():
         L.orc_l1_error.argtypes = [cp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.orc_sensor_features.argtypes = [cp, dp, dp]
         L.orc_sensor_labels.argtypes = [cp, dp, dp]
+        u64 = ctypes.c_uint64
+        L.orc_splitmix64.argtypes = [u64, u64]
+        L.orc_splitmix64.restype = u64
+        L.orc_sf_bins.argtypes = [cp, ctypes.c_int, dp]
+        L.orc_sf_pair.argtypes = [cp, u64, u64, ctypes.c_double, dp, dp]
+        L.orc_sf_pair.restype = None
+        L.orc_velocity_at.argtypes = [cp, dp, dp, dp]
+        L.orc_velocity_at.restype = None
+        L.orc_structure_function.argtypes = [cp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, ctypes.c_long,
+                                             u64, dp]
+        L.orc_velocity_grid.argtypes = [cp, dp, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -358,6 +369,74 @@ def sensor_labels(cfg: Cfg, u):
     out = np.zeros(cfg.ncell)
     _check(lib().orc_sensor_labels(cfg.c(), _d(_f64(u)), _d(out)))
     return out
+
+
+# ------------------------------------------------------------- flow statistics
+# Sec. 4.3: velocity structure function S2(l) = <|v(x) - v(x + l n)|^2>, v(l) = sqrt(S2/2),
+# and the velocity power spectrum on the N p grid (the readings are listed in orc.c).
+
+def splitmix64(seed: int, i: int) -> int:
+    """Draw i of the counter-based SplitMix64 stream `seed` (64-bit unsigned)."""
+    return int(lib().orc_splitmix64(seed & (2 ** 64 - 1), i & (2 ** 64 - 1)))
+
+
+def sf_bins(cfg: Cfg, nbins: int):
+    out = np.zeros(nbins)
+    _check(lib().orc_sf_bins(cfg.c(), nbins, _d(out)))
+    return out
+
+
+def sf_pair(cfg: Cfg, seed: int, pair: int, l: float):
+    x1, x2 = np.zeros(3), np.zeros(3)
+    lib().orc_sf_pair(cfg.c(), seed, pair, float(l), _d(x1), _d(x2))
+    return x1, x2
+
+
+def velocity_at(cfg: Cfg, u, x):
+    u = _f64(u)
+    x = _f64(x)
+    v = np.zeros(3)
+    lib().orc_velocity_at(cfg.c(), _d(u), _d(x), _d(v))
+    return v
+
+
+def structure_function(cfg: Cfg, u, nbins: int, npairs: int, seed: int, b0: int = 0, nsel: int = None):
+    """S2 of bins b0 .. b0+nsel-1 (default all) of an nbins-bin measurement."""
+    nsel = nbins - b0 if nsel is None else nsel
+    l = sf_bins(cfg, nbins)
+    out = np.zeros(nsel)
+    _check(lib().orc_structure_function(cfg.c(), _d(_f64(u)), nbins, b0, nsel, _d(l), npairs, seed, _d(out)))
+    return out
+
+
+def velocity_grid(cfg: Cfg, u, p: int):
+    out = np.zeros((3, cfg.nz * p, cfg.ny * p, cfg.nx * p))
+    _check(lib().orc_velocity_grid(cfg.c(), _d(_f64(u)), p, _d(out)))
+    return out
+
+
+def power_spectrum(grid):
+    """Shell sums of 1/2 |v_hat|^2 with v_hat = FFT(v) / (number of points) over integer
+    shells |kappa| in [K - 1/2, K + 1/2) (kappa in box wavenumber units); index K of the
+    result; sum over K = 1/2 <|v|^2>."""
+    grid = np.asarray(grid, dtype=np.float64)
+    Z, Y, X = grid.shape[1:]
+    vh = np.fft.fftn(grid, axes=(1, 2, 3)) / (X * Y * Z)
+    e = 0.5 * (np.abs(vh) ** 2).sum(0)
+    fz = np.fft.fftfreq(Z, 1.0 / Z)[:, None, None]
+    fy = np.fft.fftfreq(Y, 1.0 / Y)[None, :, None]
+    fx = np.fft.fftfreq(X, 1.0 / X)[None, None, :]
+    shell = np.floor(np.sqrt(fx ** 2 + fy ** 2 + fz ** 2) + 0.5).astype(np.int64)
+    return np.bincount(shell.reshape(-1), weights=e.reshape(-1), minlength=spectrum_nshell(X, Y, Z))
+
+
+def spectrum_nshell(X: int, Y: int, Z: int) -> int:
+    """Number of integer shells K = 0 .. Kmax of an X x Y x Z grid."""
+    return int(np.floor(np.sqrt((X // 2) ** 2 + (Y // 2) ** 2 + (Z // 2) ** 2) + 0.5)) + 1
+
+
+def velocity_spectrum(cfg: Cfg, u, p: int):
+    return power_spectrum(velocity_grid(cfg, u, p))
 
 
 def _check(rc):

@@ -1037,3 +1037,158 @@ int orc_sensor_labels(const orc_cfg *cfg, const double *u, double *nu)
     free(T);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------ flow statistics
+ * Velocity structure function and the velocity grid for power spectra (Sec. 4.3, the
+ * definition of the scale-dependent velocity v(l), and the subsection on measuring
+ * structure functions and power spectra).
+ *
+ * Random numbers: the counter-based SplitMix64 generator (Steele, Lea & Flood 2014):
+ * draw i of stream `seed` is the SplitMix64 output for the state seed + (i+1) gamma,
+ * gamma = 0x9E3779B97F4A7C15, and a uniform double in [0,1) is its top 53 bits times
+ * 2^-53.  Pair j of bin b owns the draws 256 (b npairs + j) + t, t < 256.
+ *
+ * Readings (the paper gives the recipe in words):
+ *   - bins: nbins log-spaced bins between the resolution limit h/(k+1) and half the
+ *     shortest box side; the distance of bin b is the geometric centre
+ *     lmin (lmax/lmin)^((b + 1/2)/nbins);
+ *   - first point uniform in the box (draws t = 0, 1, 2); direction uniform on the unit
+ *     sphere by rejection from the cube [-1,1]^3 (attempt a uses draws 3 + 3a + 0..2,
+ *     accepted when 1e-12 < r^2 <= 1, at most 84 attempts, else +z); second point
+ *     x + l n (one fused multiply-add per axis), wrapped into the periodic box;
+ *   - velocity v = m / max(rho, rho_floor) from the expansions of the cell that holds the
+ *     point (positivity is only enforced at the Gauss points), cell index floor(x/h)
+ *     clamped to the mesh;
+ *   - S2(l) = mean over the pairs of |v(x) - v(x + l n)|^2; v(l) = sqrt(S2 / 2).
+ */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static double uniform01(uint64_t seed, uint64_t i)
+{
+    return (double)(orc_splitmix64(seed, i) >> 11) * 0x1.0p-53;
+}
+
+static void box_of(const orc_cfg *cfg, double L[3])
+{
+    L[0] = cfg->nx * cfg->h;
+    L[1] = cfg->ny * cfg->h;
+    L[2] = cfg->nz * cfg->h;
+}
+
+int orc_sf_bins(const orc_cfg *cfg, int nbins, double *l)
+{
+    if (check_cfg(cfg) || nbins < 1) return ORC_EINVAL;
+    double L[3];
+    box_of(cfg, L);
+    double lmax = 0.5 * fmin(L[0], fmin(L[1], L[2]));
+    double lmin = cfg->h / (cfg->k + 1);
+    for (int b = 0; b < nbins; ++b) l[b] = lmin * pow(lmax / lmin, (b + 0.5) / nbins);
+    return ORC_OK;
+}
+
+/* the two points of pair `pair` at distance l */
+void orc_sf_pair(const orc_cfg *cfg, uint64_t seed, uint64_t pair, double l, double x1[3], double x2[3])
+{
+    double L[3];
+    box_of(cfg, L);
+    const uint64_t base = pair * 256u;
+    for (int a = 0; a < 3; ++a) x1[a] = uniform01(seed, base + a) * L[a];
+    double n[3] = {0.0, 0.0, 1.0};
+    for (int t = 0; t < 84; ++t) {
+        double c[3];
+        for (int a = 0; a < 3; ++a) c[a] = 2.0 * uniform01(seed, base + 3 + 3 * t + a) - 1.0;
+        double r2 = fma(c[2], c[2], fma(c[1], c[1], c[0] * c[0]));
+        if (r2 > 1e-12 && r2 <= 1.0) {
+            double r = sqrt(r2);
+            for (int a = 0; a < 3; ++a) n[a] = c[a] / r;
+            break;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        double y = fma(l, n[a], x1[a]);
+        if (y >= L[a]) y -= L[a];
+        else if (y < 0.0) y += L[a];
+        x2[a] = y;
+    }
+}
+
+/* v = m / max(rho, floor) at a point of the box */
+void orc_velocity_at(const orc_cfg *cfg, const double *u, const double x[3], double v[3])
+{
+    int n[3] = {cfg->nx, cfg->ny, cfg->nz}, ijk[3];
+    double xi[3];
+    for (int a = 0; a < 3; ++a) {
+        double s = x[a] / cfg->h;
+        int i = (int)floor(s);
+        if (i < 0) i = 0;
+        if (i > n[a] - 1) i = n[a] - 1;
+        ijk[a] = i;
+        xi[a] = 2.0 * (s - i) - 1.0;
+    }
+    long c = cell_id(cfg, ijk[0], ijk[1], ijk[2]);
+    int nb = orc_nbasis(cfg->k);
+    long nc = ncell_of(cfg);
+    double phi[NBMAX];
+    for (int l = 0; l < nb; ++l) orc_basis_eval(cfg->k, l, xi, &phi[l], NULL);
+    double rho = fmax(expand(u, nb, nc, 0, c, phi), cfg->rho_floor);
+    for (int d = 0; d < 3; ++d) v[d] = expand(u, nb, nc, 1 + d, c, phi) / rho;
+}
+
+/* S2 of the bins b0 .. b0+nsel-1 of an nbins-bin measurement with npairs pairs per bin
+ * (the pairs of a bin do not depend on the other bins, so bins can be computed alone). */
+int orc_structure_function(const orc_cfg *cfg, const double *u, int nbins, int b0, int nsel, const double *l,
+                           long npairs, uint64_t seed, double *s2)
+{
+    if (check_cfg(cfg) || nbins < 1 || b0 < 0 || nsel < 0 || b0 + nsel > nbins || npairs < 1) return ORC_EINVAL;
+    #pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < nsel; ++i) {
+        int b = b0 + i;
+        double sum = 0.0;
+        for (long j = 0; j < npairs; ++j) {
+            double x1[3], x2[3], v1[3], v2[3];
+            orc_sf_pair(cfg, seed, (uint64_t)b * (uint64_t)npairs + (uint64_t)j, l[b], x1, x2);
+            orc_velocity_at(cfg, u, x1, v1);
+            orc_velocity_at(cfg, u, x2, v2);
+            for (int d = 0; d < 3; ++d) sum += (v1[d] - v2[d]) * (v1[d] - v2[d]);
+        }
+        s2[i] = sum / (double)npairs;
+    }
+    return ORC_OK;
+}
+
+/* Velocity on the uniform grid of p points per cell per dimension (cell-centred
+ * sub-points xi_s = -1 + (2s+1)/p; the N p grid of the paper's spectra):
+ * grid[d][z][y][x], x fastest, (nz p) x (ny p) x (nx p) points. */
+int orc_velocity_grid(const orc_cfg *cfg, const double *u, int p, double *grid)
+{
+    if (check_cfg(cfg) || p < 1) return ORC_EINVAL;
+    long X = (long)cfg->nx * p, Y = (long)cfg->ny * p, Z = (long)cfg->nz * p;
+    long npts = X * Y * Z;
+    int nb = orc_nbasis(cfg->k);
+    long nc = ncell_of(cfg);
+    #pragma omp parallel for schedule(static)
+    for (long gz = 0; gz < Z; ++gz)
+        for (long gy = 0; gy < Y; ++gy)
+            for (long gx = 0; gx < X; ++gx) {
+                long g[3] = {gx, gy, gz};
+                int ijk[3];
+                double xi[3];
+                for (int a = 0; a < 3; ++a) {
+                    ijk[a] = (int)(g[a] / p);
+                    xi[a] = -1.0 + (2.0 * (double)(g[a] % p) + 1.0) / p;
+                }
+                long c = cell_id(cfg, ijk[0], ijk[1], ijk[2]);
+                double phi[NBMAX];
+                for (int l = 0; l < nb; ++l) orc_basis_eval(cfg->k, l, xi, &phi[l], NULL);
+                double rho = fmax(expand(u, nb, nc, 0, c, phi), cfg->rho_floor);
+                long o = gx + X * (gy + Y * gz);
+                for (int d = 0; d < 3; ++d) grid[d * npts + o] = expand(u, nb, nc, 1 + d, c, phi) / rho;
+            }
+    return ORC_OK;
+}
