@@ -250,6 +250,53 @@ int dg_mlp_grad(dg_ctx *ctx, const float *params_dev, const float *x_dev, const 
 int dg_mlp_adam(dg_ctx *ctx, float *params_dev, const float *grad_dev, float *m_dev,
                 float *v_dev, int step, float lr);
 
+/* ---------------------------------------------------------------- flow statistics
+ * Sec. 4.3 (the scale-dependent velocity v(l) and the subsection on measuring structure
+ * functions and power spectra).  The velocity is v = m / max(rho, rho_floor) evaluated from
+ * the expansions of the cell that holds a point (positivity is only enforced at the Gauss
+ * points).  Both calls take a caller scratch buffer in DEVICE memory (256-byte aligned, at
+ * least dg_stats_scratch_bytes bytes, contents not preserved), leave the state untouched,
+ * and synchronise. */
+
+/* The separations of an nbins-bin structure function: logarithmic bins between the
+ * resolution limit h/(k+1) and half the shortest box side, each bin represented by its
+ * geometric centre, l_b = lmin (lmax/lmin)^((b + 1/2)/nbins).  l_host[nbins] host memory. */
+int dg_sf_bins(const dg_ctx *ctx, int nbins, double *l_host);
+
+/* Scratch bytes for dg_structure_function with nbins bins (0: not needed) and for
+ * dg_velocity_spectrum with p samples per cell (0: not needed); the larger of the two.
+ * Structure function: 4 nb ncell doubles of cell records plus 65 nbins doubles.  Spectrum:
+ * the velocity grid (3 X Y Z doubles), its half spectrum (3 (X/2+1) Y Z complex doubles)
+ * and 1024 per-block shell histograms. */
+size_t dg_stats_scratch_bytes(const dg_ctx *ctx, int nbins, int p);
+
+/* Second-order velocity structure function S2(l_b) = mean over npairs random pairs of
+ * |v(x) - v(x + l_b n)|^2 for every bin of dg_sf_bins (the paper's v(l) = sqrt(S2/2);
+ * typically 100 bins of 1e5 pairs).  Pair j of bin b: first point uniform in the periodic
+ * box, direction uniform on the unit sphere (rejection from the cube), second point wrapped
+ * into the box; the random numbers are draws 256 (b npairs + j) + t of the counter-based
+ * SplitMix64 stream `seed` (Steele, Lea & Flood 2014), so the pairs of a bin do not
+ * depend on the other bins or on the launch shape.  FP64 evaluation and sums for either
+ * state precision; deterministic.  s2_host[nbins] host memory.
+ * Errors: DG_EINVAL (null/misaligned pointer, nbins outside 1..65535, npairs < 1),
+ * DG_ENOMEM (scratch too small). */
+int dg_structure_function(dg_ctx *ctx, const void *u, int nbins, long long npairs, unsigned long long seed,
+                          void *scratch, size_t scratch_bytes, double *s2_host);
+
+/* Number of integer shells K = 0 .. Kmax of the p-sample grid, Kmax = round(|(X/2, Y/2,
+ * Z/2)|) with X = nx p etc. (integer division); negative on bad arguments. */
+int dg_spectrum_nshell(const dg_ctx *ctx, int p);
+
+/* Velocity power spectrum on the grid of p cell-centred points per cell per dimension
+ * (sub-points xi_s = -1 + (2s+1)/p): e_host[K] = sum over wave vectors kappa (box units)
+ * with round(|kappa|) = K of 1/2 |v_hat(kappa)|^2, v_hat = the discrete Fourier transform
+ * divided by the number of grid points, so that sum_K e_host[K] = 1/2 <|v|^2> over the grid.
+ * FP64 grid and FFT (hipFFT, double precision real-to-complex).  e_host has
+ * dg_spectrum_nshell(p) entries (host memory).
+ * Errors: DG_EINVAL (bad pointer, p < 1, fewer than 2 grid points along an axis),
+ * DG_EUNSUPPORTED (more than 4096 shells), DG_ENOMEM (scratch too small), DG_EHIP. */
+int dg_velocity_spectrum(dg_ctx *ctx, const void *u, int p, void *scratch, size_t scratch_bytes, double *e_host);
+
 #ifdef __cplusplus
 }
 #endif

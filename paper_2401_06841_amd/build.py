@@ -12,7 +12,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libdg.so")
-SOURCES = ["dg_api.hip", "dg_sensor.hip", "dg_forcing.cpp"]
+SOURCES = ["dg_api.hip", "dg_sensor.hip", "dg_stats.hip", "dg_forcing.cpp"]
+# hipFFT for the spectrum of the flow statistics
+LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lhipfft"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
@@ -28,7 +30,7 @@ def build(verbose: bool = False, resource_usage: bool = False) -> str:
     if resource_usage:
         cmd += ["-Rpass-analysis=kernel-resource-usage"]
     tmp = SO + ".tmp"
-    cmd += ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd += ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES] + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

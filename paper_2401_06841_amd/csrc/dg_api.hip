@@ -27,22 +27,6 @@ int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...)
     return code;
 }
 
-#define HIPCHK(ctx, call)                                                                         \
-    do {                                                                                          \
-        hipError_t e_ = (call);                                                                   \
-        if (e_ != hipSuccess)                                                                     \
-            return dg_fail((ctx), DG_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
-                           __FILE__, __LINE__);                                                   \
-    } while (0)
-
-#define LAUNCHCHK(ctx)                                                                            \
-    do {                                                                                          \
-        hipError_t e_ = hipGetLastError();                                                        \
-        if (e_ != hipSuccess)                                                                     \
-            return dg_fail((ctx), DG_EHIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
-                           __FILE__, __LINE__);                                                   \
-    } while (0)
-
 // ------------------------------------------------------------------ tables
 // Host-side FP64 construction of the basis / quadrature tables.
 namespace {

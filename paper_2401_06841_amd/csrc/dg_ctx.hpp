@@ -55,5 +55,23 @@ struct dg_ctx {
 };
 
 int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...);
+
+// return a DG_EHIP error with the failing call and its place from a host function
+#define HIPCHK(ctx, call)                                                                         \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return dg_fail((ctx), DG_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                           __FILE__, __LINE__);                                                   \
+    } while (0)
+
+#define LAUNCHCHK(ctx)                                                                            \
+    do {                                                                                          \
+        hipError_t e_ = hipGetLastError();                                                        \
+        if (e_ != hipSuccess)                                                                     \
+            return dg_fail((ctx), DG_EHIP, "kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                           __FILE__, __LINE__);                                                   \
+    } while (0)
+
 int sensor_infer_impl(dg_ctx *c, const void *u);
 int sensor_reset_flags(dg_ctx *c);

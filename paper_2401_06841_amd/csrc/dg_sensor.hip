@@ -458,19 +458,6 @@ __global__ void k_fill_int(int *__restrict__ p, int n, int value)
 
 using namespace dg;
 
-#define HIPCHK(ctx, call)                                                                         \
-    do {                                                                                          \
-        hipError_t e_ = (call);                                                                   \
-        if (e_ != hipSuccess)                                                                     \
-            return dg_fail((ctx), DG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));        \
-    } while (0)
-
-#define LAUNCHCHK(ctx)                                                                            \
-    do {                                                                                          \
-        hipError_t e_ = hipGetLastError();                                                        \
-        if (e_ != hipSuccess) return dg_fail((ctx), DG_EHIP, "kernel launch failed: %s", hipGetErrorString(e_)); \
-    } while (0)
-
 // gradient: at most MLP_WAVES waves, one partial-sum row each
 static int mlp_blocks(int n)
 {

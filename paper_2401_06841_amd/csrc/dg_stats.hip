@@ -1,0 +1,493 @@
+// dg_stats.hip -- flow statistics of a DG state on the GPU (Sec. 4.3): the second-order
+// velocity structure function from random point pairs evaluated through the cell
+// expansions, and the shell-summed velocity power spectrum of the sampling grid of p
+// points per cell per dimension.
+//
+// Pairs: pair j of bin b owns the draws 256 (b npairs + j) + t of the counter-based
+// SplitMix64 stream `seed` (Steele, Lea & Flood 2014; a draw is the generator's output for
+// the state seed + (i+1) 0x9E3779B97F4A7C15, a uniform double its top 53 bits times 2^-53):
+// t = 0..2 the first point (uniform in the box), then direction attempts of three draws
+// each, uniform in [-1,1]^3, accepted when 1e-12 < r^2 <= 1 (at most 84, else +z); the
+// second point is x + l n (one fused multiply-add per axis) wrapped into the box.  Every
+// decision that picks a cell is taken from correctly rounded operations only, so a pair
+// lands in the same cells on any IEEE machine.
+//
+// Layout for the random gathers: the state is first copied to one record per cell,
+// [cell][var][mode] in FP64 (4 nb doubles, 16-byte aligned), so a point reads one
+// contiguous record instead of 4 nb separate cache lines.  Sums are per thread, per block
+// (fixed tree) and over blocks in a fixed order, so the structure function is
+// deterministic.  The spectrum bins shell energies with LDS atomics inside a block (the
+// order of additions inside a block is not fixed; blocks are summed in a fixed order).
+#include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dg.h"
+#include "dg_ctx.hpp"
+#include "dg_kernels.hpp"
+
+namespace dg {
+
+constexpr int SF_CHUNKS = 64;       // blocks per bin of the pair kernel
+constexpr int SP_BLOCKS = 1024;     // blocks of the shell kernel
+constexpr int SF_MAX_BINS = 65535;  // grid y limit
+constexpr int SP_MAX_SHELLS = 4096; // LDS histogram of the shell kernel (32 KiB)
+
+struct StatsGeom {
+    int nx, ny, nz;
+    double h, Lx, Ly, Lz, floor;
+};
+
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long seed, unsigned long long i)
+{
+    unsigned long long z = seed + (i + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double uniform01(unsigned long long seed, unsigned long long i)
+{
+    return (double)(splitmix64(seed, i) >> 11) * 0x1.0p-53;
+}
+
+// Lt_n(x) = sqrt(2n+1) P_n(x), n = 0..K, by the three-term recurrence of P_n
+template <int K>
+__device__ __forceinline__ void legendre_row(double x, double (&L)[K + 1])
+{
+    double pm = 1.0, p = x;
+    L[0] = 1.0;
+    if constexpr (K >= 1) L[1] = __builtin_sqrt(3.0) * x;
+#pragma unroll
+    for (int n = 1; n < K; ++n) {
+        const double pn = ((2 * n + 1) * x * p - n * pm) * (1.0 / (n + 1));
+        pm = p;
+        p = pn;
+        L[n + 1] = __builtin_sqrt(double(2 * n + 3)) * pn;
+    }
+}
+
+// v = m / max(rho, floor) at x from the cell record that holds x
+template <int K>
+__device__ __forceinline__ void velocity_at(const double *cells, const StatsGeom &g, const double (&x)[3],
+                                            double (&v)[3])
+{
+    constexpr int NB = Shape<K>::NB;
+    constexpr Modes<K> M = make_modes<K>();
+    const int n[3] = {g.nx, g.ny, g.nz};
+    int ijk[3];
+    double xi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double s = x[a] / g.h;
+        int i = (int)floor(s);
+        i = i < 0 ? 0 : (i > n[a] - 1 ? n[a] - 1 : i);
+        ijk[a] = i;
+        xi[a] = 2.0 * (s - i) - 1.0;
+    }
+    double Lx[K + 1], Ly[K + 1], Lz[K + 1];
+    legendre_row<K>(xi[0], Lx);
+    legendre_row<K>(xi[1], Ly);
+    legendre_row<K>(xi[2], Lz);
+    const size_t c = (size_t)ijk[0] + (size_t)g.nx * ((size_t)ijk[1] + (size_t)g.ny * ijk[2]);
+    const double2 *rec = (const double2 *)(cells + c * 4 * NB);
+    double w[4 * NB];
+#pragma unroll
+    for (int i = 0; i < 2 * NB; ++i) {
+        const double2 t = rec[i];
+        w[2 * i] = t.x;
+        w[2 * i + 1] = t.y;
+    }
+    double r = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+        const double phi = Lx[M.e[l][0]] * Ly[M.e[l][1]] * Lz[M.e[l][2]];
+        r += w[l] * phi;
+        m0 += w[NB + l] * phi;
+        m1 += w[2 * NB + l] * phi;
+        m2 += w[3 * NB + l] * phi;
+    }
+    r = fmax(r, g.floor);
+    v[0] = m0 / r;
+    v[1] = m1 / r;
+    v[2] = m2 / r;
+}
+
+// [var][mode][cell] (T) -> [cell][var][mode] (FP64)
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_cell_records(const void *u_, int nc, double *cells)
+{
+    constexpr int NB = Shape<K>::NB;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= nc) return;
+    const T *u = (const T *)u_;
+    double *r = cells + (size_t)c * 4 * NB;
+#pragma unroll
+    for (int i = 0; i < 4 * NB; ++i) r[i] = (double)u[(size_t)i * nc + c];
+}
+
+// grid (chunks, bins): block (x, b) sums |dv|^2 over the pairs j = x BLOCK + t + m chunks BLOCK
+template <int K>
+__global__ void __launch_bounds__(BLOCK) k_sf_pairs(const double *cells, StatsGeom g, const double *lb,
+                                                    long long npairs, unsigned long long seed, double *part)
+{
+    __shared__ double lds[4 * 4];
+    const int b = blockIdx.y;
+    const double l = lb[b];
+    const double L[3] = {g.Lx, g.Ly, g.Lz};
+    double sum = 0.0;
+    for (long long j = (long long)blockIdx.x * BLOCK + threadIdx.x; j < npairs; j += (long long)gridDim.x * BLOCK) {
+        const unsigned long long base = ((unsigned long long)b * (unsigned long long)npairs + (unsigned long long)j) * 256ull;
+        double x1[3], x2[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x1[a] = uniform01(seed, base + a) * L[a];
+        double n0 = 0.0, n1 = 0.0, n2 = 1.0;
+        for (int t = 0; t < 84; ++t) {
+            const double c0 = 2.0 * uniform01(seed, base + 3 + 3 * t) - 1.0;
+            const double c1 = 2.0 * uniform01(seed, base + 4 + 3 * t) - 1.0;
+            const double c2 = 2.0 * uniform01(seed, base + 5 + 3 * t) - 1.0;
+            const double r2 = fma(c2, c2, fma(c1, c1, c0 * c0));
+            if (r2 > 1e-12 && r2 <= 1.0) {
+                const double r = sqrt(r2);
+                n0 = c0 / r;
+                n1 = c1 / r;
+                n2 = c2 / r;
+                break;
+            }
+        }
+        const double nn[3] = {n0, n1, n2};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double y = fma(l, nn[a], x1[a]);
+            if (y >= L[a]) y -= L[a];
+            else if (y < 0.0) y += L[a];
+            x2[a] = y;
+        }
+        double v1[3], v2[3];
+        velocity_at<K>(cells, g, x1, v1);
+        velocity_at<K>(cells, g, x2, v2);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) sum += (v1[d] - v2[d]) * (v1[d] - v2[d]);
+    }
+    double acc[1] = {sum};
+    block_sum<1>(acc, lds);
+    if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = acc[0];
+}
+
+// out[b] = (sum over the chunks of bin b, in order) / npairs
+static __global__ void k_sf_final(const double *part, int nchunks, int nbins, long long npairs, double *out)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins) return;
+    double s = 0.0;
+    for (int i = 0; i < nchunks; ++i) s += part[(size_t)b * nchunks + i];
+    out[b] = s / (double)npairs;
+}
+
+// v on the grid of p cell-centred sub-points per cell per dimension, [d][Z][Y][X], x fastest
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_velocity_grid(const void *u_, StatsGeom g, int p, double *grid)
+{
+    constexpr int NB = Shape<K>::NB;
+    constexpr Modes<K> M = make_modes<K>();
+    const long long X = (long long)g.nx * p, Y = (long long)g.ny * p, Z = (long long)g.nz * p;
+    const long long npts = X * Y * Z;
+    const long long o = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (o >= npts) return;
+    const long long gg[3] = {o % X, (o / X) % Y, o / (X * Y)};
+    int ijk[3];
+    double xi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ijk[a] = (int)(gg[a] / p);
+        xi[a] = -1.0 + (2.0 * (double)(gg[a] % p) + 1.0) / p;
+    }
+    double Lx[K + 1], Ly[K + 1], Lz[K + 1];
+    legendre_row<K>(xi[0], Lx);
+    legendre_row<K>(xi[1], Ly);
+    legendre_row<K>(xi[2], Lz);
+    const size_t nc = (size_t)g.nx * g.ny * g.nz;
+    const size_t c = (size_t)ijk[0] + (size_t)g.nx * ((size_t)ijk[1] + (size_t)g.ny * ijk[2]);
+    const T *u = (const T *)u_;
+    double r = 0.0, m[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < NB; ++l) {
+        const double phi = Lx[M.e[l][0]] * Ly[M.e[l][1]] * Lz[M.e[l][2]];
+        r += (double)u[(size_t)l * nc + c] * phi;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) m[d] += (double)u[((size_t)(1 + d) * NB + l) * nc + c] * phi;
+    }
+    r = fmax(r, g.floor);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) grid[(size_t)d * npts + o] = m[d] / r;
+}
+
+// Shell sums of 1/2 |F / npts|^2 over the half spectrum F[d][Z][Y][X/2+1] of a real X x Y x Z
+// grid (the planes 0 < kx < X/2 stand for themselves and their mirror images, weight 2);
+// per-block histograms to part[block][nshell]
+static __global__ void __launch_bounds__(BLOCK) k_shells(const double2 *F, long long X, long long Y, long long Z,
+                                                         int nshell, double *part)
+{
+    extern __shared__ double hist[];
+    for (int s = threadIdx.x; s < nshell; s += BLOCK) hist[s] = 0.0;
+    __syncthreads();
+    const long long Xh = X / 2 + 1;
+    const long long M = Xh * Y * Z;
+    const double inv = 1.0 / ((double)X * (double)Y * (double)Z);
+    for (long long o = (long long)blockIdx.x * BLOCK + threadIdx.x; o < M; o += (long long)gridDim.x * BLOCK) {
+        const long long ix = o % Xh, r = o / Xh, iy = r % Y, iz = r / Y;
+        const long long fy = iy < (Y + 1) / 2 ? iy : iy - Y;
+        const long long fz = iz < (Z + 1) / 2 ? iz : iz - Z;
+        const int shell = (int)floor(sqrt((double)(ix * ix + fy * fy + fz * fz)) + 0.5);
+        const double w = (ix == 0 || (X % 2 == 0 && ix == X / 2)) ? 0.5 : 1.0;
+        double e = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double2 f = F[(size_t)d * M + o];
+            e += f.x * f.x + f.y * f.y;
+        }
+        atomicAdd(&hist[shell], w * e * inv * inv);
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < nshell; s += BLOCK) part[(size_t)blockIdx.x * nshell + s] = hist[s];
+}
+
+static __global__ void k_shells_final(const double *part, int nblk, int nshell, double *out)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nshell) return;
+    double t = 0.0;
+    for (int b = 0; b < nblk; ++b) t += part[(size_t)b * nshell + s];
+    out[s] = t;
+}
+
+}  // namespace dg
+
+using namespace dg;
+
+namespace {
+
+size_t up256(size_t x) { return (x + 255) & ~size_t(255); }
+
+StatsGeom geom_of(const dg_ctx *c)
+{
+    StatsGeom g;
+    g.nx = c->cfg.nx;
+    g.ny = c->cfg.ny;
+    g.nz = c->cfg.nz;
+    g.h = c->cfg.h;
+    g.Lx = c->cfg.nx * c->cfg.h;
+    g.Ly = c->cfg.ny * c->cfg.h;
+    g.Lz = c->cfg.nz * c->cfg.h;
+    g.floor = c->cfg.rho_floor;
+    return g;
+}
+
+struct SfLayout {
+    size_t cells, lb, part, out, total;
+};
+
+SfLayout sf_layout(const dg_ctx *c, int nbins)
+{
+    SfLayout s;
+    size_t o = 0;
+    s.cells = o; o += up256((size_t)c->nc * 4 * c->nb * sizeof(double));
+    s.lb = o; o += up256((size_t)nbins * sizeof(double));
+    s.part = o; o += up256((size_t)nbins * SF_CHUNKS * sizeof(double));
+    s.out = o; o += up256((size_t)nbins * sizeof(double));
+    s.total = o;
+    return s;
+}
+
+struct SpLayout {
+    long long X, Y, Z, npts, M;
+    int nshell;
+    size_t grid, cplx, part, out, total;
+};
+
+SpLayout sp_layout(const dg_ctx *c, int p)
+{
+    SpLayout s;
+    s.X = (long long)c->cfg.nx * p;
+    s.Y = (long long)c->cfg.ny * p;
+    s.Z = (long long)c->cfg.nz * p;
+    s.npts = s.X * s.Y * s.Z;
+    s.M = (s.X / 2 + 1) * s.Y * s.Z;
+    const double kmax = std::sqrt((double)((s.X / 2) * (s.X / 2) + (s.Y / 2) * (s.Y / 2) + (s.Z / 2) * (s.Z / 2)));
+    s.nshell = (int)std::floor(kmax + 0.5) + 1;
+    size_t o = 0;
+    s.grid = o; o += up256((size_t)s.npts * 3 * sizeof(double));
+    s.cplx = o; o += up256((size_t)s.M * 3 * 2 * sizeof(double));
+    s.part = o; o += up256((size_t)SP_BLOCKS * s.nshell * sizeof(double));
+    s.out = o; o += up256((size_t)s.nshell * sizeof(double));
+    s.total = o;
+    return s;
+}
+
+int check_state_ptr(dg_ctx *c, const void *u)
+{
+    if (!u) return dg_fail(c, DG_EINVAL, "u is null");
+    if ((uintptr_t)u & (c->es - 1)) return dg_fail(c, DG_EINVAL, "u is misaligned");
+    return DG_OK;
+}
+
+int check_scratch(dg_ctx *c, const void *scratch, size_t bytes, size_t need)
+{
+    if (!scratch) return dg_fail(c, DG_EINVAL, "scratch is null");
+    if ((uintptr_t)scratch & 255) return dg_fail(c, DG_EINVAL, "scratch must be 256-byte aligned");
+    if (bytes < need) return dg_fail(c, DG_ENOMEM, "scratch too small: %zu < %zu bytes", bytes, need);
+    return DG_OK;
+}
+
+template <typename T, int K>
+int launch_sf(dg_ctx *c, const void *u, int nbins, long long npairs, unsigned long long seed, char *scr,
+              const SfLayout &s, const double *lb_host)
+{
+    const StatsGeom g = geom_of(c);
+    double *cells = (double *)(scr + s.cells);
+    double *lb = (double *)(scr + s.lb);
+    double *part = (double *)(scr + s.part);
+    double *out = (double *)(scr + s.out);
+    HIPCHK(c, hipMemcpyAsync(lb, lb_host, (size_t)nbins * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL((k_cell_records<T, K>), dim3((c->nc + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream, u, c->nc,
+                       cells);
+    LAUNCHCHK(c);
+    const long long need = (npairs + BLOCK - 1) / BLOCK;
+    const int chunks = (int)(need < SF_CHUNKS ? need : SF_CHUNKS);
+    hipLaunchKernelGGL((k_sf_pairs<K>), dim3(chunks, nbins), dim3(BLOCK), 0, c->stream, (const double *)cells, g,
+                       (const double *)lb, npairs, seed, part);
+    LAUNCHCHK(c);
+    hipLaunchKernelGGL(k_sf_final, dim3((nbins + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
+                       (const double *)part, chunks, nbins, npairs, out);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+template <typename T, int K>
+int launch_grid(dg_ctx *c, const void *u, int p, double *grid, long long npts)
+{
+    const StatsGeom g = geom_of(c);
+    hipLaunchKernelGGL((k_velocity_grid<T, K>), dim3((unsigned)((npts + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0,
+                       c->stream, u, g, p, grid);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
+#define STATS_DISPATCH(c, FN, ...)                                                  \
+    ((c)->es == 8 ? ((c)->k == 1   ? FN<double, 1>(__VA_ARGS__)                     \
+                     : (c)->k == 2 ? FN<double, 2>(__VA_ARGS__)                     \
+                                   : FN<double, 3>(__VA_ARGS__))                    \
+                  : ((c)->k == 1   ? FN<float, 1>(__VA_ARGS__)                      \
+                     : (c)->k == 2 ? FN<float, 2>(__VA_ARGS__)                      \
+                                   : FN<float, 3>(__VA_ARGS__)))
+
+int fft_fail(dg_ctx *c, const char *what, hipfftResult r)
+{
+    return dg_fail(c, DG_EHIP, "%s failed: hipfftResult %d", what, (int)r);
+}
+
+}  // namespace
+
+int dg_sf_bins(const dg_ctx *c, int nbins, double *l_host)
+{
+    if (!c || !l_host || nbins < 1) return DG_EINVAL;
+    const StatsGeom g = geom_of(c);
+    const double lmax = 0.5 * std::fmin(g.Lx, std::fmin(g.Ly, g.Lz));
+    const double lmin = g.h / (c->k + 1);
+    for (int b = 0; b < nbins; ++b) l_host[b] = lmin * std::pow(lmax / lmin, (b + 0.5) / nbins);
+    return DG_OK;
+}
+
+size_t dg_stats_scratch_bytes(const dg_ctx *c, int nbins, int p)
+{
+    if (!c) return 0;
+    size_t need = 0;
+    if (nbins > 0) need = sf_layout(c, nbins).total;
+    if (p > 0) {
+        const size_t s = sp_layout(c, p).total;
+        need = s > need ? s : need;
+    }
+    return need;
+}
+
+int dg_structure_function(dg_ctx *c, const void *u, int nbins, long long npairs, unsigned long long seed,
+                          void *scratch, size_t scratch_bytes, double *s2_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = check_state_ptr(c, u))) return rc;
+    if (nbins < 1 || nbins > SF_MAX_BINS) return dg_fail(c, DG_EINVAL, "nbins must be in 1..%d", SF_MAX_BINS);
+    if (npairs < 1) return dg_fail(c, DG_EINVAL, "npairs must be positive");
+    if ((unsigned long long)nbins * (unsigned long long)npairs > (1ull << 55))
+        return dg_fail(c, DG_EINVAL, "nbins * npairs too large for the draw counters");
+    if (!s2_host) return dg_fail(c, DG_EINVAL, "s2_host is null");
+    const SfLayout s = sf_layout(c, nbins);
+    if ((rc = check_scratch(c, scratch, scratch_bytes, s.total))) return rc;
+    std::vector<double> lb(nbins);
+    dg_sf_bins(c, nbins, lb.data());
+    rc = STATS_DISPATCH(c, launch_sf, c, u, nbins, npairs, seed, (char *)scratch, s, lb.data());
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(s2_host, (char *)scratch + s.out, (size_t)nbins * sizeof(double), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return DG_OK;
+}
+
+int dg_spectrum_nshell(const dg_ctx *c, int p)
+{
+    if (!c || p < 1) return DG_EINVAL;
+    return sp_layout(c, p).nshell;
+}
+
+int dg_velocity_spectrum(dg_ctx *c, const void *u, int p, void *scratch, size_t scratch_bytes, double *e_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = check_state_ptr(c, u))) return rc;
+    if (p < 1) return dg_fail(c, DG_EINVAL, "p must be positive");
+    if (!e_host) return dg_fail(c, DG_EINVAL, "e_host is null");
+    const SpLayout s = sp_layout(c, p);
+    if (s.X < 2 || s.Y < 2 || s.Z < 2) return dg_fail(c, DG_EINVAL, "the sampling grid needs at least 2 points per axis");
+    if (s.X > (1 << 30) || s.Y > (1 << 30) || s.Z > (1 << 30) || s.npts > (1ll << 40))
+        return dg_fail(c, DG_EINVAL, "sampling grid too large");
+    if (s.nshell > SP_MAX_SHELLS) return dg_fail(c, DG_EUNSUPPORTED, "more than %d shells", SP_MAX_SHELLS);
+    if ((rc = check_scratch(c, scratch, scratch_bytes, s.total))) return rc;
+    char *scr = (char *)scratch;
+    double *grid = (double *)(scr + s.grid);
+    double2 *cplx = (double2 *)(scr + s.cplx);
+    double *part = (double *)(scr + s.part);
+    double *out = (double *)(scr + s.out);
+    rc = STATS_DISPATCH(c, launch_grid, c, u, p, grid, s.npts);
+    if (rc) return rc;
+    hipfftHandle plan;
+    hipfftResult fr = hipfftPlan3d(&plan, (int)s.Z, (int)s.Y, (int)s.X, HIPFFT_D2Z);
+    if (fr != HIPFFT_SUCCESS) return fft_fail(c, "hipfftPlan3d", fr);
+    fr = hipfftSetStream(plan, c->stream);
+    for (int d = 0; d < 3 && fr == HIPFFT_SUCCESS; ++d)
+        fr = hipfftExecD2Z(plan, grid + (size_t)d * s.npts, (hipfftDoubleComplex *)(cplx + (size_t)d * s.M));
+    if (fr != HIPFFT_SUCCESS) {
+        (void)hipStreamSynchronize(c->stream);
+        hipfftDestroy(plan);
+        return fft_fail(c, "hipfftExecD2Z", fr);
+    }
+    const long long need = (s.M + BLOCK - 1) / BLOCK;
+    const int nblk = (int)(need < SP_BLOCKS ? need : SP_BLOCKS);
+    hipLaunchKernelGGL(k_shells, dim3(nblk), dim3(BLOCK), (size_t)s.nshell * sizeof(double), c->stream,
+                       (const double2 *)cplx, s.X, s.Y, s.Z, s.nshell, part);
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) {
+        hipLaunchKernelGGL(k_shells_final, dim3((s.nshell + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
+                           (const double *)part, nblk, s.nshell, out);
+        le = hipGetLastError();
+    }
+    if (le == hipSuccess)
+        le = hipMemcpyAsync(e_host, out, (size_t)s.nshell * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    const hipError_t se = hipStreamSynchronize(c->stream);
+    hipfftDestroy(plan);
+    if (le != hipSuccess) return dg_fail(c, DG_EHIP, "spectrum kernels failed: %s", hipGetErrorString(le));
+    if (se != hipSuccess) return dg_fail(c, DG_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(se));
+    return DG_OK;
+}

@@ -11,6 +11,7 @@ import ctypes
 import dataclasses
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -73,6 +74,12 @@ _SIGS = {
     "dg_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
     "dg_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int, _vp, _vp]),
     "dg_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_float]),
+    "dg_sf_bins": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "dg_stats_scratch_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int, ctypes.c_int]),
+    "dg_structure_function": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, ctypes.c_ulonglong, _vp,
+                                             ctypes.c_size_t, _dp]),
+    "dg_spectrum_nshell": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "dg_velocity_spectrum": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_size_t, _dp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -366,3 +373,49 @@ def dg_mlp_adam(ctx: Context, params, grad, m, v, step: int, lr: float):
     for name, b in (("params", params), ("grad", grad), ("m", m), ("v", v)):
         _need(ctx, b, torch.float32, DG_MLP_NPARAM, name)
     ctx._chk(_lib.dg_mlp_adam(ctx.h, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr)))
+
+
+# ------------------------------------------------------------------ flow statistics
+def _scratch(ctx: Context, nbytes: int, scratch):
+    import torch
+    if scratch is None:
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=ctx.device)
+    _need(ctx, scratch, torch.uint8, nbytes, "scratch")
+    return scratch
+
+
+def dg_sf_bins(ctx: Context, nbins: int):
+    out = np.zeros(nbins)
+    ctx._chk(_lib.dg_sf_bins(ctx.h, int(nbins), out.ctypes.data_as(_dp)))
+    return out
+
+
+def dg_stats_scratch_bytes(ctx: Context, nbins: int = 0, p: int = 0) -> int:
+    return int(_lib.dg_stats_scratch_bytes(ctx.h, int(nbins), int(p)))
+
+
+def dg_structure_function(ctx: Context, u, nbins: int, npairs: int, seed: int, scratch=None):
+    """S2(l_b) for the bins of dg_sf_bins (numpy array [nbins]); v(l) = sqrt(S2 / 2)."""
+    ctx._check_state(u)
+    scr = _scratch(ctx, dg_stats_scratch_bytes(ctx, nbins, 0), scratch)
+    out = np.zeros(nbins)
+    ctx._chk(_lib.dg_structure_function(ctx.h, _ptr(u), int(nbins), int(npairs), int(seed) & (2 ** 64 - 1),
+                                        _ptr(scr), scr.numel(), out.ctypes.data_as(_dp)))
+    return out
+
+
+def dg_spectrum_nshell(ctx: Context, p: int) -> int:
+    n = _lib.dg_spectrum_nshell(ctx.h, int(p))
+    if n < 1:
+        raise DGError(n, f"no spectrum for p = {p}")
+    return n
+
+
+def dg_velocity_spectrum(ctx: Context, u, p: int, scratch=None):
+    """Shell-summed velocity power spectrum on the p-sample grid (numpy array)."""
+    ctx._check_state(u)
+    n = dg_spectrum_nshell(ctx, p)
+    scr = _scratch(ctx, dg_stats_scratch_bytes(ctx, 0, p), scratch)
+    out = np.zeros(n)
+    ctx._chk(_lib.dg_velocity_spectrum(ctx.h, _ptr(u), int(p), _ptr(scr), scr.numel(), out.ctypes.data_as(_dp)))
+    return out
