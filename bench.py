@@ -26,6 +26,7 @@ log distance (the FP32 legs' statistics error against the FP64 path).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5]
                        [--precision fp64|fp32] [--no-compare] [--no-learned] [--no-cpu]
+                       [--no-stats]
 """
 from __future__ import annotations
 
@@ -128,6 +129,56 @@ def _summary(args, sim, precision, wall, prof, retries, dt_min):
     return out
 
 
+def _sonic_scale(l, mach_l):
+    """Separation where M(l) = v(l)/cs first reaches 1 from below (log-log interpolation
+    between bins), or None."""
+    import numpy as np
+    up = np.nonzero(mach_l >= 1.0)[0]
+    if up.size == 0 or up[0] == 0:
+        return None
+    i = up[0]
+    t = np.log(1.0 / mach_l[i - 1]) / np.log(mach_l[i] / mach_l[i - 1])
+    return float(np.exp(np.log(l[i - 1]) + t * np.log(l[i] / l[i - 1])))
+
+
+def _statistics(sim):
+    """Flow statistics of the final state on the GPU (Sec. 4.3), timed: the structure
+    function with 100 bins of 1e5 pairs and the spectrum on the N p grid (p = k+1).  Each
+    is run once untimed (hipFFT plan set-up) and then timed on the host clock around the
+    synchronising call.  The pair kernel reads two cell records of 4 nb doubles per pair."""
+    import numpy as np
+    import torch
+
+    from paper_2401_06841_amd import analysis, dg
+    ctx, u, k = sim.ctx, sim.u, sim.cfg.degree
+    nbins, npairs, p = analysis.SF_BINS, analysis.SF_PAIRS, k + 1
+    scr = torch.empty(dg.dg_stats_scratch_bytes(ctx, nbins, p), dtype=torch.uint8, device=ctx.device)
+    out = {}
+    for rep in range(2):
+        t0 = time.perf_counter()
+        s2 = dg.dg_structure_function(ctx, u, nbins, npairs, analysis.SF_SEED, scratch=scr)
+        t_sf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        e = dg.dg_velocity_spectrum(ctx, u, p, scratch=scr)
+        t_sp = time.perf_counter() - t0
+    l = dg.dg_sf_bins(ctx, nbins)
+    mach_l = np.sqrt(0.5 * s2) / sim.cfg.cs
+    rec_bytes = 4 * sim.cfg.nb * 8
+    pairs = nbins * npairs
+    out["structure_function"] = {
+        "bins": nbins, "pairs_per_bin": npairs, "ms": 1e3 * t_sf, "pairs_per_s": pairs / t_sf,
+        "record_bytes_per_pair": 2 * rec_bytes, "record_GB_per_s": 2 * rec_bytes * pairs / t_sf / 1e9,
+        "l_min": float(l[0]), "l_max": float(l[-1]),
+        "mach_at_l_min": float(mach_l[0]), "mach_at_l_max": float(mach_l[-1]),
+        "sonic_scale": _sonic_scale(l, mach_l)}
+    npts = (sim.cfg.nx * p) * (sim.cfg.ny * p) * (sim.cfg.nz * p)
+    out["spectrum"] = {"samples_per_cell": p, "grid_points": npts, "ms": 1e3 * t_sp, "shells": len(e),
+                       "half_v2": float(e.sum())}
+    del scr
+    torch.cuda.synchronize()
+    return out
+
+
 def _train_sensor(args, sim, ds):
     """Fit the learned sensor on the snapshots taken during the warm-up (library kernels)."""
     from paper_2401_06841_amd import sensor
@@ -176,6 +227,8 @@ def run_gpu(args, precision, measure_profile=True):
     drive0 = sim.driving_state()
     wall, prof, retries, dt_min = _timed(sim, args.steps, measure_profile)
     main = _summary(args, sim, precision, wall, prof, retries, dt_min)
+    if not args.no_stats:
+        main["statistics"] = _statistics(sim)
     compare = None
     if not args.no_compare:
         compare = {}
@@ -197,7 +250,7 @@ def run_gpu(args, precision, measure_profile=True):
                 sim2.set_driving_state(drive0)
                 w2, p2, r2, d2 = _timed(sim2, args.steps, measure_profile)
                 rec = _summary(args, sim2, other, w2, p2, r2, d2)
-                rec["vs_main"] = analysis.compare(sim2.u, ref, k, (N, N, N))
+                rec["vs_main"] = analysis.compare(sim2.u, ref, k, (N, N, N), sim2.ctx, sim.ctx)
                 if use_learned:
                     rec["training"] = train_info
                     rec["fallback_fraction_mean"] = float(sum(sim2.fallback_counts)) / max(
@@ -271,6 +324,7 @@ def main():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=10)
     p.add_argument("--no-learned", action="store_true")
+    p.add_argument("--no-stats", action="store_true", help="skip the flow-statistics timing")
     p.add_argument("--snapshots", type=int, default=16)
     p.add_argument("--snapshot-every", type=int, default=100)
     p.add_argument("--train-steps", type=int, default=2000)
@@ -312,6 +366,7 @@ def main():
         "roofline": main_run.get("roofline"),
         "cpu_baseline": cpu,
         "kernels": main_run.get("kernels"),
+        "statistics": main_run.get("statistics"),
         "retries": main_run["retries"],
         "rms_mach": main_run["rms_mach"],
         "sim_time": main_run["sim_time"],

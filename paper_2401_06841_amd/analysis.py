@@ -13,6 +13,11 @@
   so that the sampling grid has at most 256 points per dimension.
 The basis (orthonormal total-degree Legendre, graded order) is evaluated here with numpy's
 Legendre routines; nothing here runs in a simulation step.
+
+With library contexts for the two states, compare() instead takes the statistics from the
+GPU (dg_velocity_spectrum on the full N p grid with p = k+1, and dg_structure_function
+with 100 bins of 1e5 pairs, the same pairs for both states, so the difference reflects the
+states and not the sampling).
 """
 from __future__ import annotations
 
@@ -111,13 +116,40 @@ def spectrum_distance(e_test, e_ref, kmax: int) -> float:
     return float(np.mean(np.abs(np.log10(a[ok]) - np.log10(b[ok])))) if ok.any() else float("nan")
 
 
-def compare(u_test, u_ref, k: int, n: tuple[int, int, int]):
-    """Per-field relative L2 difference, density-PDF distance and spectrum distance of two
-    states on the same mesh."""
+SF_BINS, SF_PAIRS, SF_SEED = 100, 100000, 0x5F3759DF
+
+
+def gpu_structure_function(ctx, u, nbins: int = SF_BINS, npairs: int = SF_PAIRS, seed: int = SF_SEED):
+    """(l, v(l)) of Sec. 4.3 on the GPU: v(l) = sqrt(S2(l) / 2)."""
+    from . import dg
+    return dg.dg_sf_bins(ctx, nbins), np.sqrt(0.5 * dg.dg_structure_function(ctx, u, nbins, npairs, seed))
+
+
+def log_distance(a, b) -> float:
+    """Mean |log10 a - log10 b| over the entries where both are positive."""
+    a, b = np.asarray(a), np.asarray(b)
+    ok = (a > 0) & (b > 0)
+    return float(np.mean(np.abs(np.log10(a[ok]) - np.log10(b[ok])))) if ok.any() else float("nan")
+
+
+def compare(u_test, u_ref, k: int, n: tuple[int, int, int], ctx_test=None, ctx_ref=None):
+    """Per-field relative L2 difference, density-PDF distance, spectrum distance (and, with
+    contexts, structure-function distance) of two states on the same mesh."""
     a, b = _as_numpy(u_test), _as_numpy(u_ref)
     rho = float(np.linalg.norm(a[0] - b[0]) / np.linalg.norm(b[0]))
     mom = float(np.linalg.norm(a[1:] - b[1:]) / np.linalg.norm(b[1:]))
     pa, pb = density_pdf(a, k), density_pdf(b, k)
+    if ctx_test is not None and ctx_ref is not None:
+        from . import dg
+        p = k + 1
+        ea, eb = dg.dg_velocity_spectrum(ctx_test, u_test, p), dg.dg_velocity_spectrum(ctx_ref, u_ref, p)
+        _, va = gpu_structure_function(ctx_test, u_test)
+        _, vb = gpu_structure_function(ctx_ref, u_ref)
+        return {"l2_rel_rho": rho, "l2_rel_m": mom, "density_pdf_l1": pdf_distance(pa, pb),
+                "spectrum_samples_per_cell": p,
+                "spectrum_log10_mean_abs": spectrum_distance(ea, eb, min(n) * p // 2),
+                "spectrum_log10_mean_abs_cell_scales": spectrum_distance(ea, eb, min(n) // 2),
+                "structure_function_log10_mean_abs": log_distance(va, vb)}
     # k+1 samples per cell (the paper's N p grid), fewer on large meshes so that the grid
     # stays at most 256 points per dimension
     p = max(1, min(k + 1, 256 // max(n)))

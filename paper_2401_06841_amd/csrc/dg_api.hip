@@ -264,6 +264,7 @@ void dg_free(dg_ctx *c)
     if (c->modes_dev) (void)hipFree(c->modes_dev);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->mlp_bf16) (void)hipFree(c->mlp_bf16);
+    stats_release(c);
     delete c;
 }
 

@@ -48,6 +48,10 @@ struct dg_ctx {
     const void *vh_cache_u = nullptr;
     unsigned long vh_cache_gen = 0;
 
+    // cached hipFFT plan of the velocity spectrum (a hipfftHandle) and its grid X, Y, Z
+    void *fft_plan = nullptr;
+    long long fft_dims[3] = {0, 0, 0};
+
     void *wp(size_t o) const { return ws + o; }
     double *scal() const { return (double *)(ws + off.scal); }
     double *abar() const { return scal(); }          // scal[0..2]
@@ -74,4 +78,5 @@ int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...);
     } while (0)
 
 int sensor_infer_impl(dg_ctx *c, const void *u);
+void stats_release(dg_ctx *c);
 int sensor_reset_flags(dg_ctx *c);

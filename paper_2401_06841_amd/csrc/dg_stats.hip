@@ -14,9 +14,12 @@
 //
 // Layout for the random gathers: the state is first copied to one record per cell,
 // [cell][var][mode] in FP64 (4 nb doubles, 16-byte aligned), so a point reads one
-// contiguous record instead of 4 nb separate cache lines.  Sums are per thread, per block
-// (fixed tree) and over blocks in a fixed order, so the structure function is
-// deterministic.  The spectrum bins shell energies with LDS atomics inside a block (the
+// contiguous record instead of 4 nb separate cache lines.  The pair kernel runs one wave
+// per block and stages the 64 records of its lanes' points through LDS: consecutive lanes
+// load consecutive 16-byte pieces of the same records, so every cache line of a record is
+// fetched by one instruction instead of by 2 nb per-lane loads spread over time.  Sums are
+// per lane, per wave (fixed tree) and over blocks in a fixed order, so the structure
+// function is deterministic.  The spectrum bins shell energies with LDS atomics inside a block (the
 // order of additions inside a block is not fixed; blocks are summed in a fixed order).
 #include <hip/hip_runtime.h>
 #include <hipfft/hipfft.h>
@@ -31,7 +34,8 @@
 
 namespace dg {
 
-constexpr int SF_CHUNKS = 64;       // blocks per bin of the pair kernel
+constexpr int SF_CHUNKS = 256;      // blocks (one wave each) per bin of the pair kernel
+constexpr int SFB = 64;             // threads per block of the pair kernel
 constexpr int SP_BLOCKS = 1024;     // blocks of the shell kernel
 constexpr int SF_MAX_BINS = 65535;  // grid y limit
 constexpr int SP_MAX_SHELLS = 4096; // LDS histogram of the shell kernel (32 KiB)
@@ -70,16 +74,11 @@ __device__ __forceinline__ void legendre_row(double x, double (&L)[K + 1])
     }
 }
 
-// v = m / max(rho, floor) at x from the cell record that holds x
-template <int K>
-__device__ __forceinline__ void velocity_at(const double *cells, const StatsGeom &g, const double (&x)[3],
-                                            double (&v)[3])
+// cell that holds x and the reference coordinates of x in it
+__device__ __forceinline__ int locate(const StatsGeom &g, const double (&x)[3], double (&xi)[3])
 {
-    constexpr int NB = Shape<K>::NB;
-    constexpr Modes<K> M = make_modes<K>();
     const int n[3] = {g.nx, g.ny, g.nz};
     int ijk[3];
-    double xi[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const double s = x[a] / g.h;
@@ -88,12 +87,20 @@ __device__ __forceinline__ void velocity_at(const double *cells, const StatsGeom
         ijk[a] = i;
         xi[a] = 2.0 * (s - i) - 1.0;
     }
+    return ijk[0] + g.nx * (ijk[1] + g.ny * ijk[2]);
+}
+
+// v = m / max(rho, floor) at reference point xi of the cell record w[var][mode]
+template <int K>
+__device__ __forceinline__ void velocity_from_record(const double2 *rec, const double (&xi)[3], double floor_,
+                                                     double (&v)[3])
+{
+    constexpr int NB = Shape<K>::NB;
+    constexpr Modes<K> M = make_modes<K>();
     double Lx[K + 1], Ly[K + 1], Lz[K + 1];
     legendre_row<K>(xi[0], Lx);
     legendre_row<K>(xi[1], Ly);
     legendre_row<K>(xi[2], Lz);
-    const size_t c = (size_t)ijk[0] + (size_t)g.nx * ((size_t)ijk[1] + (size_t)g.ny * ijk[2]);
-    const double2 *rec = (const double2 *)(cells + c * 4 * NB);
     double w[4 * NB];
 #pragma unroll
     for (int i = 0; i < 2 * NB; ++i) {
@@ -110,40 +117,57 @@ __device__ __forceinline__ void velocity_at(const double *cells, const StatsGeom
         m1 += w[2 * NB + l] * phi;
         m2 += w[3 * NB + l] * phi;
     }
-    r = fmax(r, g.floor);
+    r = fmax(r, floor_);
     v[0] = m0 / r;
     v[1] = m1 / r;
     v[2] = m2 / r;
 }
 
-// [var][mode][cell] (T) -> [cell][var][mode] (FP64)
+// [var][mode][cell] (T) -> [cell][var][mode] (FP64) through an LDS tile of 64 cells: the
+// reads run along cells and the writes along the contiguous records of the 64 cells
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_cell_records(const void *u_, int nc, double *cells)
 {
-    constexpr int NB = Shape<K>::NB;
-    const int c = blockIdx.x * BLOCK + threadIdx.x;
-    if (c >= nc) return;
+    constexpr int NR = 4 * Shape<K>::NB;    // doubles per record
+    constexpr int TC = 64;                  // cells per block
+    __shared__ double tile[NR][TC + 1];
     const T *u = (const T *)u_;
-    double *r = cells + (size_t)c * 4 * NB;
-#pragma unroll
-    for (int i = 0; i < 4 * NB; ++i) r[i] = (double)u[(size_t)i * nc + c];
+    const int c0 = blockIdx.x * TC;
+    const int ncb = nc - c0 < TC ? nc - c0 : TC;
+    for (int idx = threadIdx.x; idx < NR * TC; idx += BLOCK) {
+        const int i = idx / TC, t = idx - i * TC;
+        if (t < ncb) tile[i][t] = (double)u[(size_t)i * nc + c0 + t];
+    }
+    __syncthreads();
+    double *out = cells + (size_t)c0 * NR;
+    for (int q = threadIdx.x; q < NR * ncb; q += BLOCK) {
+        const int t = q / NR, i = q - t * NR;
+        out[q] = tile[i][t];
+    }
 }
 
-// grid (chunks, bins): block (x, b) sums |dv|^2 over the pairs j = x BLOCK + t + m chunks BLOCK
+// grid (chunks, bins), one wave per block: block (x, b) takes the pairs j = j0 + lane,
+// j0 = x 64, x 64 + chunks 64, ...; lanes past npairs repeat the block's first pair and
+// are not summed
 template <int K>
-__global__ void __launch_bounds__(BLOCK) k_sf_pairs(const double *cells, StatsGeom g, const double *lb,
-                                                    long long npairs, unsigned long long seed, double *part)
+__global__ void __launch_bounds__(SFB) k_sf_pairs(const double *cells, StatsGeom g, const double *lb,
+                                                  long long npairs, unsigned long long seed, double *part)
 {
-    __shared__ double lds[4 * 4];
+    constexpr int R2 = 2 * Shape<K>::NB;    // 16-byte pieces per record
+    __shared__ double2 rec[SFB * R2];
     const int b = blockIdx.y;
+    const int lane = threadIdx.x;
     const double l = lb[b];
     const double L[3] = {g.Lx, g.Ly, g.Lz};
+    const double2 *src = (const double2 *)cells;
     double sum = 0.0;
-    for (long long j = (long long)blockIdx.x * BLOCK + threadIdx.x; j < npairs; j += (long long)gridDim.x * BLOCK) {
-        const unsigned long long base = ((unsigned long long)b * (unsigned long long)npairs + (unsigned long long)j) * 256ull;
-        double x1[3], x2[3];
+    for (long long j0 = (long long)blockIdx.x * SFB; j0 < npairs; j0 += (long long)gridDim.x * SFB) {
+        const bool act = j0 + lane < npairs;
+        const unsigned long long j = (unsigned long long)(act ? j0 + lane : j0);
+        const unsigned long long base = ((unsigned long long)b * (unsigned long long)npairs + j) * 256ull;
+        double x[2][3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) x1[a] = uniform01(seed, base + a) * L[a];
+        for (int a = 0; a < 3; ++a) x[0][a] = uniform01(seed, base + a) * L[a];
         double n0 = 0.0, n1 = 0.0, n2 = 1.0;
         for (int t = 0; t < 84; ++t) {
             const double c0 = 2.0 * uniform01(seed, base + 3 + 3 * t) - 1.0;
@@ -161,20 +185,33 @@ __global__ void __launch_bounds__(BLOCK) k_sf_pairs(const double *cells, StatsGe
         const double nn[3] = {n0, n1, n2};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double y = fma(l, nn[a], x1[a]);
+            double y = fma(l, nn[a], x[0][a]);
             if (y >= L[a]) y -= L[a];
             else if (y < 0.0) y += L[a];
-            x2[a] = y;
+            x[1][a] = y;
         }
-        double v1[3], v2[3];
-        velocity_at<K>(cells, g, x1, v1);
-        velocity_at<K>(cells, g, x2, v2);
+        double v[2][3];
+#pragma unroll 1
+        for (int pt = 0; pt < 2; ++pt) {
+            double xi[3];
+            const int c = locate(g, x[pt], xi);
+            __syncthreads();                        // the previous point's records are consumed
 #pragma unroll
-        for (int d = 0; d < 3; ++d) sum += (v1[d] - v2[d]) * (v1[d] - v2[d]);
+            for (int s = 0; s < R2; ++s) {
+                const int item = s * SFB + lane;
+                const int r = item / R2, o = item - r * R2;
+                const int cr = __shfl(c, r, 64);
+                rec[item] = src[(size_t)cr * R2 + o];
+            }
+            __syncthreads();
+            velocity_from_record<K>(rec + lane * R2, xi, g.floor, v[pt]);
+        }
+        if (act)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sum += (v[0][d] - v[1][d]) * (v[0][d] - v[1][d]);
     }
-    double acc[1] = {sum};
-    block_sum<1>(acc, lds);
-    if (threadIdx.x == 0) part[(size_t)b * gridDim.x + blockIdx.x] = acc[0];
+    sum = wave_sum(sum);
+    if (lane == 0) part[(size_t)b * gridDim.x + blockIdx.x] = sum;
 }
 
 // out[b] = (sum over the chunks of bin b, in order) / npairs
@@ -255,13 +292,15 @@ static __global__ void __launch_bounds__(BLOCK) k_shells(const double2 *F, long 
     for (int s = threadIdx.x; s < nshell; s += BLOCK) part[(size_t)blockIdx.x * nshell + s] = hist[s];
 }
 
-static __global__ void k_shells_final(const double *part, int nblk, int nshell, double *out)
+// one block per shell: fixed strided partial sums, then the fixed block tree
+static __global__ void __launch_bounds__(BLOCK) k_shells_final(const double *part, int nblk, int nshell, double *out)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nshell) return;
-    double t = 0.0;
-    for (int b = 0; b < nblk; ++b) t += part[(size_t)b * nshell + s];
-    out[s] = t;
+    __shared__ double lds[4 * 4];
+    const int s = blockIdx.x;
+    double t[1] = {0.0};
+    for (int b = threadIdx.x; b < nblk; b += BLOCK) t[0] += part[(size_t)b * nshell + s];
+    block_sum<1>(t, lds);
+    if (threadIdx.x == 0) out[s] = t[0];
 }
 
 }  // namespace dg
@@ -352,12 +391,11 @@ int launch_sf(dg_ctx *c, const void *u, int nbins, long long npairs, unsigned lo
     double *part = (double *)(scr + s.part);
     double *out = (double *)(scr + s.out);
     HIPCHK(c, hipMemcpyAsync(lb, lb_host, (size_t)nbins * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    hipLaunchKernelGGL((k_cell_records<T, K>), dim3((c->nc + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream, u, c->nc,
-                       cells);
+    hipLaunchKernelGGL((k_cell_records<T, K>), dim3((c->nc + 63) / 64), dim3(BLOCK), 0, c->stream, u, c->nc, cells);
     LAUNCHCHK(c);
-    const long long need = (npairs + BLOCK - 1) / BLOCK;
+    const long long need = (npairs + SFB - 1) / SFB;
     const int chunks = (int)(need < SF_CHUNKS ? need : SF_CHUNKS);
-    hipLaunchKernelGGL((k_sf_pairs<K>), dim3(chunks, nbins), dim3(BLOCK), 0, c->stream, (const double *)cells, g,
+    hipLaunchKernelGGL((k_sf_pairs<K>), dim3(chunks, nbins), dim3(SFB), 0, c->stream, (const double *)cells, g,
                        (const double *)lb, npairs, seed, part);
     LAUNCHCHK(c);
     hipLaunchKernelGGL(k_sf_final, dim3((nbins + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
@@ -389,7 +427,35 @@ int fft_fail(dg_ctx *c, const char *what, hipfftResult r)
     return dg_fail(c, DG_EHIP, "%s failed: hipfftResult %d", what, (int)r);
 }
 
+// the context's real-to-complex plan for an X x Y x Z grid (made once per grid shape)
+int fft_plan(dg_ctx *c, const SpLayout &s, hipfftHandle *out)
+{
+    if (c->fft_plan && c->fft_dims[0] == s.X && c->fft_dims[1] == s.Y && c->fft_dims[2] == s.Z) {
+        *out = (hipfftHandle)c->fft_plan;
+        return DG_OK;
+    }
+    stats_release(c);
+    hipfftHandle plan;
+    const hipfftResult fr = hipfftPlan3d(&plan, (int)s.Z, (int)s.Y, (int)s.X, HIPFFT_D2Z);
+    if (fr != HIPFFT_SUCCESS) return fft_fail(c, "hipfftPlan3d", fr);
+    c->fft_plan = (void *)plan;
+    c->fft_dims[0] = s.X;
+    c->fft_dims[1] = s.Y;
+    c->fft_dims[2] = s.Z;
+    *out = plan;
+    return DG_OK;
+}
+
 }  // namespace
+
+void stats_release(dg_ctx *c)
+{
+    if (c->fft_plan) {
+        (void)hipStreamSynchronize(c->stream);
+        hipfftDestroy((hipfftHandle)c->fft_plan);
+        c->fft_plan = nullptr;
+    }
+}
 
 int dg_sf_bins(const dg_ctx *c, int nbins, double *l_host)
 {
@@ -463,14 +529,12 @@ int dg_velocity_spectrum(dg_ctx *c, const void *u, int p, void *scratch, size_t 
     rc = STATS_DISPATCH(c, launch_grid, c, u, p, grid, s.npts);
     if (rc) return rc;
     hipfftHandle plan;
-    hipfftResult fr = hipfftPlan3d(&plan, (int)s.Z, (int)s.Y, (int)s.X, HIPFFT_D2Z);
-    if (fr != HIPFFT_SUCCESS) return fft_fail(c, "hipfftPlan3d", fr);
-    fr = hipfftSetStream(plan, c->stream);
+    if ((rc = fft_plan(c, s, &plan))) return rc;
+    hipfftResult fr = hipfftSetStream(plan, c->stream);
     for (int d = 0; d < 3 && fr == HIPFFT_SUCCESS; ++d)
         fr = hipfftExecD2Z(plan, grid + (size_t)d * s.npts, (hipfftDoubleComplex *)(cplx + (size_t)d * s.M));
     if (fr != HIPFFT_SUCCESS) {
-        (void)hipStreamSynchronize(c->stream);
-        hipfftDestroy(plan);
+        stats_release(c);
         return fft_fail(c, "hipfftExecD2Z", fr);
     }
     const long long need = (s.M + BLOCK - 1) / BLOCK;
@@ -479,14 +543,13 @@ int dg_velocity_spectrum(dg_ctx *c, const void *u, int p, void *scratch, size_t 
                        (const double2 *)cplx, s.X, s.Y, s.Z, s.nshell, part);
     hipError_t le = hipGetLastError();
     if (le == hipSuccess) {
-        hipLaunchKernelGGL(k_shells_final, dim3((s.nshell + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
-                           (const double *)part, nblk, s.nshell, out);
+        hipLaunchKernelGGL(k_shells_final, dim3(s.nshell), dim3(BLOCK), 0, c->stream, (const double *)part, nblk,
+                           s.nshell, out);
         le = hipGetLastError();
     }
     if (le == hipSuccess)
         le = hipMemcpyAsync(e_host, out, (size_t)s.nshell * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     const hipError_t se = hipStreamSynchronize(c->stream);
-    hipfftDestroy(plan);
     if (le != hipSuccess) return dg_fail(c, DG_EHIP, "spectrum kernels failed: %s", hipGetErrorString(le));
     if (se != hipSuccess) return dg_fail(c, DG_EHIP, "hipStreamSynchronize failed: %s", hipGetErrorString(se));
     return DG_OK;
