@@ -129,18 +129,6 @@ def _summary(args, sim, precision, wall, prof, retries, dt_min):
     return out
 
 
-def _sonic_scale(l, mach_l):
-    """Separation where M(l) = v(l)/cs first reaches 1 from below (log-log interpolation
-    between bins), or None."""
-    import numpy as np
-    up = np.nonzero(mach_l >= 1.0)[0]
-    if up.size == 0 or up[0] == 0:
-        return None
-    i = up[0]
-    t = np.log(1.0 / mach_l[i - 1]) / np.log(mach_l[i] / mach_l[i - 1])
-    return float(np.exp(np.log(l[i - 1]) + t * np.log(l[i] / l[i - 1])))
-
-
 def _statistics(sim):
     """Flow statistics of the final state on the GPU (Sec. 4.3), timed: the structure
     function with 100 bins of 1e5 pairs and the spectrum on the N p grid (p = k+1).  Each
@@ -170,7 +158,7 @@ def _statistics(sim):
         "record_bytes_per_pair": 2 * rec_bytes, "record_GB_per_s": 2 * rec_bytes * pairs / t_sf / 1e9,
         "l_min": float(l[0]), "l_max": float(l[-1]),
         "mach_at_l_min": float(mach_l[0]), "mach_at_l_max": float(mach_l[-1]),
-        "sonic_scale": _sonic_scale(l, mach_l)}
+        "sonic_scale": analysis.sonic_scale(l, mach_l)}
     npts = (sim.cfg.nx * p) * (sim.cfg.ny * p) * (sim.cfg.nz * p)
     out["spectrum"] = {"samples_per_cell": p, "grid_points": npts, "ms": 1e3 * t_sp, "shells": len(e),
                        "half_v2": float(e.sum())}

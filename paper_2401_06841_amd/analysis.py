@@ -125,6 +125,60 @@ def gpu_structure_function(ctx, u, nbins: int = SF_BINS, npairs: int = SF_PAIRS,
     return dg.dg_sf_bins(ctx, nbins), np.sqrt(0.5 * dg.dg_structure_function(ctx, u, nbins, npairs, seed))
 
 
+def loglog_slope(x, y, lo: float, hi: float) -> float:
+    """Least-squares slope of log y against log x over lo <= x <= hi (the paper fits v(l)
+    between 0.1 and 0.25 of the box, Sec. 5)."""
+    x, y = np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64)
+    sel = (x >= lo) & (x <= hi) & (y > 0)
+    if sel.sum() < 2:
+        return float("nan")
+    return float(np.polyfit(np.log(x[sel]), np.log(y[sel]), 1)[0])
+
+
+def sonic_scale(l, v, cs: float = 1.0):
+    """Separation where M(l) = v(l)/cs first reaches 1 from below, interpolated linearly in
+    log l and log M between bins; None when M(l) does not cross 1 inside the bins."""
+    l, m = np.asarray(l, dtype=np.float64), np.asarray(v, dtype=np.float64) / cs
+    up = np.nonzero(m >= 1.0)[0]
+    if up.size == 0 or up[0] == 0:
+        return None
+    i = up[0]
+    t = np.log(1.0 / m[i - 1]) / np.log(m[i] / m[i - 1])
+    return float(np.exp(np.log(l[i - 1]) + t * np.log(l[i] / l[i - 1])))
+
+
+class StatisticsSeries:
+    """Structure functions and spectra of one run measured on the GPU at the caller's
+    output times, summarised as the mean and the 1-sigma spread over the measurements (the
+    paper averages 96 measurements over five eddy turnover times, Sec. 4.3).  Measurement i
+    draws its pairs from stream seed + i, so every measurement uses fresh pairs."""
+
+    def __init__(self, ctx, nbins: int = SF_BINS, npairs: int = SF_PAIRS, p: int | None = None,
+                 seed: int = SF_SEED):
+        import torch
+
+        from . import dg
+        self.ctx, self.nbins, self.npairs, self.seed = ctx, nbins, npairs, seed
+        self.p = p or ctx.cfg.degree + 1
+        self.l = dg.dg_sf_bins(ctx, nbins)
+        self.scratch = torch.empty(dg.dg_stats_scratch_bytes(ctx, nbins, self.p), dtype=torch.uint8,
+                                   device=ctx.device)
+        self.v, self.e = [], []
+
+    def measure(self, u):
+        from . import dg
+        s2 = dg.dg_structure_function(self.ctx, u, self.nbins, self.npairs, self.seed + len(self.v),
+                                      scratch=self.scratch)
+        self.v.append(np.sqrt(0.5 * s2))
+        self.e.append(dg.dg_velocity_spectrum(self.ctx, u, self.p, scratch=self.scratch))
+
+    def summary(self):
+        """{"l", "v_mean", "v_std", "E_mean", "E_std", "n"} over the measurements so far."""
+        v, e = np.array(self.v), np.array(self.e)
+        return {"l": self.l, "v_mean": v.mean(0), "v_std": v.std(0), "E_mean": e.mean(0), "E_std": e.std(0),
+                "n": len(self.v)}
+
+
 def log_distance(a, b) -> float:
     """Mean |log10 a - log10 b| over the entries where both are positive."""
     a, b = np.asarray(a), np.asarray(b)

@@ -13,11 +13,13 @@
 // lands in the same cells on any IEEE machine.
 //
 // Layout for the random gathers: the state is first copied to one record per cell,
-// [cell][var][mode] in FP64 (4 nb doubles, 16-byte aligned), so a point reads one
-// contiguous record instead of 4 nb separate cache lines.  The pair kernel runs one wave
-// per block and stages the 64 records of its lanes' points through LDS: consecutive lanes
-// load consecutive 16-byte pieces of the same records, so every cache line of a record is
-// fetched by one instruction instead of by 2 nb per-lane loads spread over time.  Sums are
+// [cell][var][mode] in the state's precision (4 nb values, 16-byte aligned), so a point
+// reads one contiguous record instead of 4 nb separate cache lines; the evaluation is FP64.
+// The pair kernel runs one wave per block and stages the records of its 64 lanes' points
+// through LDS: consecutive lanes load consecutive 16-byte pieces of the same records, so
+// every cache line of a record is fetched by one instruction instead of by per-lane loads
+// spread over time.  Records above 320 bytes (FP64 at degree 3) are staged in two halves
+// (rho, m_x then m_y, m_z) so that 20 KB of LDS per wave keeps two waves per SIMD.  Sums are
 // per lane, per wave (fixed tree) and over blocks in a fixed order, so the structure
 // function is deterministic.  The spectrum bins shell energies with LDS atomics inside a block (the
 // order of additions inside a block is not fixed; blocks are summed in a fixed order).
@@ -90,56 +92,36 @@ __device__ __forceinline__ int locate(const StatsGeom &g, const double (&x)[3], 
     return ijk[0] + g.nx * (ijk[1] + g.ny * ijk[2]);
 }
 
-// v = m / max(rho, floor) at reference point xi of the cell record w[var][mode]
+// phi_l(xi) of every mode, FP64
 template <int K>
-__device__ __forceinline__ void velocity_from_record(const double2 *rec, const double (&xi)[3], double floor_,
-                                                     double (&v)[3])
+__device__ __forceinline__ void basis_at(const double (&xi)[3], double (&phi)[Shape<K>::NB])
 {
-    constexpr int NB = Shape<K>::NB;
     constexpr Modes<K> M = make_modes<K>();
     double Lx[K + 1], Ly[K + 1], Lz[K + 1];
     legendre_row<K>(xi[0], Lx);
     legendre_row<K>(xi[1], Ly);
     legendre_row<K>(xi[2], Lz);
-    double w[4 * NB];
 #pragma unroll
-    for (int i = 0; i < 2 * NB; ++i) {
-        const double2 t = rec[i];
-        w[2 * i] = t.x;
-        w[2 * i + 1] = t.y;
-    }
-    double r = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0;
-#pragma unroll
-    for (int l = 0; l < NB; ++l) {
-        const double phi = Lx[M.e[l][0]] * Ly[M.e[l][1]] * Lz[M.e[l][2]];
-        r += w[l] * phi;
-        m0 += w[NB + l] * phi;
-        m1 += w[2 * NB + l] * phi;
-        m2 += w[3 * NB + l] * phi;
-    }
-    r = fmax(r, floor_);
-    v[0] = m0 / r;
-    v[1] = m1 / r;
-    v[2] = m2 / r;
+    for (int l = 0; l < Shape<K>::NB; ++l) phi[l] = Lx[M.e[l][0]] * Ly[M.e[l][1]] * Lz[M.e[l][2]];
 }
 
-// [var][mode][cell] (T) -> [cell][var][mode] (FP64) through an LDS tile of 64 cells: the
-// reads run along cells and the writes along the contiguous records of the 64 cells
+// [var][mode][cell] -> [cell][var][mode] (element type T) through an LDS tile of 64 cells:
+// the reads run along cells and the writes along the contiguous records of the 64 cells
 template <typename T, int K>
-__global__ void __launch_bounds__(BLOCK) k_cell_records(const void *u_, int nc, double *cells)
+__global__ void __launch_bounds__(BLOCK) k_cell_records(const void *u_, int nc, T *cells)
 {
-    constexpr int NR = 4 * Shape<K>::NB;    // doubles per record
+    constexpr int NR = 4 * Shape<K>::NB;    // values per record
     constexpr int TC = 64;                  // cells per block
-    __shared__ double tile[NR][TC + 1];
+    __shared__ T tile[NR][TC + 1];
     const T *u = (const T *)u_;
     const int c0 = blockIdx.x * TC;
     const int ncb = nc - c0 < TC ? nc - c0 : TC;
     for (int idx = threadIdx.x; idx < NR * TC; idx += BLOCK) {
         const int i = idx / TC, t = idx - i * TC;
-        if (t < ncb) tile[i][t] = (double)u[(size_t)i * nc + c0 + t];
+        if (t < ncb) tile[i][t] = u[(size_t)i * nc + c0 + t];
     }
     __syncthreads();
-    double *out = cells + (size_t)c0 * NR;
+    T *out = cells + (size_t)c0 * NR;
     for (int q = threadIdx.x; q < NR * ncb; q += BLOCK) {
         const int t = q / NR, i = q - t * NR;
         out[q] = tile[i][t];
@@ -149,17 +131,23 @@ __global__ void __launch_bounds__(BLOCK) k_cell_records(const void *u_, int nc, 
 // grid (chunks, bins), one wave per block: block (x, b) takes the pairs j = j0 + lane,
 // j0 = x 64, x 64 + chunks 64, ...; lanes past npairs repeat the block's first pair and
 // are not summed
-template <int K>
-__global__ void __launch_bounds__(SFB) k_sf_pairs(const double *cells, StatsGeom g, const double *lb,
+template <int K, typename RT>
+__global__ void __launch_bounds__(SFB) __attribute__((amdgpu_waves_per_eu(2))) k_sf_pairs(const RT *cells, StatsGeom g, const double *lb,
                                                   long long npairs, unsigned long long seed, double *part)
 {
-    constexpr int R2 = 2 * Shape<K>::NB;    // 16-byte pieces per record
-    __shared__ double2 rec[SFB * R2];
+    constexpr int NB = Shape<K>::NB;
+    constexpr int RECB = 4 * NB * (int)sizeof(RT);          // bytes per record
+    constexpr int VPP = RECB > 320 ? 2 : 4;                  // variables staged per phase
+    constexpr int NPH = 4 / VPP;
+    constexpr int PIECES = VPP * NB * (int)sizeof(RT) / 16;  // 16-byte pieces per phase
+    constexpr int RECP = RECB / 16;
+    static_assert(RECB % 16 == 0 && (VPP * NB * (int)sizeof(RT)) % 16 == 0, "records in 16-byte pieces");
+    __shared__ uint4 rec[SFB * PIECES];
     const int b = blockIdx.y;
     const int lane = threadIdx.x;
     const double l = lb[b];
     const double L[3] = {g.Lx, g.Ly, g.Lz};
-    const double2 *src = (const double2 *)cells;
+    const uint4 *src = (const uint4 *)cells;
     double sum = 0.0;
     for (long long j0 = (long long)blockIdx.x * SFB; j0 < npairs; j0 += (long long)gridDim.x * SFB) {
         const bool act = j0 + lane < npairs;
@@ -193,18 +181,31 @@ __global__ void __launch_bounds__(SFB) k_sf_pairs(const double *cells, StatsGeom
         double v[2][3];
 #pragma unroll 1
         for (int pt = 0; pt < 2; ++pt) {
-            double xi[3];
+            double xi[3], phi[NB];
             const int c = locate(g, x[pt], xi);
-            __syncthreads();                        // the previous point's records are consumed
+            basis_at<K>(xi, phi);
+            double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int s = 0; s < R2; ++s) {
-                const int item = s * SFB + lane;
-                const int r = item / R2, o = item - r * R2;
-                const int cr = __shfl(c, r, 64);
-                rec[item] = src[(size_t)cr * R2 + o];
+            for (int ph = 0; ph < NPH; ++ph) {
+                __syncthreads();                    // the previous records are consumed
+#pragma unroll
+                for (int s = 0; s < PIECES; ++s) {
+                    const int item = s * SFB + lane;
+                    const int r = item / PIECES, o = item - r * PIECES;
+                    const int cr = __shfl(c, r, 64);
+                    rec[item] = src[(size_t)cr * RECP + ph * PIECES + o];
+                }
+                __syncthreads();
+                const RT *w = (const RT *)(rec + lane * PIECES);
+#pragma unroll
+                for (int vv = 0; vv < VPP; ++vv)
+#pragma unroll
+                    for (int m = 0; m < NB; ++m) acc[ph * VPP + vv] += (double)w[vv * NB + m] * phi[m];
             }
-            __syncthreads();
-            velocity_from_record<K>(rec + lane * R2, xi, g.floor, v[pt]);
+            const double rho = fmax(acc[0], g.floor);
+            v[pt][0] = acc[1] / rho;
+            v[pt][1] = acc[2] / rho;
+            v[pt][2] = acc[3] / rho;
         }
         if (act)
 #pragma unroll
@@ -229,7 +230,6 @@ template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_velocity_grid(const void *u_, StatsGeom g, int p, double *grid)
 {
     constexpr int NB = Shape<K>::NB;
-    constexpr Modes<K> M = make_modes<K>();
     const long long X = (long long)g.nx * p, Y = (long long)g.ny * p, Z = (long long)g.nz * p;
     const long long npts = X * Y * Z;
     const long long o = (long long)blockIdx.x * BLOCK + threadIdx.x;
@@ -242,20 +242,17 @@ __global__ void __launch_bounds__(BLOCK) k_velocity_grid(const void *u_, StatsGe
         ijk[a] = (int)(gg[a] / p);
         xi[a] = -1.0 + (2.0 * (double)(gg[a] % p) + 1.0) / p;
     }
-    double Lx[K + 1], Ly[K + 1], Lz[K + 1];
-    legendre_row<K>(xi[0], Lx);
-    legendre_row<K>(xi[1], Ly);
-    legendre_row<K>(xi[2], Lz);
+    double phi[NB];
+    basis_at<K>(xi, phi);
     const size_t nc = (size_t)g.nx * g.ny * g.nz;
     const size_t c = (size_t)ijk[0] + (size_t)g.nx * ((size_t)ijk[1] + (size_t)g.ny * ijk[2]);
     const T *u = (const T *)u_;
     double r = 0.0, m[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int l = 0; l < NB; ++l) {
-        const double phi = Lx[M.e[l][0]] * Ly[M.e[l][1]] * Lz[M.e[l][2]];
-        r += (double)u[(size_t)l * nc + c] * phi;
+        r += (double)u[(size_t)l * nc + c] * phi[l];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) m[d] += (double)u[((size_t)(1 + d) * NB + l) * nc + c] * phi;
+        for (int d = 0; d < 3; ++d) m[d] += (double)u[((size_t)(1 + d) * NB + l) * nc + c] * phi[l];
     }
     r = fmax(r, g.floor);
 #pragma unroll
@@ -333,7 +330,7 @@ SfLayout sf_layout(const dg_ctx *c, int nbins)
 {
     SfLayout s;
     size_t o = 0;
-    s.cells = o; o += up256((size_t)c->nc * 4 * c->nb * sizeof(double));
+    s.cells = o; o += up256((size_t)c->nc * 4 * c->nb * c->es);
     s.lb = o; o += up256((size_t)nbins * sizeof(double));
     s.part = o; o += up256((size_t)nbins * SF_CHUNKS * sizeof(double));
     s.out = o; o += up256((size_t)nbins * sizeof(double));
@@ -386,7 +383,7 @@ int launch_sf(dg_ctx *c, const void *u, int nbins, long long npairs, unsigned lo
               const SfLayout &s, const double *lb_host)
 {
     const StatsGeom g = geom_of(c);
-    double *cells = (double *)(scr + s.cells);
+    T *cells = (T *)(scr + s.cells);
     double *lb = (double *)(scr + s.lb);
     double *part = (double *)(scr + s.part);
     double *out = (double *)(scr + s.out);
@@ -395,7 +392,7 @@ int launch_sf(dg_ctx *c, const void *u, int nbins, long long npairs, unsigned lo
     LAUNCHCHK(c);
     const long long need = (npairs + SFB - 1) / SFB;
     const int chunks = (int)(need < SF_CHUNKS ? need : SF_CHUNKS);
-    hipLaunchKernelGGL((k_sf_pairs<K>), dim3(chunks, nbins), dim3(SFB), 0, c->stream, (const double *)cells, g,
+    hipLaunchKernelGGL((k_sf_pairs<K, T>), dim3(chunks, nbins), dim3(SFB), 0, c->stream, (const T *)cells, g,
                        (const double *)lb, npairs, seed, part);
     LAUNCHCHK(c);
     hipLaunchKernelGGL(k_sf_final, dim3((nbins + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,

@@ -65,3 +65,18 @@ def test_compare_of_a_state_with_itself():
                                          0 * x[..., 0], 0 * x[..., 0]]))
     c = analysis.compare(u, u, k, (n, n, n))
     assert c["l2_rel_rho"] == 0.0 and c["density_pdf_l1"] == 0.0 and c["spectrum_log10_mean_abs"] == 0.0
+
+
+def test_loglog_slope_of_power_laws():
+    l = np.geomspace(0.01, 0.5, 40)
+    assert analysis.loglog_slope(l, 3.0 * l ** 0.5, 0.1, 0.25) == pytest.approx(0.5, abs=1e-12)
+    assert analysis.loglog_slope(l, 0.2 * l ** (1 / 3), 0.1, 0.25) == pytest.approx(1 / 3, abs=1e-12)
+    assert np.isnan(analysis.loglog_slope(l, l, 0.3, 0.31))          # fewer than two points
+
+
+def test_sonic_scale_of_a_power_law():
+    l = np.geomspace(0.005, 0.5, 100)
+    v = 4.0 * (l / 0.5) ** 0.5                       # M(l) = 1 at l = 0.5 / 16
+    assert analysis.sonic_scale(l, v) == pytest.approx(0.5 / 16, rel=1e-12)
+    assert analysis.sonic_scale(l, 0.5 * np.ones_like(l)) is None    # subsonic everywhere
+    assert analysis.sonic_scale(l, 2.0 * np.ones_like(l)) is None    # supersonic at every bin

@@ -32,9 +32,11 @@ SF_CASES = {
     "8c-k2-fp64": (8, 8, 8, 2, dg.DG_FP64, 12, 3000),
     "8c-k2-fp32": (8, 8, 8, 2, dg.DG_FP32, 12, 3000),
     "8c-k1-fp64": (8, 8, 8, 1, dg.DG_FP64, 7, 2000),
-    "8c-k3-fp64": (8, 8, 8, 3, dg.DG_FP64, 7, 2000),
+    "8c-k3-fp64": (8, 8, 8, 3, dg.DG_FP64, 7, 2000),            # records staged in two halves
+    "8c-k1-fp32": (8, 8, 8, 1, dg.DG_FP32, 7, 2000),
+    "8c-k3-fp32": (8, 8, 8, 3, dg.DG_FP32, 7, 2000),
     "noncubic-k2": (6, 5, 4, 2, dg.DG_FP64, 9, 1500),
-    "strided-pairs": (10, 10, 10, 2, dg.DG_FP64, 3, 40000),     # > 64 blocks x 256 pairs per bin
+    "strided-pairs": (10, 10, 10, 2, dg.DG_FP64, 3, 40000),     # > 256 one-wave blocks x 64 pairs per bin
     "one-pair-one-bin": (4, 4, 4, 2, dg.DG_FP64, 1, 1),
 }
 
@@ -144,3 +146,22 @@ def test_statistics_reject_bad_arguments():
     one = make(1, 4, 4, 1, FLAGS)                   # 1 x 4 x 4 grid at p = 1: too thin
     with pytest.raises(dg.DGError):
         dg.dg_velocity_spectrum(one, dev(np.zeros(one.cfg.shape) + 1.0, one), 1)
+
+
+def test_statistics_series_mean_and_spread():
+    """Measurement i of a series uses pair stream seed + i; the mean and spread are those of
+    the individual calls."""
+    from paper_2401_06841_amd import analysis
+    n, k = 8, 2
+    ctx = make(n, n, n, k, FLAGS)
+    u = dev(_state(n, n, n, k, dg.DG_FP64, seed=5), ctx)
+    ser = analysis.StatisticsSeries(ctx, nbins=6, npairs=2000, seed=40)
+    for _ in range(3):
+        ser.measure(u)
+    s = ser.summary()
+    single = [np.sqrt(0.5 * dg.dg_structure_function(ctx, u, 6, 2000, 40 + i)) for i in range(3)]
+    assert s["n"] == 3
+    assert np.allclose(s["v_mean"], np.mean(single, 0), rtol=1e-14)
+    assert np.allclose(s["v_std"], np.std(single, 0), rtol=1e-12, atol=1e-15)
+    assert np.all(s["v_std"] > 0)                   # fresh pairs per measurement
+    assert np.all(s["E_std"] <= 1e-12 * s["E_mean"].sum())   # same state: same spectrum
