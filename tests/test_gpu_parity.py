@@ -74,6 +74,24 @@ def test_rhs_fp32(k):
     assert max(e) < TOL[dg.DG_FP32], e
 
 
+# Meshes whose x lines are whole waves, where the face sharing between the lanes of a block
+# applies along x (and along y for the lines of a block but the last), in both precisions:
+# several lines per block (64 x 4 x 6, 64 x 8 x 4), two 128-cell lines per block
+# (128 x 2 x 2, 128 x 2 x 3), an odd count of lines (64 x 6 x 5) and a single line smaller
+# than one block (64 x 1 x 1).
+LINE_MESHES = [((64, 4, 6), dg.DG_FP64), ((64, 8, 4), dg.DG_FP32), ((128, 2, 2), dg.DG_FP64),
+               ((64, 6, 5), dg.DG_FP64), ((128, 2, 3), dg.DG_FP32), ((64, 1, 1), dg.DG_FP64)]
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("mesh,precision", LINE_MESHES)
+def test_rhs_whole_line_meshes(k, mesh, precision):
+    print(f"rhs whole-line mesh k={k} mesh={mesh} precision={precision}", flush=True)
+    modes = synthetic.forcing_table(5, amp=5.0)
+    e, _, _, _ = _rhs_case(*mesh, k, FORCE, precision, seed=k + mesh[1], modes=modes)
+    assert max(e) < TOL[precision], e
+
+
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_uniform_state_gives_zero(k):
     ctx = make(5, 4, 3, k, ALL)
