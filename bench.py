@@ -59,10 +59,15 @@ WORKLOADS = {
 }
 
 
+# the sources that define and launch the step kernels (the counters in profiles/ are valid
+# while these are unchanged)
+STEP_SOURCES = ("dg_api.hip", "dg_basis.hpp", "dg_ctx.hpp", "dg_kernels.hpp")
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2401_06841_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in STEP_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode())
             h.update(fh.read())

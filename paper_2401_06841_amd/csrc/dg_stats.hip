@@ -215,14 +215,15 @@ __global__ void __launch_bounds__(SFB) __attribute__((amdgpu_waves_per_eu(2))) k
     if (lane == 0) part[(size_t)b * gridDim.x + blockIdx.x] = sum;
 }
 
-// out[b] = (sum over the chunks of bin b, in order) / npairs
-static __global__ void k_sf_final(const double *part, int nchunks, int nbins, long long npairs, double *out)
+// one block per bin: out[b] = (fixed-order sum over the chunks of bin b) / npairs
+static __global__ void __launch_bounds__(BLOCK) k_sf_final(const double *part, int nchunks, long long npairs, double *out)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbins) return;
-    double s = 0.0;
-    for (int i = 0; i < nchunks; ++i) s += part[(size_t)b * nchunks + i];
-    out[b] = s / (double)npairs;
+    __shared__ double lds[4 * 4];
+    const int b = blockIdx.x;
+    double t[1] = {0.0};
+    for (int i = threadIdx.x; i < nchunks; i += BLOCK) t[0] += part[(size_t)b * nchunks + i];
+    block_sum<1>(t, lds);
+    if (threadIdx.x == 0) out[b] = t[0] / (double)npairs;
 }
 
 // v on the grid of p cell-centred sub-points per cell per dimension, [d][Z][Y][X], x fastest
@@ -395,8 +396,7 @@ int launch_sf(dg_ctx *c, const void *u, int nbins, long long npairs, unsigned lo
     hipLaunchKernelGGL((k_sf_pairs<K, T>), dim3(chunks, nbins), dim3(SFB), 0, c->stream, (const T *)cells, g,
                        (const double *)lb, npairs, seed, part);
     LAUNCHCHK(c);
-    hipLaunchKernelGGL(k_sf_final, dim3((nbins + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, c->stream,
-                       (const double *)part, chunks, nbins, npairs, out);
+    hipLaunchKernelGGL(k_sf_final, dim3(nbins), dim3(BLOCK), 0, c->stream, (const double *)part, chunks, npairs, out);
     LAUNCHCHK(c);
     return DG_OK;
 }
