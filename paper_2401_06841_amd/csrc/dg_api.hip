@@ -168,7 +168,9 @@ static void layout(dg_ctx *c, size_t *total)
     c->off.feat = o; o += learned ? align_up(nc * DG_MLP_NIN * 4) : 0;
     c->off.lab = o; o += learned ? align_up(nc * 8) : 0;
     c->off.mlp = o; o += align_up((size_t)256 * (DG_MLP_NPARAM + 1) * 4);   // per-wave network gradients
-    c->off.part = o; o += align_up((size_t)c->nblk * 4 * 8);
+    // per-block partials: the FP64 degree-3 right-hand side runs two lanes per cell (twice
+    // the blocks)
+    c->off.part = o; o += align_up((size_t)c->nblk * 2 * 4 * 8);
     c->off.scal = o; o += align_up(64 * 8);
     c->off.iflags = o; o += align_up(64 * 4);
     *total = o;
@@ -415,6 +417,13 @@ static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int 
     return DG_OK;
 }
 
+// The FP64 right-hand side at degree 3 runs two lanes per cell (k_rhs_pair): one lane per
+// cell fits only one wave per SIMD there, two lanes fit two (measured 15 % faster at 64^3).
+// At degrees 1 and 2 the one-lane kernel is faster (the pair costs twice the loads and a
+// lane swap per point value, 194 -> 265 us at 64^3 degree 2).
+template <typename T, int K>
+constexpr bool rhs_pair() { return sizeof(T) == 8 && K == 3; }
+
 template <typename T, int K>
 static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt, int *fail_reset = nullptr)
 {
@@ -443,7 +452,13 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     a.dt = dt;
     int rc = prof_mark(c, 0, 0);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_rhs<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    if constexpr (rhs_pair<T, K>()) {
+        c->rhs_nblk = (c->nc + BLOCK / 2 - 1) / (BLOCK / 2);
+        hipLaunchKernelGGL((k_rhs_pair<K>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
+    } else {
+        c->rhs_nblk = c->nblk;
+        hipLaunchKernelGGL((k_rhs<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    }
     LAUNCHCHK(c);
     return prof_mark(c, 0, 1);
 }
@@ -455,7 +470,7 @@ static bool use_meanfree(const dg_ctx *c)
 
 static int launch_abar(dg_ctx *c)
 {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->nblk, 1,
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->rhs_nblk, 1,
                        1.0, 0.0, c->abar());
     LAUNCHCHK(c);
     return DG_OK;

@@ -685,6 +685,340 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     }
 }
 
+// ------------------------------------------- RHS kernel, FP64, two lanes per cell
+// The FP64 kernel above keeps all 4 NB coefficients and 4 NB accumulators of a cell in one
+// lane, which at degree 3 fits only one wave per SIMD.  Here the lanes 2i and 2i+1 of a wave share
+// cell i: lane h owns variables 2h and 2h+1 (coefficients, accumulators, face traces), and
+// the partner's point values come across in registers (a DPP lane swap).  The flux at a
+// point, which needs all four variables, is formed in both lanes; each lane contracts and
+// lifts its own two variables.  Buffer resources must be uniform over the wave, so a lane
+// loads its variable 2h+i by loading variables i and 2+i and keeping its own.
+
+// the value held by the other lane of the pair (lane ^ 1)
+__device__ __forceinline__ double pair_swap(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffull), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// all four variables from the own pair (a0, a1) and the partner's pair (b0, b1): lane 0
+// owns variables 0 and 1, lane 1 variables 2 and 3
+__device__ __forceinline__ void pair_assemble(int h, double a0, double a1, double b0, double b1, double (&x)[4])
+{
+    x[0] = h ? b0 : a0;
+    x[1] = h ? b1 : a1;
+    x[2] = h ? a0 : b0;
+    x[3] = h ? a1 : b1;
+}
+
+// one face of the cell for the lane's two variables; src[i] points at variable 2h+i of
+// the trace field (mode planes nc apart), c and cn the own and the neighbour cell
+template <int K, int D, int CB>
+__device__ __forceinline__ void face_pair(const Field<double, 4> &src, unsigned bo, unsigned bn, int s, int h,
+                                          ctab<double> *tab, bool prim, bool use_hllc, double cs, double cs2,
+                                          double (&L)[2][Shape<K>::NB], double *share, int cb)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    double Co[2][S::NB2], Cn[2][S::NB2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) { Co[i][j] = 0.0; Cn[i][j] = 0.0; }
+    ctab<double> *lend = tab + TL::LEND;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            const int e = M.e[l][D];
+            // variable 2h+i through the uniform per-variable buffers: both candidates, then
+            // the lane's own
+            const double wo0 = src.get(i, l, bo), wo1 = src.get(2 + i, l, bo);
+            const double wn0 = src.get(i, l, bn), wn1 = src.get(2 + i, l, bn);
+            const double wo = h ? wo1 : wo0, wn = h ? wn1 : wn0;
+            Co[i][M.d2[D][l]] += wo * lend[2 * e + s];
+            Cn[i][M.d2[D][l]] += wn * lend[2 * e + 1 - s];
+            // keep at most one variable's loads in flight (register pressure)
+            if (l == S::NB - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+    ctab<double> *plift = tab + TL::PLIFT + (D * 2 + s) * S::NF * S::NB;
+#pragma unroll 1
+    for (int r = 0; r < S::NF; ++r) {
+        ctab<double> *f2 = tab + TL::F2 + r * S::NB2;
+        double ao[2] = {0.0, 0.0}, an[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) {
+            const double f = f2[j];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                ao[i] += Co[i][j] * f;
+                an[i] += Cn[i][j] * f;
+            }
+        }
+        double xo[4], xn[4];
+        pair_assemble(h, ao[0], ao[1], pair_swap(ao[0]), pair_swap(ao[1]), xo);
+        pair_assemble(h, an[0], an[1], pair_swap(an[0]), pair_swap(an[1]), xn);
+        double uo[4], un[4], vo[3], vn[3];
+        uo[0] = xo[0];
+        un[0] = xn[0];
+        if (prim) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                vo[d] = xo[1 + d]; uo[1 + d] = xo[0] * xo[1 + d];
+                vn[d] = xn[1 + d]; un[1 + d] = xn[0] * xn[1 + d];
+            }
+        } else {
+            const double io = rcp(xo[0]), in = rcp(xn[0]);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                uo[1 + d] = xo[1 + d]; vo[d] = xo[1 + d] * io;
+                un[1 + d] = xn[1 + d]; vn[d] = xn[1 + d] * in;
+            }
+        }
+        double F[4];
+        if (use_hllc) {
+            if (s) hllc<D>(cs, cs2, uo, vo, un, vn, F);
+            else   hllc<D>(cs, cs2, un, vn, uo, vo, F);
+        } else {
+            if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
+            else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
+        }
+        const double f0 = h ? F[2] : F[0], f1 = h ? F[3] : F[1];
+        if (share) {
+            share[(r * 4 + 2 * h) * CB + cb] = f0;
+            share[(r * 4 + 2 * h + 1) * CB + cb] = f1;
+        }
+        const double wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];
+        ctab<double> *pl = plift + r * S::NB;
+        const double g0 = wr * f0, g1 = wr * f1;
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            L[0][l] += g0 * pl[l];
+            L[1][l] += g1 * pl[l];
+        }
+    }
+}
+
+// high face from the fluxes the neighbour cell (slot) stored in its low-face pass
+template <int K, int D, int CB>
+__device__ __forceinline__ void face_shared_pair(const double *share, int slot, int h, ctab<double> *tab,
+                                                 double (&L)[2][Shape<K>::NB])
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    ctab<double> *plift = tab + TL::PLIFT + (D * 2 + 1) * S::NF * S::NB;
+#pragma unroll 1
+    for (int r = 0; r < S::NF; ++r) {
+        const double wr = -tab[TL::FW + r];
+        ctab<double> *pl = plift + r * S::NB;
+        const double g0 = wr * share[(r * 4 + 2 * h) * CB + slot];
+        const double g1 = wr * share[(r * 4 + 2 * h + 1) * CB + slot];
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            L[0][l] += g0 * pl[l];
+            L[1][l] += g1 * pl[l];
+        }
+    }
+}
+
+template <int K>
+constexpr int rhs_pair_waves() { return K <= 2 ? 3 : 2; }   // no scratch at these targets
+
+template <int K>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_pair_waves<K>()))) k_rhs_pair(RhsArgs a)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    constexpr int NB = S::NB, ND = S::ND;
+    constexpr int CB = BLOCK / 2;                  // cells per block
+    __shared__ double lds[4 * 4];
+    __shared__ double fsh[S::NF * 4 * CB];          // point fluxes of the low faces, [r][v][cell]
+    ctab<double> *tab = as_tab<double>(a.tab);
+    const int nc = a.g.nc;
+    const size_t ncs = (size_t)nc;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int h = threadIdx.x & 1;                 // variables 2h and 2h+1
+    const int cb = threadIdx.x >> 1;
+    const int c0 = blk * CB + cb;
+    const bool active = c0 < nc;
+    const int c = active ? c0 : 0;
+
+    const bool av = a.flags & F_AV;
+    const bool prim = a.flags & F_PRIM;
+    const bool force = a.flags & F_FORCE;
+    const bool use_hllc = a.flags & F_HLLC;
+    const double cs = a.cs, cs2 = a.cs * a.cs;
+    const double hp = a.h / (K + 1);
+    const double inv_dt = a.dt > 0.0 ? 1.0 / a.dt : 1e300;
+    const double alpha = a.alpha, beta = a.beta;
+    const double two_h = 2.0 / a.h;
+
+    const unsigned bo = (unsigned)c * 8u;
+    const Field<double, 4> U(a.u, NB, nc);
+    double W[2][NB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            const double w0 = U.get(i, l, bo), w1 = U.get(2 + i, l, bo);
+            W[i][l] = h ? w1 : w0;
+        }
+
+    constexpr DivMap<K> DM = make_divmap<K>();
+    constexpr int NDIV = DivMap<K>::NDIV;
+    double Dv[NDIV];
+#pragma unroll
+    for (int m = 0; m < NDIV; ++m) Dv[m] = 0.0;
+    bool learned = false;
+    double nu = 0.0;
+    const Field<double, 3> VH(a.vh, NB, nc);
+    if (av) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int l = 0; l < NB; ++l)
+                if (M.e[l][d] >= 1) {
+                    const double v = VH.get(d, l, bo);
+#pragma unroll
+                    for (int t = 0; t < DivMap<K>::MAXT; ++t)
+                        if (DM.m[d][l][t] >= 0) Dv[DM.m[d][l][t]] += v * __builtin_sqrt(double(DM.f[d][l][t]));
+                }
+        if (a.flags & F_LEARNED) {
+            learned = a.fb[c] == 0;
+            nu = ((const double *)a.nu)[c];
+        }
+    }
+
+    double L[2][NB];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) L[i][l] = 0.0;
+    double fs0 = 0.0, fs1 = 0.0, fs2 = 0.0;
+    const Field<double, 3> AP(a.apts, S::NQ, nc);
+    const double half_h = 0.5 * a.h;
+
+    // ---- volume integral (the driving acceleration of the next point requested ahead)
+    double an0 = 0.0, an1 = 0.0, an2 = 0.0;
+    if (force) { an0 = AP.get(0, 0, bo); an1 = AP.get(1, 0, bo); an2 = AP.get(2, 0, bo); }
+#pragma unroll 1
+    for (int q = 0; q < S::NQ; ++q) {
+        const double ac0 = an0, ac1 = an1, ac2 = an2;
+        if (force && q + 1 < S::NQ) {
+            an0 = AP.get(0, q + 1, bo);
+            an1 = AP.get(1, q + 1, bo);
+            an2 = AP.get(2, q + 1, bo);
+        }
+        ctab<double> *ph = tab + TL::VPHI + q * NB;
+        ctab<double> *dph = tab + TL::VDPHI + q * 3 * ND;
+        const double wq = tab[TL::VW + q];
+        double x0 = 0.0, x1 = 0.0;
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            x0 += W[0][l] * ph[l];
+            x1 += W[1][l] * ph[l];
+        }
+        double xv[4];
+        pair_assemble(h, x0, x1, pair_swap(x0), pair_swap(x1), xv);
+        const double rho = xv[0];
+        const double m[3] = {xv[1], xv[2], xv[3]};
+        double pi = 0.0;
+        if (av) {
+            double div = 0.0;
+#pragma unroll
+            for (int mm = 0; mm < NDIV; ++mm) div += Dv[mm] * ph[mm];
+            div *= two_h;
+            const double pv = vnr_pi<double>(rho, div, hp, alpha, beta, cs, inv_dt);
+            const double sq = -div;
+            double pl = fmin(rho * nu * sq, 0.5 * rho * hp * hp * sq * inv_dt);
+            pl = (sq > 0.0 && nu > 0.0) ? pl : 0.0;
+            pi = learned ? pl : pv;
+        }
+        const double ir = rcp(rho);
+        const double pw = (cs2 * rho + pi) * wq;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double md = m[d] * wq;
+            const double mdr = md * ir;
+            // lane 0: (rho, m_x) fluxes; lane 1: (m_y, m_z)
+            const double fa = h ? mdr * m[1] + (d == 1 ? pw : 0.0) : md;
+            const double fb = h ? mdr * m[2] + (d == 2 ? pw : 0.0) : mdr * m[0] + (d == 0 ? pw : 0.0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                if (M.dj[d][l] < 0) continue;
+                const double dp = dph[d * ND + M.dj[d][l]];
+                L[0][l] += dp * fa;
+                L[1][l] += dp * fb;
+            }
+        }
+        if (force) {
+            const double rw = rho * wq;
+            const double s0 = rw * ac0, s1 = rw * ac1, s2 = rw * ac2;
+            fs0 += s0; fs1 += s1; fs2 += s2;
+            const double ta = h ? s1 * half_h : 0.0;
+            const double tb = h ? s2 * half_h : s0 * half_h;
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const double p = ph[l];
+                L[0][l] += ta * p;
+                L[1][l] += tb * p;
+            }
+        }
+    }
+    const double mass0 = W[0][0];                   // cell mean density (lane 0)
+
+    // ---- surface integral, with the low x and y face fluxes shared through LDS as in the
+    // one-lane kernel (cells of the block: CB consecutive cells)
+    int nbr[6], ijk[3];
+    neighbours(a.g, c, nbr, ijk);
+    const Field<double, 4> SRC = prim ? Field<double, 4>(a.u, a.vh, NB, nc) : U;
+    const int base = blk * CB;
+    const bool xsh = __all((unsigned)(nbr[1] - base) < (unsigned)CB);
+    const bool ysh = __all((unsigned)(nbr[3] - base) < (unsigned)CB);
+#pragma unroll 1
+    for (int s = 0; s < (xsh ? 1 : 2); ++s)
+        face_pair<K, 0, CB>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * 8u, s, h, tab, prim, use_hllc, cs, cs2, L,
+                            s == 0 ? fsh : nullptr, cb);
+    __syncthreads();
+    if (xsh) face_shared_pair<K, 0, CB>(fsh, nbr[1] - base, h, tab, L);
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < (ysh ? 1 : 2); ++s)
+        face_pair<K, 1, CB>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * 8u, s, h, tab, prim, use_hllc, cs, cs2, L,
+                            s == 0 ? fsh : nullptr, cb);
+    __syncthreads();
+    if (ysh) face_shared_pair<K, 1, CB>(fsh, nbr[3] - base, h, tab, L);
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s)
+        face_pair<K, 2, CB>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * 8u, s, h, tab, prim, use_hllc, cs, cs2, L, nullptr, cb);
+
+    const double inv4h = 0.25 / a.h;
+    if (active) {
+        double *ob = (double *)a.out;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) ob[((size_t)(2 * h + i) * NB + l) * ncs + c] = L[i][l] * inv4h;
+    }
+    if (force && a.part) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (active) {
+            acc[0] = h ? 0.0 : 0.125 * fs0;
+            acc[1] = h ? 0.125 * fs1 : 0.0;
+            acc[2] = h ? 0.125 * fs2 : 0.0;
+            acc[3] = h ? 0.0 : mass0;
+        }
+        block_sum<4>(acc, lds);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a.part[blk * 4 + i] = acc[i];
+    }
+}
+
 // Projected velocity of one cell (Sec. 3.2; stored when vh is not null) and, when part is
 // not null, the per-block maxima for the time step: signal speed sum_d |v_d| + cs over the
 // interior points, and bulk viscosity alpha (h/p)^2 |div v| + beta cs h/p at compressing
