@@ -143,7 +143,12 @@ int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
  * state-changing call (dg_rhs, dg_rk_step, dg_limit, dg_set_workspace) came in between,
  * and recomputes the projection otherwise; it cannot see writes made outside libdg.
  * One synchronisation per call (status and dt_next in one read-back).  With
- * DG_LEARNED_SENSOR: DG_EUNSUPPORTED (the next time step there needs the network). */
+ * DG_LEARNED_SENSOR the stages use the stored viscosity (of u^n), and after the last stage
+ * the network runs on u^(n+1) (as dg_sensor_infer would): its viscosity is stored for the
+ * next step and enters *dt_next_host, which then equals dg_sensor_infer followed by
+ * dg_dt_max of u^(n+1).  On DG_RETRY the viscosity of the restored u^n is stored again.
+ * A judge call between steps changes the fallback flags: take dg_dt_max afterwards instead
+ * of the returned value.  DG_ESTATE when no viscosity is stored yet. */
 int dg_rk_step_next(dg_ctx *ctx, void *u, double dt, int reuse, int *status_host, double *dt_next_host);
 
 /* Time step dt = min(dt_adv, dt_visc), reduced in FP64 over all cells and interior points:

@@ -598,6 +598,9 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
         rc = launch_project<T, K>(c, u, vh[0], nullptr, c->fail());
         if (rc) return rc;
     }
+    // learned sensor: the network's viscosity of the new state serves its time step (and the
+    // next step's stages), so the bounds are taken after the inference, not in the last stage
+    const bool learned_next = dt_next && (c->cfg.flags & DG_LEARNED_SENSOR);
     for (int s = 0; s < S.stages; ++s) {
         const StageSpec &g = S.s[s];
         const bool last = s == S.stages - 1;
@@ -608,13 +611,17 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
             if (rc) return rc;
         }
         void *vnext = !last ? vh[(s + 1) & 1] : (dt_next ? vh[0] : nullptr);
-        double *part = (last && dt_next) ? (double *)c->wp(c->off.part) : nullptr;
+        double *part = (last && dt_next && !learned_next) ? (double *)c->wp(c->off.part) : nullptr;
         rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext,
                                 s == 0 ? c->wp(c->off.un_copy) : nullptr, g.coef, dt, nullptr, part,
                                 g.w ? buf[g.w] : nullptr, g.wcoef);
         if (rc) return rc;
     }
     if (dt_next) {
+        if (learned_next) {
+            if ((rc = sensor_infer_impl(c, u))) return rc;
+            if ((rc = launch_project<T, K>(c, u, nullptr, (double *)c->wp(c->off.part), nullptr))) return rc;
+        }
         rc = launch_dt_final<T, K>(c, c->scal() + 8);
         if (rc) return rc;
         HIPCHK(c, hipMemcpyAsync(c->pinned + 1, c->scal() + 8, sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -626,6 +633,8 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
     if (st_flag) {
         const size_t bytes = 4 * (size_t)c->nb * c->nc * c->es;
         HIPCHK(c, hipMemcpyAsync(u, c->wp(c->off.un_copy), bytes, hipMemcpyDeviceToDevice, c->stream));
+        // the viscosity inferred from the rejected state is replaced by that of u^n again
+        if (learned_next && (rc = sensor_infer_impl(c, u))) return rc;
         return DG_RETRY;
     }
     if (dt_next) {
@@ -678,9 +687,7 @@ int dg_rk_step_next(dg_ctx *c, void *u, double dt, int reuse, int *status_host, 
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
     if (!dt_next_host) return dg_fail(c, DG_EINVAL, "dt_next_host is null");
-    if (c->cfg.flags & DG_LEARNED_SENSOR)
-        return dg_fail(c, DG_EUNSUPPORTED, "the next time step of a learned-sensor run depends on the network: "
-                                           "use dg_sensor_infer, dg_dt_max and dg_rk_step");
+    if ((rc = learned_ready(c))) return rc;
     return DISPATCH(c, do_step, c, u, dt, status_host, reuse != 0, dt_next_host);
 }
 

@@ -1,13 +1,14 @@
 """Time-stepping driver around libdg (host control flow only; all arithmetic on the GPU).
 
-One driver step: CFL time step (FP64 reduction on the GPU: dg_dt_max, or for the plain
-sensor the value dg_rk_step_next returned with the previous step, so that a step costs
-one read-back), Ornstein-Uhlenbeck driving updates on the host whenever the simulation time
-crosses the next update time (every t_c/100, Sec. 4.2), then dg_rk_step; when the step
-reports a positivity failure the state has been restored and the step is retried with
-half the time step (Sec. 3.1).  With the learned sensor the network runs on u^n before the
-time step (its viscosity enters the viscous bound and serves the three stages), and every
-judge_every steps the judge recomputes the plain labels and the fallback flags.  Checkpoints are the raw [var][mode][cell] array plus a
+One driver step: CFL time step (FP64 reduction on the GPU: the value dg_rk_step_next
+returned with the previous step, so that a step costs one read-back, else dg_dt_max),
+Ornstein-Uhlenbeck driving updates on the host whenever the simulation time crosses the
+next update time (every t_c/100, Sec. 4.2), then dg_rk_step_next; when the step reports a
+positivity failure the state has been restored and the step is retried with half the time
+step (Sec. 3.1).  With the learned sensor the network's viscosity of u^n enters the viscous
+bound and serves the stages (the previous fused step ran the network on this state), and
+every judge_every steps the judge recomputes the plain labels and the fallback flags, after
+which the time step is taken again.  Checkpoints are the raw [var][mode][cell] array plus a
 JSON record of the run parameters, the simulation time and the driving state.
 """
 from __future__ import annotations
@@ -87,16 +88,17 @@ class Simulation:
         self._dt_next = None
 
     def step(self):
-        fused = not self.learned
+        reuse = self._dt_next is not None and self._u_version == self.u._version
         if self.learned:
-            # the network's viscosity of u^n serves the time step and the three stages; the
-            # judge (which also runs the network) refreshes the fallback flags
+            # the network's viscosity of u^n serves the time step and the stages: the fused
+            # step of the previous call already ran it on this state; the judge (which also
+            # runs the network) refreshes the fallback flags, which changes the time step
             if self.nstep % self.judge_every == 0:
                 self.fallback_counts.append(dg.dg_sensor_judge(self.ctx, self.u, self.tau))
-            else:
+                self._dt_next = None
+            elif not reuse:
                 dg.dg_sensor_infer(self.ctx, self.u)
-        reuse = fused and self._dt_next is not None and self._u_version == self.u._version
-        dt = self._dt_next if reuse else dg.dg_dt_max(self.ctx, self.u)
+        dt = self._dt_next if (reuse and self._dt_next is not None) else dg.dg_dt_max(self.ctx, self.u)
         if not (dt > 0.0 and np.isfinite(dt)):
             raise RuntimeError(f"invalid time step {dt} at step {self.nstep}")
         if self.driving is not None:
@@ -106,10 +108,7 @@ class Simulation:
         tries = 0
         self._dt_next = None
         while True:
-            if fused:
-                rc, dt_next = dg.dg_rk_step_next(self.ctx, self.u, dt, reuse)
-            else:
-                rc, dt_next = dg.dg_rk_step(self.ctx, self.u, dt), None
+            rc, dt_next = dg.dg_rk_step_next(self.ctx, self.u, dt, reuse)
             if rc == dg.DG_OK:
                 break
             self.retries += 1

@@ -140,10 +140,55 @@ def test_driver_detects_torch_writes_between_steps():
     assert torch.equal(a.u, b.u)
 
 
-def test_learned_context_rejects_the_fused_step():
+def _flat_params(seed):
+    params = synthetic.mlp_params(seed)
+    flat = np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in params]).astype(np.float32)
+    return torch.as_tensor(flat, device="cuda")
+
+
+def test_learned_fused_step_needs_a_stored_viscosity():
     ctx = make(4, 4, 4, 2, FLAGS | dg.DG_LEARNED_SENSOR)
     u = ctx.empty_state()
     u.zero_()
     u[0, 0] = 1.0
     with pytest.raises(dg.DGError):
         dg.dg_rk_step_next(ctx, u, 1e-3, False)
+
+
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+def test_learned_fused_steps_match_plain_steps_bitwise(precision):
+    """The fused learned step runs the network on the new state and returns the time step
+    of dg_sensor_infer + dg_dt_max; the next fused step uses that viscosity."""
+    n, k = 8, 2
+    flags = FLAGS | dg.DG_LEARNED_SENSOR
+    u0 = synthetic.turbulent_like(n, n, n, k, mach=3.0, seed=12, high_amp=0.02, kmax_frac=0.125)
+    modes = synthetic.forcing_table(4, amp=2.0)
+    a, b = make(n, n, n, k, flags, precision), make(n, n, n, k, flags, precision)
+    P = _flat_params(3)
+    for c in (a, b):
+        dg.dg_set_forcing(c, modes)
+        dg.dg_sensor_set_params(c, P)
+    ua, ub = dev(u0, a), dev(u0, b)
+    dg.dg_sensor_infer(b, ub)
+    dtb = dg.dg_dt_max(b, ub)
+    for i in range(6):
+        dg.dg_sensor_infer(a, ua)
+        dta = dg.dg_dt_max(a, ua)
+        assert dg.dg_rk_step(a, ua, dta) == dg.DG_OK
+        assert dta == dtb
+        rc, dtb = dg.dg_rk_step_next(b, ub, dtb, i > 0)
+        assert rc == dg.DG_OK
+    assert torch.equal(ua, ub)
+
+
+def test_learned_driver_run_with_judge():
+    """Driver with the learned sensor: judge every 3 steps, fused steps in between; the run
+    stays finite and the judge keeps a count per judgement."""
+    n = 8
+    cfg = dg.Config(n, n, n, degree=2, precision=dg.DG_FP32, flags=FLAGS | dg.DG_LEARNED_SENSOR)
+    sim = Simulation(cfg, driving=Driving(3.0, 2.5, seed=1), sensor_params=_flat_params(4), judge_every=3)
+    for _ in range(10):
+        dt = sim.step()
+        assert dt > 0 and np.isfinite(dt)
+    assert len(sim.fallback_counts) == 4
+    assert torch.all(torch.isfinite(sim.u))
