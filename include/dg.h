@@ -174,7 +174,7 @@ int dg_limit(dg_ctx *ctx, void *u, long *nfail_host);
 int dg_conserved_sums(dg_ctx *ctx, const void *u, double *out_host);
 
 /* Instrumentation: with enable = 1 every launch of the right-hand-side kernel and of the
- * stage-combination kernel issued by dg_rhs / dg_rk_step is bracketed by HIP events on
+ * stage-combination kernel issued by dg_rhs / dg_rk_step / dg_rk_step_next is bracketed by HIP events on
  * the context stream and the elapsed times are accumulated (counters cleared);
  * enable = 0 stops.  dg_profile_read synchronises and writes out_host[4] = {RHS-kernel
  * milliseconds, RHS launches, stage-kernel milliseconds, stage launches}. */
