@@ -45,6 +45,7 @@ METRIC = "DG DOF-updates/sec per RK stage (3D, order p) + % HBM/MFMA roofline vs
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector = matrix FP64 peak
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (packed issue)
 FP32_UNPACKED_TFLOPS = 78.6  # issue limit without packed FP32, which this build does not emit
+PEAK_HBM_TBPS = 8.0          # MI355X HBM3E
 
 WORKLOADS = {
     # name: (N, degree, default precision, target Mach, driving sigma, default warm-up steps)
@@ -130,6 +131,12 @@ def _summary(args, sim, precision, wall, prof, retries, dt_min):
                            "traffic": traffic_from_profiles("k_rhs", args.workload, precision, 1)}
         if precision == "fp32":
             out["roofline"]["frac_of_unpacked_fp32"] = achieved / FP32_UNPACKED_TFLOPS
+        traffic = out["roofline"]["traffic"]
+        if traffic:
+            # HBM rate implied by the counted bytes per launch over the live launch time
+            gbps = traffic / (avg * 1e-3) / 1e9
+            out["roofline"]["traffic_GB_per_s"] = gbps
+            out["roofline"]["traffic_frac_of_hbm"] = gbps / (PEAK_HBM_TBPS * 1e3)
         out["algorithmic_flops_per_launch"] = flops
     return out
 
