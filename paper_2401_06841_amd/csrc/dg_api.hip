@@ -167,7 +167,7 @@ static void layout(dg_ctx *c, size_t *total)
     c->off.fb = o; o += align_up(nc * 4);
     c->off.feat = o; o += learned ? align_up(nc * DG_MLP_NIN * 4) : 0;
     c->off.lab = o; o += learned ? align_up(nc * 8) : 0;
-    c->off.mlp = o; o += align_up((size_t)256 * (DG_MLP_NPARAM + 1) * 4);   // per-wave network gradients
+    c->off.mlp = o; o += align_up((size_t)MLP_PART_ROWS * (DG_MLP_NPARAM + 1) * 4);   // per-wave network gradients
     // per-block partials: the FP64 degree-3 right-hand side runs two lanes per cell (twice
     // the blocks)
     c->off.part = o; o += align_up((size_t)c->nblk * 2 * 4 * 8);

@@ -7,6 +7,9 @@
 
 #include "dg.h"
 
+// rows of per-wave partial network gradients in the workspace (waves of the gradient kernel)
+constexpr int MLP_PART_ROWS = 1024;
+
 struct dg_offsets {
     size_t un_copy, stA, stB, stC, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, scal, iflags;
 };

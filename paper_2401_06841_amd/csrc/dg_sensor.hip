@@ -22,7 +22,7 @@ namespace dg {
 constexpr int NIN = DG_MLP_NIN, NH = DG_MLP_NHID, NPARAM = DG_MLP_NPARAM;
 constexpr int OFF_W1 = 0, OFF_B1 = NH * NIN, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH,
               OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NH;
-constexpr int MLP_WAVES = 256;          // waves of the gradient kernel (partials buffer rows)
+constexpr int MLP_WAVES = MLP_PART_ROWS;  // waves of the gradient kernel: one per SIMD at its occupancy of 1
 constexpr double NU0 = 1e-3;            // nu scale of the target t = log(1 + nu/nu0)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -309,16 +309,25 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float *__restrict__ P, c
     }
 }
 
-// fixed-order sum of the per-wave partials: grad[p] and loss = sum / n
+// fixed-order sum of the per-wave partials: grad[p] and loss = sum / n.  A block takes 64
+// entries; its wave w sums the rows w, w+4, w+8, ... in order, and the four wave sums are
+// added in wave order.
 __global__ void __launch_bounds__(256) k_mlp_reduce(const float *__restrict__ part, int nwaves, int n,
                                                     float *__restrict__ grad, float *__restrict__ loss)
 {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p > NPARAM) return;
+    __shared__ float lds[4][64];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 64 + lane;
     float s = 0.0f;
-    for (int wv = 0; wv < nwaves; ++wv) s += part[(size_t)wv * (NPARAM + 1) + p];
-    if (p < NPARAM) grad[p] = s;
-    else loss[0] = s / (float)n;
+    if (p <= NPARAM)
+        for (int wv = w; wv < nwaves; wv += 4) s += part[(size_t)wv * (NPARAM + 1) + p];
+    lds[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && p <= NPARAM) {
+        const float t = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
+        if (p < NPARAM) grad[p] = t;
+        else loss[0] = t / (float)n;
+    }
 }
 
 // Adam (Kingma & Ba 2015), beta1 0.9, beta2 0.999, eps 1e-8
@@ -504,7 +513,7 @@ int dg_mlp_grad(dg_ctx *c, const float *P, const float *x, const float *t, int n
     const int nb = mlp_blocks(n);
     hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, c->stream, P, x, t, n, mlp_part(c));
     LAUNCHCHK(c);
-    hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, c->stream, (const float *)mlp_part(c),
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 1 + 63) / 64), dim3(256), 0, c->stream, (const float *)mlp_part(c),
                        nb * 4, n, grad, loss);
     LAUNCHCHK(c);
     return DG_OK;
