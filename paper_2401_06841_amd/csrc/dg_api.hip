@@ -230,6 +230,12 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
     c->es = cfg->precision == DG_FP64 ? 8 : 4;
     c->nblk = (c->nc + BLOCK - 1) / BLOCK;
     c->stream = (hipStream_t)cfg->stream;
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            c->ncu = ncu;
+    }
     layout(c, &c->ws_need);
 
     std::vector<double> t;

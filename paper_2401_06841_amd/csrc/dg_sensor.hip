@@ -475,14 +475,15 @@ static int mlp_blocks(int n)
     return (nw + 3) / 4;
 }
 
-// forward: no reduction, so spread the 16-row tiles over the whole chip (about four
-// tiles per wave, which amortises loading the network into registers)
-static int fwd_blocks(int n)
+// forward: one full round of waves at the kernel's occupancy (3 waves per SIMD), each wave
+// looping over its share of the 16-row tiles (the network is loaded into registers once per
+// wave, and no wave waits for a second round)
+static int fwd_blocks(const dg_ctx *c, int n)
 {
     const long ntile = ((long)n + 15) / 16;
-    const long nw = (ntile + 3) / 4;
-    const long nb = (nw + 3) / 4;
-    return (int)(nb < 1 ? 1 : (nb > 16384 ? 16384 : nb));
+    const long round = (long)c->ncu * 4 * 3;
+    const long nw = ntile < round ? ntile : round;
+    return (int)((nw + 3) / 4);
 }
 
 static float *mlp_part(dg_ctx *c) { return (float *)c->wp(c->off.mlp); }
@@ -499,7 +500,7 @@ int dg_mlp_forward(dg_ctx *c, const float *P, const float *x, int n, float *y)
     if (!c) return DG_EINVAL;
     if (!P || !x || !y || n < 0) return dg_fail(c, DG_EINVAL, "bad network arguments");
     if (n == 0) return DG_OK;
-    hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(n)), dim3(256), 0, c->stream, P, x, n, y,
+    hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(c, n)), dim3(256), 0, c->stream, P, x, n, y,
                        (float *)nullptr);
     LAUNCHCHK(c);
     return DG_OK;
@@ -597,11 +598,11 @@ int sensor_infer_impl(dg_ctx *c, const void *u)
     rc = dg_sensor_features(c, u, x);
     if (rc) return rc;
     if (c->es == 8)
-        hipLaunchKernelGGL((k_mlp_forward<double>), dim3(fwd_blocks(c->nc)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_mlp_forward<double>), dim3(fwd_blocks(c, c->nc)), dim3(256), 0, c->stream,
                            (const float *)c->mlp_bf16, (const float *)x, c->nc, (float *)nullptr,
                            (double *)c->wp(c->off.nu));
     else
-        hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(c->nc)), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(c, c->nc)), dim3(256), 0, c->stream,
                            (const float *)c->mlp_bf16, (const float *)x, c->nc, (float *)nullptr,
                            (float *)c->wp(c->off.nu));
     LAUNCHCHK(c);
