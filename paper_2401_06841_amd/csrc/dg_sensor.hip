@@ -320,6 +320,7 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(const float *__restrict__ pa
     const int p = blockIdx.x * 64 + lane;
     float s = 0.0f;
     if (p <= NPARAM)
+#pragma unroll 8
         for (int wv = w; wv < nwaves; wv += 4) s += part[(size_t)wv * (NPARAM + 1) + p];
     lds[w][lane] = s;
     __syncthreads();
