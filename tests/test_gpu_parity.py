@@ -255,6 +255,35 @@ def test_c2_full_size_sampled(precision):
     assert err.max() < (1e-12 if precision == dg.DG_FP64 else 1e-5), err.max()
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+def test_c2_full_size_fused_step(precision):
+    """The step the benchmark times, at its full size: 64^3, degree 2, AV + projection +
+    limiter + mean-free driving, one dg_rk_step_next from a Mach-3 state; the oracle runs
+    the whole SSP-RK3 step on the whole mesh.  The whole state and the returned next time
+    step are compared."""
+    n, k = 64, 2
+    print(f"C2 full fused step precision={precision}", flush=True)
+    u = synthetic.turbulent_like(n, n, n, k, mach=3.0, seed=13, high_amp=0.02, kmax_frac=0.125)
+    if precision == dg.DG_FP32:
+        u = u.astype(np.float32).astype(np.float64)
+    modes = synthetic.forcing_table(6, amp=2.5)
+    ocfg = _orc_cfg(n, n, n, k, FORCE)
+    dt = oracle.dt_max(ocfg, u)
+    ref, st = oracle.rk_step(ocfg, u, dt, modes)
+    assert st == oracle.OK
+    ctx = make(n, n, n, k, FORCE, precision)
+    dg.dg_set_forcing(ctx, modes)
+    ud = dev(u, ctx)
+    rc, dt_next = dg.dg_rk_step_next(ctx, ud, dt, False)
+    assert rc == dg.DG_OK
+    tol = 1e-12 if precision == dg.DG_FP64 else 1e-5
+    e = field_rel(host(ud), ref, ref)
+    assert max(e) < tol, e
+    dref = oracle.dt_max(ocfg, ref)
+    assert abs(dt_next - dref) <= tol * dref, (dt_next, dref)
+
+
 # ------------------------------------------------------- HLLC-type interface flux
 @pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
 @pytest.mark.parametrize("k", [1, 2, 3])
