@@ -124,8 +124,8 @@ def _summary(args, sim, precision, wall, prof, retries, dt_min):
         achieved = flops / (avg * 1e-3) / 1e12
         peak = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
         out["kernels"] = {"k_rhs_avg_ms": avg, "k_rhs_launches": rhs_n,
-                          "k_stage_avg_ms": st_ms / max(st_n, 1), "k_stage_launches": st_n,
-                          "k_rhs_share_of_step": rhs_ms / (1e3 * wall)}
+                          "k_stage_avg_ms": st_ms / st_n if st_n else None, "k_stage_launches": st_n,
+                          "k_rhs_share_of_step": avg * 3 * args.steps / (1e3 * wall)}
         out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                            "frac": achieved / peak,
                            "traffic": traffic_from_profiles("k_rhs", args.workload, precision, 1)}

@@ -129,9 +129,10 @@ int dg_rhs(dg_ctx *ctx, const void *u, void *dudt, double dt);
  * after every stage when DG_POS_LIMITER is set (Sec. 3.1: all high-order weights of a cell
  * scaled by one factor so that the density at every volume and face Gauss point is at
  * least max(rho_floor, rho_floor_rel * cell mean)).  Synchronises the stream once to read
- * the 4-byte status into *status_host (may be NULL).  Returns DG_RETRY (and restores u
- * to its value at entry, kept in the workspace) when a cell mean fell to or below the
- * floor, i.e. the caller must retry with a smaller dt (Sec. 3.1). */
+ * the 4-byte status into *status_host (may be NULL).  Returns DG_RETRY, with u left at its
+ * value at entry, when a cell mean fell to or below the floor, i.e. the caller must retry
+ * with a smaller dt (Sec. 3.1): only the last stage writes u, its failure is decided before
+ * it writes, and once any stage has failed it writes nothing. */
 int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
 
 /* The same step, also returning the time step of the new state: on DG_OK,
@@ -142,11 +143,13 @@ int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
  * projection.  The library additionally checks the array pointer and that no other
  * state-changing call (dg_rhs, dg_rk_step, dg_limit, dg_set_workspace) came in between,
  * and recomputes the projection otherwise; it cannot see writes made outside libdg.
- * One synchronisation per call (status and dt_next in one read-back).  With
+ * One wait per call: the step's last kernel stores the status and dt_next into pinned host
+ * memory and the call returns once they are visible, when every other kernel of the step has
+ * completed.  With
  * DG_LEARNED_SENSOR the stages use the stored viscosity (of u^n), and after the last stage
  * the network runs on u^(n+1) (as dg_sensor_infer would): its viscosity is stored for the
  * next step and enters *dt_next_host, which then equals dg_sensor_infer followed by
- * dg_dt_max of u^(n+1).  On DG_RETRY the viscosity of the restored u^n is stored again.
+ * dg_dt_max of u^(n+1).  On DG_RETRY u is u^n and the stored viscosity is that of u^n.
  * A judge call between steps changes the fallback flags: take dg_dt_max afterwards instead
  * of the returned value.  DG_ESTATE when no viscosity is stored yet. */
 int dg_rk_step_next(dg_ctx *ctx, void *u, double dt, int reuse, int *status_host, double *dt_next_host);
@@ -173,11 +176,14 @@ int dg_limit(dg_ctx *ctx, void *u, long *nfail_host);
  * reduction; out_host[4] host memory; synchronises. */
 int dg_conserved_sums(dg_ctx *ctx, const void *u, double *out_host);
 
-/* Instrumentation: with enable = 1 every launch of the right-hand-side kernel and of the
- * stage-combination kernel issued by dg_rhs / dg_rk_step / dg_rk_step_next is bracketed by HIP events on
- * the context stream and the elapsed times are accumulated (counters cleared);
- * enable = 0 stops.  dg_profile_read synchronises and writes out_host[4] = {RHS-kernel
- * milliseconds, RHS launches, stage-kernel milliseconds, stage launches}. */
+/* Instrumentation: launches issued by dg_rhs / dg_rk_step / dg_rk_step_next are bracketed
+ * by HIP events on the context stream (without the system-scope fence) and the elapsed
+ * times are accumulated (counters cleared).  Each event leaves the GPU idle for a few
+ * microseconds, so enable = 1 brackets only the right-hand-side kernel of every dg_rhs and
+ * of the first stage of every step (the stages of a step launch the same kernel on the same
+ * mesh); enable = 2 brackets every right-hand-side and stage-combination launch; enable = 0
+ * stops.  dg_profile_read synchronises and writes out_host[4] = {RHS-kernel milliseconds,
+ * RHS launches, stage-kernel milliseconds, stage launches}. */
 int dg_profile(dg_ctx *ctx, int enable);
 int dg_profile_read(dg_ctx *ctx, double *out_host);
 

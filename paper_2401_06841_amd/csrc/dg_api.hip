@@ -2,6 +2,7 @@
 // layout, kernel launches and the C ABI declared in include/dg.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -153,7 +154,6 @@ static void layout(dg_ctx *c, size_t *total)
     const size_t state = align_up(4 * (size_t)c->nb * nc * es);
     const size_t vh = align_up(3 * (size_t)c->nb * nc * es);
     size_t o = 0;
-    c->off.un_copy = o; o += state;
     c->off.stA = o; o += state;
     c->off.stB = o; o += state;
     // a third stage buffer for the five-stage scheme (degree 3 with DG_RK_BY_ORDER)
@@ -254,7 +254,11 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
         e = hipMemcpy(c->tab, tf.data(), tf.size() * 4, hipMemcpyHostToDevice);
     }
     if (e == hipSuccess) e = hipMalloc((void **)&c->modes_dev, 64 * 9 * sizeof(double));
-    if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned, 256, hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&c->modes_stage, dg_ctx::MODE_SLOTS * 64 * 9 * sizeof(double), hipHostMallocDefault);
+    // coherent: the step's last kernel stores its published values straight to host memory
+    if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned, 256, hipHostMallocCoherent);
+    if (e == hipSuccess) std::memset(c->pinned, 0, 256);
     if (e == hipSuccess) e = hipMalloc((void **)&c->mlp_bf16, 8 * DG_MLP_NPARAM);
     if (e != hipSuccess) rc = DG_EHIP;
     if (rc != DG_OK) { dg_free(c); return rc; }
@@ -271,6 +275,9 @@ void dg_free(dg_ctx *c)
     if (c->tab) (void)hipFree(c->tab);
     if (c->modes_dev) (void)hipFree(c->modes_dev);
     if (c->pinned) (void)hipHostFree(c->pinned);
+    for (int i = 0; i < dg_ctx::MODE_SLOTS; ++i)
+        if (c->modes_ev[i]) (void)hipEventDestroy(c->modes_ev[i]);
+    if (c->modes_stage) (void)hipHostFree(c->modes_stage);
     if (c->mlp_bf16) (void)hipFree(c->mlp_bf16);
     stats_release(c);
     delete c;
@@ -315,8 +322,25 @@ int dg_set_forcing(dg_ctx *c, const double *modes_host, int nmodes)
         return dg_fail(c, DG_EINVAL, "bad forcing table (nmodes=%d)", nmodes);
     std::memcpy(c->modes_host, modes_host, sizeof(double) * 9 * nmodes);
     c->nmodes = nmodes;
-    HIPCHK(c, hipMemcpy(c->modes_dev, c->modes_host, sizeof(double) * 9 * (nmodes > 0 ? nmodes : 1),
-                        hipMemcpyHostToDevice));
+    bool sep = true;
+    for (int m = 0; m < nmodes; ++m)
+        for (int a = 0; a < 3; ++a) {
+            const double n = modes_host[9 * m + a];
+            sep = sep && n == std::nearbyint(n) && std::fabs(n) <= 2.0;
+        }
+    c->modes_sep = sep;
+    // asynchronous upload from a ring of pinned slots: a slot is rewritten only after the
+    // copy that last read it has completed
+    const int slot = c->modes_slot;
+    c->modes_slot = (slot + 1) % dg_ctx::MODE_SLOTS;
+    if (c->modes_ev[slot]) HIPCHK(c, hipEventSynchronize(c->modes_ev[slot]));
+    else HIPCHK(c, hipEventCreateWithFlags(&c->modes_ev[slot], hipEventDisableTiming));
+    double *stage = c->modes_stage + (size_t)slot * 64 * 9;
+    std::memcpy(stage, c->modes_host, sizeof(double) * 9 * nmodes);
+    if (nmodes > 0) {
+        HIPCHK(c, hipMemcpyAsync(c->modes_dev, stage, sizeof(double) * 9 * nmodes, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipEventRecord(c->modes_ev[slot], c->stream));
+    }
     c->forcing_dirty = true;
     return DG_OK;
 }
@@ -344,9 +368,14 @@ static int prof_drain(dg_ctx *c)
 }
 
 // bracket one launch with events when profiling: call with stop = 0 before, 1 after
+// Each event costs the GPU a few microseconds of idle time (measured: about 2 us per
+// event without the system-scope fence, 3 to 6 us with it), so level 1 brackets only the
+// right-hand side of a step's first stage (the three right-hand sides of a step are the same
+// kernel on the same mesh) and level 2 every right-hand-side and stage launch.
 static int prof_mark(dg_ctx *c, int kind, int stop)
 {
     if (!c->prof) return DG_OK;
+    if (c->prof == 1 && (kind != 0 || !c->prof_first)) return DG_OK;
     if (!stop && c->nev >= 2 * dg_ctx::NEV) {
         int rc = prof_drain(c);
         if (rc) return rc;
@@ -366,12 +395,12 @@ int dg_profile(dg_ctx *c, int enable)
     if (enable) {
         for (int i = 0; i < 2 * dg_ctx::NEV; ++i)
             for (int j = 0; j < 2; ++j)
-                if (!c->ev[i][j]) HIPCHK(c, hipEventCreate(&c->ev[i][j]));
+                if (!c->ev[i][j]) HIPCHK(c, hipEventCreateWithFlags(&c->ev[i][j], hipEventDisableSystemFence));
         c->nev = 0;
         c->prof_ms[0] = c->prof_ms[1] = 0.0;
         c->prof_n[0] = c->prof_n[1] = 0;
     }
-    c->prof = enable != 0;
+    c->prof = enable < 0 ? 0 : (enable > 2 ? 2 : enable);
     return DG_OK;
 }
 
@@ -388,12 +417,18 @@ int dg_profile_read(dg_ctx *c, double *out)
 }
 
 // ------------------------------------------------------------------ launches
+// tables of integer wavevectors with components in [-2, 2] take the separable kernel (about
+// 4x fewer operations), any other table the direct one
 template <typename T, int K>
 static int launch_forcing_points(dg_ctx *c)
 {
     const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
-    hipLaunchKernelGGL((k_forcing_points<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->wp(c->off.apts),
-                       c->modes_dev, c->nmodes, c->tab, g, c->cfg.h);
+    if (c->modes_sep)
+        hipLaunchKernelGGL((k_forcing_sep<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->wp(c->off.apts),
+                           c->modes_dev, c->nmodes, c->tab, g, c->cfg.h);
+    else
+        hipLaunchKernelGGL((k_forcing_points<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, c->wp(c->off.apts),
+                           c->modes_dev, c->nmodes, c->tab, g, c->cfg.h);
     LAUNCHCHK(c);
     return DG_OK;
 }
@@ -430,8 +465,15 @@ static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int 
 template <typename T, int K>
 constexpr bool rhs_pair() { return sizeof(T) == 8 && K == 3; }
 
+// failure prediction of a last stage (RhsArgs::pred_fail): its u^n operand and coefficients
+struct StagePred {
+    const void *un;
+    const double *coef;
+};
+
 template <typename T, int K>
-static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt, int *fail_reset = nullptr)
+static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt, int *fail_reset = nullptr,
+                      const StagePred *pred = nullptr)
 {
     if ((c->cfg.flags & DG_FORCING) && c->forcing_dirty) {
         int rc = launch_forcing_points<T, K>(c);
@@ -448,6 +490,12 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     a.fb = (const int *)c->wp(c->off.fb);
     a.part = (double *)c->wp(c->off.part);
     a.fail_reset = fail_reset;
+    a.pred_fail = pred ? c->fail() : nullptr;
+    a.pred_un = pred ? pred->un : nullptr;
+    a.pred_ca = pred ? pred->coef[0] : 0.0;
+    a.pred_cb = pred ? pred->coef[1] : 0.0;
+    a.pred_cc = pred ? pred->coef[2] : 0.0;
+    a.rho_floor = c->cfg.rho_floor;
     a.g = Mesh{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
     a.flags = c->cfg.flags;
     if (c->nmodes == 0) a.flags &= ~DG_FORCING;
@@ -477,14 +525,14 @@ static bool use_meanfree(const dg_ctx *c)
 static int launch_abar(dg_ctx *c)
 {
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->rhs_nblk, 1,
-                       1.0, 0.0, c->abar());
+                       1.0, 0.0, c->abar(), (const int *)nullptr, (volatile long long *)nullptr, 0LL);
     LAUNCHCHK(c);
     return DG_OK;
 }
 
 template <typename T, int K>
 static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
-                        void *un_copy, const double (&coef)[3], double dt, long long *nlim, double *part = nullptr,
+                        bool skip_if_failed, const double (&coef)[3], double dt, long long *nlim, double *part = nullptr,
                         void *w = nullptr, const double (&wcoef)[3] = {0.0, 0.0, 0.0})
 {
     StageArgs a;
@@ -493,7 +541,7 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.L = L;
     a.out = out;
     a.vh_out = vh_out;
-    a.un_copy = un_copy;
+    a.skip_flag = skip_if_failed ? c->fail() : nullptr;
     a.tab = c->tab;
     a.abar = (L && use_meanfree(c)) ? c->abar() : nullptr;
     a.fail = c->fail();
@@ -525,6 +573,7 @@ static int do_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
 {
     int rc = launch_project<T, K>(c, u, c->wp(c->off.vh0), nullptr, nullptr);
     if (rc) return rc;
+    c->prof_first = true;
     rc = launch_rhs<T, K>(c, u, c->wp(c->off.vh0), dudt, dt);
     if (rc) return rc;
     if (use_meanfree(c)) {
@@ -536,14 +585,45 @@ static int do_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
     return DG_OK;
 }
 
+// seq > 0: also publish the time step and the failure flag to the host (dg_ctx::PUB)
 template <typename T, int K>
-static int launch_dt_final(dg_ctx *c, double *dst)
+static int launch_dt_final(dg_ctx *c, double *dst, long long seq = 0)
 {
     const double hp = c->cfg.h / (K + 1);
+    volatile long long *pub = seq > 0 ? (volatile long long *)(c->pinned + dg_ctx::PUB) : nullptr;
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->nblk, 2,
                        c->cfg.cfl * c->cfg.h / (K + 1), c->cfg.cfl_visc > 0.0 ? c->cfg.cfl_visc * hp * hp : 0.0,
-                       dst);
+                       dst, (const int *)c->fail(), pub, seq);
     LAUNCHCHK(c);
+    return DG_OK;
+}
+
+// Wait until the kernel launched by launch_dt_final(c, dst, seq) has published: spin on the
+// sequence number in pinned memory (far lower latency than a copy back and a stream
+// synchronisation), bounded by the stream's own completion.  Should the stream complete
+// without the number showing, the values are copied back the ordinary way.
+static int wait_published(dg_ctx *c, long long seq, double *dt, int *fail_flag)
+{
+    volatile long long *pub = (volatile long long *)(c->pinned + dg_ctx::PUB);
+    for (unsigned it = 1;; ++it) {
+        if (pub[0] == seq) break;
+        if ((it & 63) == 0) {
+            const hipError_t q = hipStreamQuery(c->stream);
+            if (q == hipSuccess) {
+                if (pub[0] == seq) break;
+                HIPCHK(c, hipMemcpy(c->pinned + dg_ctx::PUB + 1, c->scal() + 8, sizeof(double), hipMemcpyDeviceToHost));
+                int f = 0;
+                HIPCHK(c, hipMemcpy(&f, c->fail(), sizeof(int), hipMemcpyDeviceToHost));
+                pub[2] = f;
+                break;
+            }
+            if (q != hipErrorNotReady) HIPCHK(c, q);
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    const long long bits = pub[1];
+    std::memcpy(dt, &bits, sizeof(double));
+    *fail_flag = (int)pub[2];
     return DG_OK;
 }
 
@@ -607,10 +687,17 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
     // learned sensor: the network's viscosity of the new state serves its time step (and the
     // next step's stages), so the bounds are taken after the inference, not in the last stage
     const bool learned_next = dt_next && (c->cfg.flags & DG_LEARNED_SENSOR);
+    int st_flag = 0;
+    double dt_pub = 0.0;
     for (int s = 0; s < S.stages; ++s) {
         const StageSpec &g = S.s[s];
         const bool last = s == S.stages - 1;
-        rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], c->wp(c->off.L), dt, (s == 0 && cached) ? c->fail() : nullptr);
+        c->prof_first = s == 0;
+        // the last stage writes the caller's array: its failure is decided by its right-hand
+        // side, so that on failure the stage kernel leaves u^n in place (no copy to restore)
+        const StagePred pred{buf[g.un], g.coef};
+        rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], c->wp(c->off.L), dt, (s == 0 && cached) ? c->fail() : nullptr,
+                              last ? &pred : nullptr);
         if (rc) return rc;
         if (use_meanfree(c)) {
             rc = launch_abar(c);
@@ -618,8 +705,8 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
         }
         void *vnext = !last ? vh[(s + 1) & 1] : (dt_next ? vh[0] : nullptr);
         double *part = (last && dt_next && !learned_next) ? (double *)c->wp(c->off.part) : nullptr;
-        rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext,
-                                s == 0 ? c->wp(c->off.un_copy) : nullptr, g.coef, dt, nullptr, part,
+        rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext, last, g.coef, dt,
+                                nullptr, part,
                                 g.w ? buf[g.w] : nullptr, g.wcoef);
         if (rc) return rc;
     }
@@ -628,23 +715,22 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
             if ((rc = sensor_infer_impl(c, u))) return rc;
             if ((rc = launch_project<T, K>(c, u, nullptr, (double *)c->wp(c->off.part), nullptr))) return rc;
         }
-        rc = launch_dt_final<T, K>(c, c->scal() + 8);
+        const long long seq = ++c->pub_seq;
+        rc = launch_dt_final<T, K>(c, c->scal() + 8, seq);
         if (rc) return rc;
-        HIPCHK(c, hipMemcpyAsync(c->pinned + 1, c->scal() + 8, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        rc = wait_published(c, seq, &dt_pub, &st_flag);
+        if (rc) return rc;
+    } else {
+        HIPCHK(c, hipMemcpyAsync(c->pinned, c->fail(), sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        st_flag = ((volatile int *)c->pinned)[0];
     }
-    HIPCHK(c, hipMemcpyAsync(c->pinned, c->fail(), sizeof(int), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    const int st_flag = ((volatile int *)c->pinned)[0];
     if (status_host) *status_host = st_flag ? DG_RETRY : DG_OK;
-    if (st_flag) {
-        const size_t bytes = 4 * (size_t)c->nb * c->nc * c->es;
-        HIPCHK(c, hipMemcpyAsync(u, c->wp(c->off.un_copy), bytes, hipMemcpyDeviceToDevice, c->stream));
-        // the viscosity inferred from the rejected state is replaced by that of u^n again
-        if (learned_next && (rc = sensor_infer_impl(c, u))) return rc;
-        return DG_RETRY;
-    }
+    // on failure the last stage wrote nothing: u is still u^n, and the network viscosity
+    // inferred after the stages is that of u^n
+    if (st_flag) return DG_RETRY;
     if (dt_next) {
-        *dt_next = ((volatile double *)c->pinned)[1];
+        *dt_next = dt_pub;
         c->vh_cache_u = u;
         c->vh_cache_gen = c->gen;
     }
@@ -748,7 +834,7 @@ static int do_limit(dg_ctx *c, void *u, long *nfail)
     HIPCHK(c, hipMemcpyAsync(cnt, c->pinned + 8, 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(fl, c->pinned + 8, 4, hipMemcpyHostToDevice, c->stream));
     static const double plain[3] = {0.0, 1.0, 0.0};
-    int rc = launch_stage<T, K>(c, u, u, nullptr, u, nullptr, nullptr, plain, 0.0, cnt);
+    int rc = launch_stage<T, K>(c, u, u, nullptr, u, nullptr, false, plain, 0.0, cnt);
     if (rc) return rc;
     HIPCHK(c, hipMemcpyAsync(c->pinned, cnt, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -778,7 +864,7 @@ static int do_sums(dg_ctx *c, const void *u, double *out)
     LAUNCHCHK(c);
     const double h3 = c->cfg.h * c->cfg.h * c->cfg.h;
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 0, h3, 0.0,
-                       c->scal() + 24);
+                       c->scal() + 24, (const int *)nullptr, (volatile long long *)nullptr, 0LL);
     LAUNCHCHK(c);
     HIPCHK(c, hipMemcpyAsync(c->pinned, c->scal() + 24, 32, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

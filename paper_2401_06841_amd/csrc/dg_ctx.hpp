@@ -11,7 +11,7 @@
 constexpr int MLP_PART_ROWS = 1024;
 
 struct dg_offsets {
-    size_t un_copy, stA, stB, stC, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, scal, iflags;
+    size_t stA, stB, stC, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, scal, iflags;
 };
 
 struct dg_ctx {
@@ -25,8 +25,18 @@ struct dg_ctx {
     double *modes_dev = nullptr;   // driving mode table [64][9]
     double modes_host[64 * 9] = {};
     int nmodes = 0;
+    bool modes_sep = false;        // integer wavevectors with components in [-2, 2]
     bool forcing_dirty = false;
+    // pinned staging slots of the asynchronous table uploads, each with the event of its copy
+    static constexpr int MODE_SLOTS = 4;
+    double *modes_stage = nullptr;
+    hipEvent_t modes_ev[MODE_SLOTS] = {};
+    int modes_slot = 0;
     double *pinned = nullptr;      // 256 bytes of pinned host memory for read-backs
+    // pinned[PUB..PUB+2]: the step's published {sequence number, time step bits, failure
+    // flag} written by the device (k_final), and the last sequence number issued
+    static constexpr int PUB = 16;
+    long long pub_seq = 0;
     char *ws = nullptr;            // caller's workspace
     size_t ws_need = 0;
     dg_offsets off{};
@@ -40,7 +50,8 @@ struct dg_ctx {
     bool have_nu = false;
     // kernel timing (dg_profile)
     static constexpr int NEV = 64;
-    bool prof = false;
+    int prof = 0;                      // 0 off, 1 first-stage right-hand sides, 2 every launch
+    bool prof_first = false;           // the launch being issued belongs to a first stage
     hipEvent_t ev[2 * NEV][2] = {};    // [slot][start/stop]
     int ev_kind[2 * NEV] = {};         // 0 = rhs kernel, 1 = stage kernel
     int nev = 0;

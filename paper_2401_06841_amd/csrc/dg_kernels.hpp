@@ -196,6 +196,12 @@ struct RhsArgs {
     const int *fb;          // [nc] fallback flags
     double *part;           // [nblocks][4] driving partial sums (mode-0 source, mass)
     int *fail_reset;        // positivity failure flag to clear before the stages, or NULL
+    // last stage of a step: decide its positivity failure here, before the stage kernel
+    // writes the caller's state (pred_fail != NULL: the flag to raise; pred_un, pred_ca,
+    // pred_cb, pred_cc: the stage's u^n operand and coefficients; rho_floor: the floor)
+    int *pred_fail;
+    const void *pred_un;
+    double pred_ca, pred_cb, pred_cc, rho_floor;
     Mesh g;
     int flags;
     double h, cs, alpha, beta, dt;
@@ -215,7 +221,7 @@ struct StageArgs {
     const void *L;          // right-hand side of u^(i) (NULL: plain copy/limit of ui)
     void *out;              // u^(i+1) (may alias un)
     void *vh_out;           // projection of u^(i+1) for the next stage, or NULL
-    void *un_copy;          // where to keep u^n for a retry, or NULL
+    const int *skip_flag;   // the last stage: the failure flag (write nothing when raised), or NULL
     const void *tab;
     const double *abar;     // removed mean acceleration (3), or NULL
     int *fail;              // positivity failure flag
@@ -231,6 +237,28 @@ struct StageArgs {
 };
 
 // ------------------------------------------------------------------ helpers
+// One coefficient of a Runge-Kutta stage, out = ca un + cb ui + cdt R, with the roundings
+// fixed by explicit fused multiply-adds: the right-hand-side kernel of a last stage
+// recomputes the density mean this way and must reach the stage kernel's value bit for bit.
+template <typename T>
+__device__ __forceinline__ T stage_value(T ca, T cb, T cdt, T un, T ui, T rhs, bool use_un)
+{
+    const T x = fma(cdt, rhs, cb * ui);
+    return use_un ? fma(ca, un, x) : x;
+}
+
+// Positivity failure of the last stage decided from its density mean (Sec. 3.1: a cell whose
+// mean is at or below the floor cannot be limited), before the stage writes the state.
+template <typename T>
+__device__ __forceinline__ void predict_failure(const RhsArgs &a, int c, T ui0, T rhs0)
+{
+    const T ca = (T)a.pred_ca, cb = (T)a.pred_cb, cdt = (T)(a.pred_cc * a.dt);
+    const bool use_un = a.pred_ca != 0.0;
+    const T un0 = use_un ? ((const T *)a.pred_un)[c] : T(0);
+    const double mean = (double)stage_value<T>(ca, cb, cdt, un0, ui0, rhs0, use_un);
+    if (!(mean > a.rho_floor)) atomicOr(a.pred_fail, 1);
+}
+
 template <typename T, int K, int NV>
 __device__ __forceinline__ void load_field(const Field<T, NV> &f, unsigned bo, T (&W)[NV][Shape<K>::NB])
 {
@@ -674,6 +702,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
         for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int l = 0; l < NB; ++l) O.put(v, l, bo, L[v][l] * inv4h);
+        if (a.pred_fail) predict_failure<T>(a, c, mass0, L[0][0] * inv4h);
     }
     if (force && a.part) {
         double acc[4] = {active ? 0.125 * (double)fs0 : 0.0, active ? 0.125 * (double)fs1 : 0.0,
@@ -1003,6 +1032,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int l = 0; l < NB; ++l) ob[((size_t)(2 * h + i) * NB + l) * ncs + c] = L[i][l] * inv4h;
+        if (a.pred_fail && h == 0) predict_failure<double>(a, c, mass0, L[0][0] * inv4h);
     }
     if (force && a.part) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1141,9 +1171,11 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
     const unsigned bo = (unsigned)c * sizeof(T);
     ctab<T> *tab = as_tab<T>(a.tab);
 
+    // the last stage writes the caller's state: nothing at all once the step has failed (the
+    // flag is final here: earlier stages and this stage's right-hand side have raised it)
+    if (a.skip_flag && *a.skip_flag) return;
     T U[4][NB];
     load_field<T, K, 4>(Field<T, 4>(a.ui, NB, nc), bo, U);
-    if (a.un_copy && active) store_field<T, K, 4>(Field<T, 4>(a.un_copy, NB, nc), bo, U);
     if (a.L) {
         const Field<T, 4> LF(a.L, NB, nc);
         const Field<T, 4> UN(a.un, NB, nc);
@@ -1167,8 +1199,9 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
                     const T w = wa * WS.get(v, l, bo) + wb * ui + wcdt * rhs;
                     if (active) WO.put(v, l, bo, w);
                 }
-                const T x = cb * ui + cdt * rhs;
-                U[v][l] = use_un ? ca * UN.get(v, l, bo) + x : x;
+                // stage_value, written out so that the u^n load stays conditional
+                const T x = fma(cdt, rhs, cb * ui);
+                U[v][l] = use_un ? fma(ca, UN.get(v, l, bo), x) : x;
             }
     }
     if (a.flags & F_LIMIT) {
@@ -1281,6 +1314,94 @@ __global__ void __launch_bounds__(BLOCK) k_forcing_points(void *apts_, const dou
     }
 }
 
+// The same field for tables whose wavevectors have integer components of magnitude at most
+// 2 (the driving shell 1 <= |n| <= 2).  The volume points form a tensor product, so
+// exp(2 pi i n.x) = X^nx Y^ny Z^nz with X = exp(2 pi i x) at the N1 coordinates of each axis:
+// 3 N1 sine-cosine pairs per cell instead of one per point and mode.  Per z layer and mode
+// the z factor and then each x factor are folded into the mode's coefficients, so a point
+// costs two multiply-adds per component and mode.  Modes are summed in table order.
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_forcing_sep(void *apts_, const double *modes, int nmodes,
+                                                       const void *tab_, Mesh g, double h)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr int N1 = S::N1;
+    const int nc = g.nc;
+    const int c = blockIdx.x * BLOCK + threadIdx.x;
+    if (c >= nc) return;
+    ctab<T> *tab = as_tab<T>(tab_);
+    const int cell[3] = {c % g.nx, (c / g.nx) % g.ny, c / g.nx / g.ny};
+    // fr/fi[a][t][p]: real and imaginary parts of X_a(t)^(p+1), p = 0, 1
+    double fr[3][N1][2], fi[3][N1][2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int t = 0; t < N1; ++t) {
+            const int q = a == 0 ? t : (a == 1 ? N1 * t : N1 * N1 * t);     // point (t,0,0), (0,t,0), (0,0,t)
+            const double x = (cell[a] + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + a]) * h;
+            double sn, cs;
+            sincospi(2.0 * x, &sn, &cs);
+            fr[a][t][0] = cs;
+            fi[a][t][0] = sn;
+            fr[a][t][1] = cs * cs - sn * sn;
+            fi[a][t][1] = 2.0 * cs * sn;
+        }
+    // X_a(t)^n for an integer n in [-2, 2] (negative powers are conjugates)
+    auto power = [&](int a, int t, int n, double &re, double &im) {
+        const int m = n < 0 ? -n : n;
+        re = m == 2 ? fr[a][t][1] : (m == 1 ? fr[a][t][0] : 1.0);
+        im = m == 2 ? fi[a][t][1] : (m == 1 ? fi[a][t][0] : 0.0);
+        if (n < 0) im = -im;
+    };
+    T *ap = (T *)apts_;
+#pragma unroll
+    for (int tz = 0; tz < N1; ++tz) {
+        double acc[3][N1 * N1];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int p = 0; p < N1 * N1; ++p) acc[k][p] = 0.0;
+#pragma unroll 1
+        for (int m = 0; m < nmodes; ++m) {
+            const double *e = modes + 9 * m;
+            const int nx = (int)e[0], ny = (int)e[1], nz = (int)e[2];
+            double zr, zi;
+            power(2, tz, nz, zr, zi);
+            double ar[3], ai[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const double re = e[3 + 2 * k], im = e[4 + 2 * k];
+                ar[k] = re * zr - im * zi;
+                ai[k] = re * zi + im * zr;
+            }
+            double yr[N1], yi[N1];
+#pragma unroll
+            for (int ty = 0; ty < N1; ++ty) power(1, ty, ny, yr[ty], yi[ty]);
+#pragma unroll
+            for (int tx = 0; tx < N1; ++tx) {
+                double xr, xi;
+                power(0, tx, nx, xr, xi);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double br = ar[k] * xr - ai[k] * xi;
+                    const double bi = ar[k] * xi + ai[k] * xr;
+#pragma unroll
+                    for (int ty = 0; ty < N1; ++ty) acc[k][tx + N1 * ty] += br * yr[ty] - bi * yi[ty];
+                }
+            }
+        }
+#pragma unroll
+        for (int ty = 0; ty < N1; ++ty)
+#pragma unroll
+            for (int tx = 0; tx < N1; ++tx) {
+                const int q = tx + N1 * (ty + N1 * tz);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) ap[(k * S::NQ + q) * (size_t)nc + c] = (T)acc[k][tx + N1 * ty];
+            }
+    }
+}
+
 // per-block sums of the cell means (conservation totals, Sec. 2.2: w_0 is the mean)
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_sums(const void *u_, Mesh g, double *part)
@@ -1306,8 +1427,13 @@ __global__ void __launch_bounds__(BLOCK) k_sums(const void *u_, Mesh g, double *
 // mode 1: out[0..2] = sum part[.][0..2] / sum part[.][3]   (mass-weighted mean acceleration)
 // mode 2: out[0] = min(scale / max part[.][0], scale2 / max part[.][1])   (time step; the
 //         second term only when scale2 > 0 and the maximum is positive)
+// Publication (mode 2, pub != null): the time step and the step's failure flag are also
+// stored into pub (pinned host memory: pub[1] = the bits of dt, pub[2] = *fail), and then
+// pub[0] = seq, each store made visible to the host before the next; the host waits for
+// pub[0] == seq instead of copying the values back and synchronising the stream.
 static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double scale2,
-                                                 double *out)
+                                                 double *out, const int *fail, volatile long long *pub,
+                                                 long long seq)
 {
     __shared__ double lds[16];
     if (mode == 2) {
@@ -1323,6 +1449,13 @@ static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int 
             double dt = scale / m;
             if (scale2 > 0.0 && n > 0.0) dt = fmin(dt, scale2 / n);
             out[0] = dt;
+            if (pub) {
+                pub[1] = __double_as_longlong(dt);
+                pub[2] = *fail;
+                __threadfence_system();
+                pub[0] = seq;
+                __threadfence_system();
+            }
         }
         return;
     }

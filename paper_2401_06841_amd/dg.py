@@ -258,8 +258,10 @@ def dg_conserved_sums(ctx: Context, u):
     return list(out)
 
 
-def dg_profile(ctx: Context, enable: bool):
-    ctx._chk(_lib.dg_profile(ctx.h, 1 if enable else 0))
+def dg_profile(ctx: Context, enable):
+    """enable: False/0 off, True/1 the first stage's right-hand side of each step, 2 every
+    right-hand-side and stage launch."""
+    ctx._chk(_lib.dg_profile(ctx.h, int(enable)))
 
 
 def dg_profile_read(ctx: Context):

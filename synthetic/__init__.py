@@ -137,6 +137,21 @@ def forcing_table(seed: int, amp: float = 1.0):
     return tab
 
 
+def forcing_table_general(seed: int, amp: float = 1.0):
+    """Driving-mode table with wavevectors off the integer shell |n_a| <= 2: components of
+    magnitude 3 and a non-integer one (a perpendicular to n as in forcing_table)."""
+    rng = np.random.default_rng(seed)
+    n = np.array([[3.0, 0.0, 1.0], [1.0, -3.0, 2.0], [0.5, 1.0, 0.0], [-2.0, 2.0, -3.0], [0.0, 1.0, -1.0]])
+    tab = np.zeros((len(n), 9))
+    tab[:, :3] = n
+    for i, nv in enumerate(n):
+        re = np.cross(nv, rng.standard_normal(3))
+        im = np.cross(nv, rng.standard_normal(3))
+        tab[i, 3::2] = re * amp / np.linalg.norm(nv)
+        tab[i, 4::2] = im * amp / np.linalg.norm(nv)
+    return tab
+
+
 def gaussian_draws(seed: int, step: int, n: int):
     """n standard normal numbers for OU update number ``step`` of stream ``seed``."""
     rng = np.random.default_rng([seed, step])

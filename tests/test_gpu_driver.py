@@ -192,3 +192,31 @@ def test_learned_driver_run_with_judge():
         assert dt > 0 and np.isfinite(dt)
     assert len(sim.fallback_counts) == 4
     assert torch.all(torch.isfinite(sim.u))
+
+
+# ------------------------------------------------------------- instrumentation levels
+
+def test_profile_levels_count_the_bracketed_launches():
+    """Level 1 times the first stage's right-hand side of each step, level 2 every
+    right-hand-side and stage launch; the timed steps give the same state as untimed ones."""
+    n = 8
+    cfg = dg.Config(n, n, n, degree=2, precision=dg.DG_FP64, flags=FLAGS)
+    drv = Driving(3.0, 2.5, seed=1)
+    plain = Simulation(cfg, driving=drv)
+    timed = Simulation(cfg, driving=drv)
+    for level, steps in ((1, 5), (2, 4)):
+        dg.dg_profile(timed.ctx, level)
+        r0 = timed.retries
+        for _ in range(steps):
+            plain.step()
+            timed.step()
+        attempts = steps + timed.retries - r0
+        rhs_ms, rhs_n, st_ms, st_n = dg.dg_profile_read(timed.ctx)
+        dg.dg_profile(timed.ctx, 0)
+        if level == 1:
+            assert (rhs_n, st_n) == (attempts, 0)
+        else:
+            assert (rhs_n, st_n) == (3 * attempts, 3 * attempts)
+            assert st_ms > 0.0
+        assert rhs_ms > 0.0
+    assert torch.equal(plain.u, timed.u) and plain.t == timed.t

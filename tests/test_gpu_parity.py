@@ -67,6 +67,36 @@ def test_rhs_fp64_forcing_meanfree(k):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
+def test_rhs_forcing_general_wavevectors(k):
+    """Tables off the integer shell |n_a| <= 2 take the direct driving-field kernel."""
+    print(f"rhs forcing general table k={k}", flush=True)
+    modes = synthetic.forcing_table_general(20 + k, amp=5.0)
+    e, _, _, _ = _rhs_case(8, 6, 5, k, FORCE, dg.DG_FP64, seed=30 + k, modes=modes)
+    assert max(e) < TOL[dg.DG_FP64], e
+
+
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+def test_separable_and_direct_driving_fields_agree(precision):
+    """The same driving field from the separable kernel (integer shell table) and from the
+    direct kernel (the same table plus a zero-amplitude mode with n_x = 3)."""
+    k = 2
+    u = synthetic.turbulent_like(12, 10, 9, k, mach=3.0, seed=5)
+    modes = synthetic.forcing_table(4, amp=5.0)
+    extra = np.zeros((1, 9))
+    extra[0, :3] = (3.0, 0.0, 0.0)
+    out = []
+    for tab in (modes, np.vstack([modes, extra])):
+        ctx = make(12, 10, 9, k, FORCE, precision)
+        dg.dg_set_forcing(ctx, tab)
+        ud = dev(u, ctx)
+        o = torch.empty_like(ud)
+        dg.dg_rhs(ctx, ud, o, 1e-3)
+        out.append(host(o))
+    scale = np.abs(out[0]).max()
+    assert np.abs(out[0] - out[1]).max() <= (1e-13 if precision == dg.DG_FP64 else 1e-5) * scale
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_rhs_fp32(k):
     print(f"rhs fp32 k={k}", flush=True)
     modes = synthetic.forcing_table(2, amp=5.0)
@@ -204,6 +234,52 @@ def test_rk_step_retry_restores_state():
     u[0, 0] = 1.0
     ud = dev(u, ctx)
     assert dg.dg_rk_step(ctx, ud, 1e-3) == dg.DG_OK
+
+
+# States and time steps whose SSP-RK3 step passes the positivity check in its first two
+# stages and fails it in the last (found with the oracle: 6 x 5 x 4 cells, Mach 4, seed 0,
+# the given multiple of the CFL time step).
+LAST_STAGE_FAILURES = {1: 10.75, 2: 4.5, 3: 25.5}
+_SSPRK3 = [(0.0, 1.0, 1.0), (0.75, 0.25, 0.25), (1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0)]
+
+
+def _oracle_stage_minima(ocfg, u, dt):
+    """Smallest cell-mean density after each stage's combination (limited in between)."""
+    ui, out = u, []
+    for ca, cb, cc in _SSPRK3:
+        w = ca * u + cb * ui + cc * dt * oracle.rhs(ocfg, ui, dt)
+        out.append(w[0, 0].min())
+        ui, _, _ = oracle.limit(ocfg, w)
+    return out
+
+
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_last_stage_failure_leaves_state(k, precision):
+    """Only the last stage writes the caller's array, and its failure is decided from the
+    stage's density means before it writes: on DG_RETRY the array is bitwise the input."""
+    print(f"last-stage failure k={k} precision={precision}", flush=True)
+    u = synthetic.turbulent_like(6, 5, 4, k, mach=4.0, seed=0)
+    if precision == dg.DG_FP32:
+        u = u.astype(np.float32).astype(np.float64)
+    ocfg = _orc_cfg(6, 5, 4, k, ALL)
+    dt = LAST_STAGE_FAILURES[k] * oracle.dt_max(ocfg, u)
+    m = _oracle_stage_minima(ocfg, u, dt)
+    assert m[0] > 1e-2 and m[1] > 1e-2 and m[2] < -1e-2, m
+    assert oracle.rk_step(ocfg, u, dt)[1] == oracle.RETRY
+    ctx = make(6, 5, 4, k, ALL, precision)
+    ud = dev(u, ctx)
+    before = ud.clone()
+    assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_RETRY
+    assert torch.equal(ud, before)
+    rc, dt_next = dg.dg_rk_step_next(ctx, ud, dt, False)
+    assert rc == dg.DG_RETRY and dt_next is None
+    assert torch.equal(ud, before)
+    # the retry with a quarter of the step goes through and matches the oracle
+    rc, _ = dg.dg_rk_step_next(ctx, ud, 0.25 * dt, False)
+    ref, st = oracle.rk_step(ocfg, u, 0.25 * dt)
+    assert rc == dg.DG_OK and st == oracle.OK
+    assert max(field_rel(host(ud), ref, ref)) < TOL[precision]
 
 
 def test_bitwise_determinism():
