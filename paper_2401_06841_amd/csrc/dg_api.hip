@@ -442,7 +442,9 @@ static ProjArgs proj_args(const dg_ctx *c)
     pa.beta = c->cfg.beta_visc;
     pa.visc = (c->cfg.flags & DG_AV) && c->cfg.cfl_visc > 0.0;
     const bool learned = (c->cfg.flags & DG_LEARNED_SENSOR) && (c->cfg.flags & DG_AV) && c->have_nu;
-    pa.nu = learned ? c->wp(c->off.nu) : nullptr;
+    // learned_bounds_later: the learned cells' viscosities are reduced by the network's
+    // forward pass instead (the fused step's last stage, before the network has run)
+    pa.nu = learned && !c->learned_bounds_later ? c->wp(c->off.nu) : nullptr;
     pa.fb = learned ? (const int *)c->wp(c->off.fb) : nullptr;
     return pa;
 }
@@ -525,7 +527,7 @@ static bool use_meanfree(const dg_ctx *c)
 static int launch_abar(dg_ctx *c)
 {
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->rhs_nblk, 1,
-                       1.0, 0.0, c->abar(), (const int *)nullptr, (volatile long long *)nullptr, 0LL);
+                       1.0, 0.0, c->abar(), (const int *)nullptr, (volatile long long *)nullptr, 0LL, (const double *)nullptr, 0);
     LAUNCHCHK(c);
     return DG_OK;
 }
@@ -585,15 +587,16 @@ static int do_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
     return DG_OK;
 }
 
-// seq > 0: also publish the time step and the failure flag to the host (dg_ctx::PUB)
+// seq > 0: also publish the time step and the failure flag to the host (dg_ctx::PUB);
+// vmax: np2 further partial maxima of the viscosity (the learned cells'), or NULL
 template <typename T, int K>
-static int launch_dt_final(dg_ctx *c, double *dst, long long seq = 0)
+static int launch_dt_final(dg_ctx *c, double *dst, long long seq = 0, const double *vmax = nullptr, int np2 = 0)
 {
     const double hp = c->cfg.h / (K + 1);
     volatile long long *pub = seq > 0 ? (volatile long long *)(c->pinned + dg_ctx::PUB) : nullptr;
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->nblk, 2,
                        c->cfg.cfl * c->cfg.h / (K + 1), c->cfg.cfl_visc > 0.0 ? c->cfg.cfl_visc * hp * hp : 0.0,
-                       dst, (const int *)c->fail(), pub, seq);
+                       dst, (const int *)c->fail(), pub, seq, vmax, np2);
     LAUNCHCHK(c);
     return DG_OK;
 }
@@ -685,7 +688,8 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
         if (rc) return rc;
     }
     // learned sensor: the network's viscosity of the new state serves its time step (and the
-    // next step's stages), so the bounds are taken after the inference, not in the last stage
+    // next step's stages).  The last stage reduces the signal speeds and the fallback cells'
+    // viscosities; the network's forward pass on the new state reduces the learned cells'.
     const bool learned_next = dt_next && (c->cfg.flags & DG_LEARNED_SENSOR);
     int st_flag = 0;
     double dt_pub = 0.0;
@@ -704,19 +708,23 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
             if (rc) return rc;
         }
         void *vnext = !last ? vh[(s + 1) & 1] : (dt_next ? vh[0] : nullptr);
-        double *part = (last && dt_next && !learned_next) ? (double *)c->wp(c->off.part) : nullptr;
+        double *part = (last && dt_next) ? (double *)c->wp(c->off.part) : nullptr;
+        c->learned_bounds_later = learned_next && last;
         rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext, last, g.coef, dt,
                                 nullptr, part,
                                 g.w ? buf[g.w] : nullptr, g.wcoef);
+        c->learned_bounds_later = false;
         if (rc) return rc;
     }
     if (dt_next) {
+        const double *vmax = nullptr;
+        int nvmax = 0;
         if (learned_next) {
-            if ((rc = sensor_infer_impl(c, u))) return rc;
-            if ((rc = launch_project<T, K>(c, u, nullptr, (double *)c->wp(c->off.part), nullptr))) return rc;
+            if ((rc = sensor_infer_impl(c, u, &nvmax))) return rc;
+            if (proj_args(c).visc) vmax = (const double *)c->wp(c->off.mlp);
         }
         const long long seq = ++c->pub_seq;
-        rc = launch_dt_final<T, K>(c, c->scal() + 8, seq);
+        rc = launch_dt_final<T, K>(c, c->scal() + 8, seq, vmax, nvmax);
         if (rc) return rc;
         rc = wait_published(c, seq, &dt_pub, &st_flag);
         if (rc) return rc;
@@ -864,7 +872,7 @@ static int do_sums(dg_ctx *c, const void *u, double *out)
     LAUNCHCHK(c);
     const double h3 = c->cfg.h * c->cfg.h * c->cfg.h;
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)part, c->nblk, 0, h3, 0.0,
-                       c->scal() + 24, (const int *)nullptr, (volatile long long *)nullptr, 0LL);
+                       c->scal() + 24, (const int *)nullptr, (volatile long long *)nullptr, 0LL, (const double *)nullptr, 0);
     LAUNCHCHK(c);
     HIPCHK(c, hipMemcpyAsync(c->pinned, c->scal() + 24, 32, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));

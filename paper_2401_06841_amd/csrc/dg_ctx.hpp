@@ -48,6 +48,7 @@ struct dg_ctx {
     void *mlp_bf16 = nullptr;      // device copy of the parameters (fp32 master + bf16 weights)
     bool have_params = false;
     bool have_nu = false;
+    bool learned_bounds_later = false;   // see proj_args
     // kernel timing (dg_profile)
     static constexpr int NEV = 64;
     int prof = 0;                      // 0 off, 1 first-stage right-hand sides, 2 every launch
@@ -93,6 +94,8 @@ int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...);
                            __FILE__, __LINE__);                                                   \
     } while (0)
 
-int sensor_infer_impl(dg_ctx *c, const void *u);
+// nvmax != NULL: the forward pass also writes the learned cells' largest viscosity per block
+// into the mlp region (as doubles) and *nvmax = the number of blocks
+int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax = nullptr);
 void stats_release(dg_ctx *c);
 int sensor_reset_flags(dg_ctx *c);

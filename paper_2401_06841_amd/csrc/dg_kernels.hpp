@@ -212,7 +212,9 @@ struct ProjArgs {
     double cs, h, alpha, beta;
     int visc;           // also reduce the largest bulk viscosity of the viscous pressure
     const void *nu;     // learned per-cell bulk viscosity (element type T), or NULL
-    const int *fb;      // fallback flags of the learned sensor (1 = plain sensor)
+    const int *fb;      // fallback flags of the learned sensor (1 = plain sensor), or NULL;
+                        // with fb set and nu NULL a learned cell adds nothing here (its
+                        // viscosity is reduced where the network writes it)
 };
 
 struct StageArgs {
@@ -1136,7 +1138,7 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
             }
             const double s = -smin * (2.0 / pa.h);
             if (s > 0.0) nm = pa.alpha * hp * hp * s + pa.beta * pa.cs * hp;
-            if (pa.nu && pa.fb[c] == 0) nm = fmax((double)((const T *)pa.nu)[c], 0.0);
+            if (pa.fb && pa.fb[c] == 0) nm = pa.nu ? fmax((double)((const T *)pa.nu)[c], 0.0) : 0.0;
         }
         __syncthreads();
         sm = block_max(active ? sm : 0.0, lds);
@@ -1426,14 +1428,15 @@ __global__ void __launch_bounds__(BLOCK) k_sums(const void *u_, Mesh g, double *
 // mode 0: out[i] = scale * sum part[.][i], i < 4
 // mode 1: out[0..2] = sum part[.][0..2] / sum part[.][3]   (mass-weighted mean acceleration)
 // mode 2: out[0] = min(scale / max part[.][0], scale2 / max part[.][1])   (time step; the
-//         second term only when scale2 > 0 and the maximum is positive)
+//         second term only when scale2 > 0 and the maximum is positive); the second
+//         maximum also runs over part2[0 .. np2) when part2 is not null
 // Publication (mode 2, pub != null): the time step and the step's failure flag are also
 // stored into pub (pinned host memory: pub[1] = the bits of dt, pub[2] = *fail), and then
 // pub[0] = seq, each store made visible to the host before the next; the host waits for
 // pub[0] == seq instead of copying the values back and synchronising the stream.
 static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double scale2,
                                                  double *out, const int *fail, volatile long long *pub,
-                                                 long long seq)
+                                                 long long seq, const double *part2, int np2)
 {
     __shared__ double lds[16];
     if (mode == 2) {
@@ -1442,6 +1445,8 @@ static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int 
             m = fmax(m, part[2 * i]);
             n = fmax(n, part[2 * i + 1]);
         }
+        if (part2)
+            for (int i = threadIdx.x; i < np2; i += BLOCK) n = fmax(n, part2[i]);
         m = block_max(m, lds);
         __syncthreads();
         n = block_max(n, lds);

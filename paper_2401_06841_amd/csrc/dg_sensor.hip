@@ -147,11 +147,17 @@ __device__ __forceinline__ void forward_tile(const float *__restrict__ x, int ro
 
 // ------------------------------------------------------------------ forward
 // y[n] from x[n][20]; with nu != nullptr the output is the viscosity
-// nu = nu0 (exp(y) - 1), clipped at zero, stored in the state's element type.
+// nu = nu0 (exp(y) - 1), clipped at zero, stored in the state's element type.  With vmax
+// != nullptr each block also writes vmax[block] = the largest stored viscosity of its cells
+// whose fallback flag fb is 0 (0 if none): the learned cells' part of the viscous time-step
+// bound.
 template <typename T>
 __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P, const float *__restrict__ x, int n,
-                                                     float *__restrict__ y, T *__restrict__ nu)
+                                                     float *__restrict__ y, T *__restrict__ nu,
+                                                     const int *__restrict__ fb, double *__restrict__ vmax)
 {
+    __shared__ double bmax[4];
+    double vm = 0.0;
     __shared__ TileLds lds[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
     Net w;
@@ -167,9 +173,19 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float *__restrict__ P
                 const int r = tile * 16 + 4 * g + j;
                 if (r >= n) continue;
                 if (y) y[r] = yy[j];
-                if (nu) nu[r] = (T)fmax(NU0 * expm1((double)yy[j]), 0.0);
+                if (nu) {
+                    const T v = (T)fmax(NU0 * expm1((double)yy[j]), 0.0);
+                    nu[r] = v;
+                    if (vmax && fb[r] == 0) vm = fmax(vm, fmax((double)v, 0.0));
+                }
             }
         }
+    }
+    if (vmax) {
+        vm = wave_max(vm);
+        if (lane == 0) bmax[wave] = vm;
+        __syncthreads();
+        if (threadIdx.x == 0) vmax[blockIdx.x] = fmax(fmax(bmax[0], bmax[1]), fmax(bmax[2], bmax[3]));
     }
 }
 
@@ -502,7 +518,7 @@ int dg_mlp_forward(dg_ctx *c, const float *P, const float *x, int n, float *y)
     if (!P || !x || !y || n < 0) return dg_fail(c, DG_EINVAL, "bad network arguments");
     if (n == 0) return DG_OK;
     hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(c, n)), dim3(256), 0, c->stream, P, x, n, y,
-                       (float *)nullptr);
+                       (float *)nullptr, (const int *)nullptr, (double *)nullptr);
     LAUNCHCHK(c);
     return DG_OK;
 }
@@ -590,7 +606,7 @@ int dg_sensor_targets(dg_ctx *c, const void *u, float *t)
     return labels_any(c, u, t);
 }
 
-int sensor_infer_impl(dg_ctx *c, const void *u)
+int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax)
 {
     int rc = need_k2(c);
     if (rc) return rc;
@@ -598,15 +614,17 @@ int sensor_infer_impl(dg_ctx *c, const void *u)
     float *x = (float *)c->wp(c->off.feat);
     rc = dg_sensor_features(c, u, x);
     if (rc) return rc;
+    const int nblk = fwd_blocks(c, c->nc);
+    const int *fb = nvmax ? (const int *)c->wp(c->off.fb) : nullptr;
+    double *vmax = nvmax ? (double *)c->wp(c->off.mlp) : nullptr;
     if (c->es == 8)
-        hipLaunchKernelGGL((k_mlp_forward<double>), dim3(fwd_blocks(c, c->nc)), dim3(256), 0, c->stream,
-                           (const float *)c->mlp_bf16, (const float *)x, c->nc, (float *)nullptr,
-                           (double *)c->wp(c->off.nu));
+        hipLaunchKernelGGL((k_mlp_forward<double>), dim3(nblk), dim3(256), 0, c->stream, (const float *)c->mlp_bf16,
+                           (const float *)x, c->nc, (float *)nullptr, (double *)c->wp(c->off.nu), fb, vmax);
     else
-        hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(c, c->nc)), dim3(256), 0, c->stream,
-                           (const float *)c->mlp_bf16, (const float *)x, c->nc, (float *)nullptr,
-                           (float *)c->wp(c->off.nu));
+        hipLaunchKernelGGL((k_mlp_forward<float>), dim3(nblk), dim3(256), 0, c->stream, (const float *)c->mlp_bf16,
+                           (const float *)x, c->nc, (float *)nullptr, (float *)c->wp(c->off.nu), fb, vmax);
     LAUNCHCHK(c);
+    if (nvmax) *nvmax = nblk;
     c->have_nu = true;
     return DG_OK;
 }
