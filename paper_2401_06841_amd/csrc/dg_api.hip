@@ -620,7 +620,8 @@ static int wait_published(dg_ctx *c, long long seq, double *dt, int *fail_flag)
                 pub[2] = f;
                 break;
             }
-            if (q != hipErrorNotReady) HIPCHK(c, q);
+            if (q != hipErrorNotReady)
+                return dg_fail(c, DG_EHIP, "stream query while waiting for the step failed: %s", hipGetErrorString(q));
         }
     }
     std::atomic_thread_fence(std::memory_order_acquire);

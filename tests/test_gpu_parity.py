@@ -96,6 +96,25 @@ def test_separable_and_direct_driving_fields_agree(precision):
     assert np.abs(out[0] - out[1]).max() <= (1e-13 if precision == dg.DG_FP64 else 1e-5) * scale
 
 
+def test_forcing_table_updates_in_a_row():
+    """Table uploads go through a small ring of pinned slots: ten updates without a step in
+    between (more than the ring holds) leave exactly the last table in effect."""
+    k = 2
+    u = synthetic.turbulent_like(8, 7, 6, k, mach=3.0, seed=11)
+    last = synthetic.forcing_table(99, amp=4.0)
+    outs = []
+    for tables in ([synthetic.forcing_table(s, amp=1.0 + s) for s in range(9)] + [last], [last]):
+        ctx = make(8, 7, 6, k, FORCE)
+        for t in tables:
+            dg.dg_set_forcing(ctx, t)
+        ud = dev(u, ctx)
+        o = torch.empty_like(ud)
+        dg.dg_rhs(ctx, ud, o, 1e-3)
+        outs.append(host(o))
+        assert np.array_equal(dg.dg_forcing_get(ctx), last)
+    assert np.array_equal(outs[0], outs[1])
+
+
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_rhs_fp32(k):
     print(f"rhs fp32 k={k}", flush=True)
