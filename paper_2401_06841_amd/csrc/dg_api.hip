@@ -721,7 +721,8 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
         const double *vmax = nullptr;
         int nvmax = 0;
         if (learned_next) {
-            if ((rc = sensor_infer_impl(c, u, &nvmax))) return rc;
+            // the last stage left the projection of u^(n+1) in vh0 (unless the step failed)
+            if ((rc = sensor_infer_impl(c, u, &nvmax, vh[0]))) return rc;
             if (proj_args(c).visc) vmax = (const double *)c->wp(c->off.mlp);
         }
         const long long seq = ++c->pub_seq;

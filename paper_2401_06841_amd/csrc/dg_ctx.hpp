@@ -95,7 +95,8 @@ int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...);
     } while (0)
 
 // nvmax != NULL: the forward pass also writes the learned cells' largest viscosity per block
-// into the mlp region (as doubles) and *nvmax = the number of blocks
-int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax = nullptr);
+// into the mlp region (as doubles) and *nvmax = the number of blocks; vhat != NULL: the
+// projected velocity of u, used by the features unless the step's failure flag is raised
+int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax = nullptr, const void *vhat = nullptr);
 void stats_release(dg_ctx *c);
 int sensor_reset_flags(dg_ctx *c);

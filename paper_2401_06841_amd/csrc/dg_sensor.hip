@@ -375,9 +375,11 @@ __global__ void __launch_bounds__(256) k_mlp_adam(float *__restrict__ P, const f
 //            D_1 = 3 sqrt(5) V_x,(200) + 3 V_y,(110) + 3 V_z,(101) (and cyclic), times 2/h,
 //            scaled by (h/3)/cs
 //   [19]     |mean velocity|/cs
+// vhat: the projected velocity of u already at hand (same arithmetic as project_cell), used
+// unless *fail is raised (then u is not the state vhat belongs to); NULL: project here.
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_features(const void *u_, float *__restrict__ x, const void *tab_, Mesh g,
-                                                    double cs)
+                                                    double cs, const void *vhat, const int *fail)
 {
     constexpr int K = 2, NB = Shape<K>::NB;
     const int nc = g.nc;
@@ -386,9 +388,15 @@ __global__ void __launch_bounds__(BLOCK) k_features(const void *u_, float *__res
     const int c = active ? c0 : 0;
     const unsigned bo = (unsigned)c * sizeof(T);
     T W[4][NB];
-    load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
     T V[3][NB];
-    project_cell<T, K>(W, as_tab<T>(tab_), V, nullptr, T(0));
+    if (vhat && !*fail) {
+#pragma unroll
+        for (int l = 0; l < NB; ++l) W[0][l] = Field<T, 1>(u_, NB, nc).get(0, l, bo);
+        load_field<T, K, 3>(Field<T, 3>(vhat, NB, nc), bo, V);
+    } else {
+        load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
+        project_cell<T, K>(W, as_tab<T>(tab_), V, nullptr, T(0));
+    }
     if (!active) return;
     const double r0 = (double)W[0][0];
     float *xc = x + (size_t)c * NIN;
@@ -555,19 +563,27 @@ int dg_sensor_set_params(dg_ctx *c, const float *P)
     return DG_OK;
 }
 
+static int launch_features(dg_ctx *c, const void *u, float *x, const void *vhat)
+{
+    const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    const int *fail = (const int *)c->fail();
+    if (c->es == 8)
+        hipLaunchKernelGGL((k_features<double>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, x, c->tab, g, c->cfg.cs,
+                           vhat, fail);
+    else
+        hipLaunchKernelGGL((k_features<float>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, x, c->tab, g, c->cfg.cs,
+                           vhat, fail);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
 int dg_sensor_features(dg_ctx *c, const void *u, float *x)
 {
     if (!c) return DG_EINVAL;
     int rc = need_k2(c);
     if (rc) return rc;
     if (!u || !x) return dg_fail(c, DG_EINVAL, "null pointer");
-    const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
-    if (c->es == 8)
-        hipLaunchKernelGGL((k_features<double>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, x, c->tab, g, c->cfg.cs);
-    else
-        hipLaunchKernelGGL((k_features<float>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, x, c->tab, g, c->cfg.cs);
-    LAUNCHCHK(c);
-    return DG_OK;
+    return launch_features(c, u, x, nullptr);
 }
 
 template <typename T, int K, typename OUT>
@@ -606,13 +622,14 @@ int dg_sensor_targets(dg_ctx *c, const void *u, float *t)
     return labels_any(c, u, t);
 }
 
-int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax)
+int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax, const void *vhat)
 {
     int rc = need_k2(c);
     if (rc) return rc;
     if (!c->have_params) return dg_fail(c, DG_ESTATE, "no network parameters (dg_sensor_set_params)");
     float *x = (float *)c->wp(c->off.feat);
-    rc = dg_sensor_features(c, u, x);
+    if (!u) return dg_fail(c, DG_EINVAL, "u is null");
+    rc = launch_features(c, u, x, vhat);
     if (rc) return rc;
     const int nblk = fwd_blocks(c, c->nc);
     const int *fb = nvmax ? (const int *)c->wp(c->off.fb) : nullptr;
