@@ -1157,8 +1157,13 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
 // of the same operands, then the positivity limiter (Sec. 3.1; target minimum
 // max(floor, rel * mean)) with FP64 comparisons, then the projected velocity of the
 // result for the next stage.
+// occupancy of the stage kernel (waves per SIMD), pinned at what its registers allow so that
+// small code changes cannot silently drop a wave (FP64 at degree 2: 128 VGPRs for 4 waves)
 template <typename T, int K>
-__global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
+constexpr int stage_waves() { return sizeof(T) == 8 ? (K == 1 ? 7 : (K == 2 ? 4 : 2)) : (K == 1 ? 7 : (K == 2 ? 5 : 3)); }
+
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stage_waves<T, K>()))) k_stage(StageArgs a)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -1207,39 +1212,57 @@ __global__ void __launch_bounds__(BLOCK) k_stage(StageArgs a)
             }
     }
     if (a.flags & F_LIMIT) {
-        // minimum density over the volume and face Gauss points
-        T rmin = T(__builtin_huge_valf());
-#pragma unroll 1
-        for (int q = 0; q < S::NQ; ++q) {
-            ctab<T> *ph = tab + TL::VPHI + q * NB;
-            T r = T(0);
-#pragma unroll
-            for (int l = 0; l < NB; ++l) r += U[0][l] * ph[l];
-            rmin = fmin(rmin, r);
-        }
-        ctab<T> *lend = tab + TL::LEND;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                T C[S::NB2];
-#pragma unroll
-                for (int j = 0; j < S::NB2; ++j) C[j] = T(0);
-#pragma unroll
-                for (int l = 0; l < NB; ++l) C[M.d2[d][l]] += U[0][l] * lend[2 * M.e[l][d] + s];
-#pragma unroll 1
-                for (int r = 0; r < S::NF; ++r) {
-                    ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
-                    T val = T(0);
-#pragma unroll
-                    for (int j = 0; j < S::NB2; ++j) val += C[j] * f2[j];
-                    rmin = fmin(rmin, val);
-                }
-            }
         const double mean = (double)U[0][0];
         const double fl = a.rho_floor;
-        const double rm = (double)rmin;
         const double target = fmax(fl, a.rho_floor_rel * mean);
+        // The density at any point of the cell differs from the mean by at most
+        // dev = sum_{l>0} |W_l| max|phi_l|, with max|phi_l| = prod_a sqrt(2 e_a + 1) (the
+        // normalised Legendre polynomials peak at the cell faces).  When mean - dev clears
+        // the target with a margin for the rounding of the point sums, the minimum below
+        // cannot fall short of the target and the limiter leaves the cell as it is; a wave
+        // whose cells all clear it skips the point evaluations (same result).
+        double dev = 0.0;
+#pragma unroll
+        for (int l = 1; l < NB; ++l) {
+            double pm = 1.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) pm *= __builtin_sqrt(2.0 * M.e[l][d] + 1.0);
+            dev += fabs((double)U[0][l]) * pm;
+        }
+        constexpr double EPS = sizeof(T) == 8 ? 1e-13 : 1e-5;
+        const bool clear = !active || mean - dev - EPS * (fabs(mean) + dev) >= target;
+        // minimum density over the volume and face Gauss points
+        T rmin = T(__builtin_huge_valf());
+        if (!__all(clear)) {
+#pragma unroll 1
+            for (int q = 0; q < S::NQ; ++q) {
+                ctab<T> *ph = tab + TL::VPHI + q * NB;
+                T r = T(0);
+#pragma unroll
+                for (int l = 0; l < NB; ++l) r += U[0][l] * ph[l];
+                rmin = fmin(rmin, r);
+            }
+            ctab<T> *lend = tab + TL::LEND;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    T C[S::NB2];
+#pragma unroll
+                    for (int j = 0; j < S::NB2; ++j) C[j] = T(0);
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) C[M.d2[d][l]] += U[0][l] * lend[2 * M.e[l][d] + s];
+#pragma unroll 1
+                    for (int r = 0; r < S::NF; ++r) {
+                        ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
+                        T val = T(0);
+#pragma unroll
+                        for (int j = 0; j < S::NB2; ++j) val += C[j] * f2[j];
+                        rmin = fmin(rmin, val);
+                    }
+                }
+        }
+        const double rm = (double)rmin;
         int bad = 0;
         if (!(mean > fl)) {
             bad = active ? 1 : 0;
