@@ -196,6 +196,30 @@ def test_limiter_and_sums(k):
     assert dg.dg_limit(ctx, bd) == 1
 
 
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_limiter_waves_that_skip_the_point_sums(k, precision):
+    """64 x 3 x 2 cells, so that every wave holds one x line: five smooth lines, where a
+    modal bound already shows that no point can fall below the target (those waves skip the
+    point evaluations), and one line with strong high modes that the limiter must scale."""
+    u = synthetic.turbulent_like(64, 3, 2, k, mach=0.5, seed=31, high_amp=0.01)
+    rough = synthetic.turbulent_like(64, 3, 2, k, mach=4.0, seed=32, high_amp=0.9)
+    line = np.arange(64)                                  # cells of the line y = 0, z = 0
+    u[:, :, line] = rough[:, :, line]
+    if precision == dg.DG_FP32:
+        u = u.astype(np.float32).astype(np.float64)
+    ocfg = _orc_cfg(64, 3, 2, k, ALL)
+    lim, nfail, theta = oracle.limit(ocfg, u)
+    assert nfail == 0
+    assert (theta[line] < 1).sum() > 3 and np.all(theta[64:] == 1)
+    ctx = make(64, 3, 2, k, ALL, precision)
+    ud = dev(u, ctx)
+    assert dg.dg_limit(ctx, ud) == 0
+    got = host(ud)
+    assert max(field_rel(got, lim, lim)) < (1e-13 if precision == dg.DG_FP64 else 1e-6)
+    assert np.array_equal(got[:, :, 64:], host(dev(u, ctx))[:, :, 64:])   # smooth lines untouched
+
+
 def test_c1_sound_wave_20_steps():
     """16^3, degree 1, sound wave of amplitude 1e-3 along a seeded axis, 20 SSP-RK3 steps
     at CFL 0.3 (dt from the oracle's CFL rule on the oracle's state)."""
