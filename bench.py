@@ -53,11 +53,25 @@ WORKLOADS = {
     # (RMS Mach grows as (sigma^2 t_c)^(1/3), Sec. 4.2; the calibration is statistical):
     # sigma 2.5 gives Mach 3.07 at t = 2.7 t_c, sigma 28 gives Mach 9.1 at t = 2.4 t_c
     # (sigma 40 reached Mach 11 and then stalled in positivity retries)
+    "c1": (16, 1, "fp64", 0.0, 0.0, 20),
     "c2": (64, 2, "fp64", 3.0, 2.5, 4000),
     "c3": (128, 3, "fp32", 10.0, 28.0, 1000),
     "c4": (128, 2, "fp32", 10.0, 28.0, 1000),
     "c5": (256, 2, "fp32", 10.0, 28.0, 1500),
 }
+
+
+# workloads without driving, artificial viscosity or projection: the 16^3 degree-1 sound wave
+# (positivity limiter only).  At 4,096 cells it is bound by launch latency, not by the
+# kernels' arithmetic or memory traffic.
+UNDRIVEN = {"c1"}
+
+
+def workload_flags(workload):
+    from paper_2401_06841_amd import dg
+    if workload in UNDRIVEN:
+        return dg.DG_POS_LIMITER
+    return dg.DG_AV | dg.DG_PRIM_PROJ | dg.DG_POS_LIMITER | dg.DG_FORCING | dg.DG_FORCE_MEANFREE
 
 
 # the sources that define and launch the step kernels (the counters in profiles/ are valid
@@ -110,7 +124,7 @@ def _timed(sim, steps, measure_profile):
 
 
 def _summary(args, sim, precision, wall, prof, retries, dt_min):
-    from paper_2401_06841_amd import model
+    from paper_2401_06841_amd import dg, model
     cfg = sim.cfg
     k = cfg.degree
     dof = 4 * cfg.nb * cfg.ncell
@@ -120,7 +134,9 @@ def _summary(args, sim, precision, wall, prof, retries, dt_min):
     if prof:
         rhs_ms, rhs_n, st_ms, st_n = prof
         avg = rhs_ms / max(rhs_n, 1)
-        flops = model.rhs_flops_per_cell(k, av=True, proj=True, forcing=True) * cfg.ncell
+        fl = cfg.flags
+        flops = model.rhs_flops_per_cell(k, av=bool(fl & dg.DG_AV), proj=bool(fl & dg.DG_PRIM_PROJ),
+                                         forcing=bool(fl & dg.DG_FORCING)) * cfg.ncell
         achieved = flops / (avg * 1e-3) / 1e12
         peak = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
         out["kernels"] = {"k_rhs_avg_ms": avg, "k_rhs_launches": rhs_n,
@@ -207,11 +223,18 @@ def run_gpu(args, precision, measure_profile=True):
     from paper_2401_06841_amd.driver import Driving, Simulation
 
     N, k, _, mach, sigma, _ = WORKLOADS[args.workload]
-    flags = dg.DG_AV | dg.DG_PRIM_PROJ | dg.DG_POS_LIMITER | dg.DG_FORCING | dg.DG_FORCE_MEANFREE
+    flags = workload_flags(args.workload)
     prec = dg.DG_FP64 if precision == "fp64" else dg.DG_FP32
     cfg = dg.Config(N, N, N, degree=k, precision=prec, flags=flags)
-    drv = Driving(mach, sigma, seed=args.seed)
-    sim = Simulation(cfg, driving=drv)
+    if args.workload in UNDRIVEN:
+        import synthetic
+        drv = None
+        u = torch.as_tensor(synthetic.c1_modal_state(args.seed, N), device="cuda").to(
+            torch.float64 if prec == dg.DG_FP64 else torch.float32).contiguous()
+        sim = Simulation(cfg, u=u, driving=None)
+    else:
+        drv = Driving(mach, sigma, seed=args.seed)
+        sim = Simulation(cfg, driving=drv)
     learned = (not args.no_compare) and (not args.no_learned) and k == 2
     # snapshots for the sensor training: at most about 1e7 cells (at least one snapshot)
     nsnap = max(1, min(args.snapshots, args.warmup // args.snapshot_every, int(1e7) // cfg.ncell)) if learned else 0
@@ -224,7 +247,7 @@ def run_gpu(args, precision, measure_profile=True):
         if args.verbose and (i + 1) % 1000 == 0:
             print(f"warm-up step {i + 1}: t={sim.t:.4f} rms Mach {sim.rms_mach():.3f}", file=sys.stderr, flush=True)
     u0 = sim.u.clone()
-    drive0 = sim.driving_state()
+    drive0 = sim.driving_state() if drv is not None else None
     wall, prof, retries, dt_min = _timed(sim, args.steps, measure_profile)
     main = _summary(args, sim, precision, wall, prof, retries, dt_min)
     if not args.no_stats:
@@ -247,7 +270,8 @@ def run_gpu(args, precision, measure_profile=True):
                 dtype = torch.float32 if other == "fp32" else torch.float64
                 sim2 = Simulation(cfg2, u=u0.to(dtype).contiguous(), driving=drv,
                                   sensor_params=params if use_learned else None)
-                sim2.set_driving_state(drive0)
+                if drive0 is not None:
+                    sim2.set_driving_state(drive0)
                 w2, p2, r2, d2 = _timed(sim2, args.steps, measure_profile)
                 rec = _summary(args, sim2, other, w2, p2, r2, d2)
                 rec["vs_main"] = analysis.compare(sim2.u, ref, k, (N, N, N), sim2.ctx, sim.ctx)
@@ -274,13 +298,19 @@ def run_cpu_baseline(args):
     import synthetic
 
     N, k, _, mach, sigma, _ = WORKLOADS[args.workload]
-    flags = oracle.AV | oracle.PRIM_PROJ | oracle.POS_LIMITER | oracle.FORCING | oracle.FORCE_MEANFREE
-    cfg = oracle.Cfg(N, N, N, k, flags=flags)
-    u = synthetic.turbulent_like(N, N, N, k, mach=mach, seed=args.seed, high_amp=0.02, kmax_frac=0.125)
-    modes = synthetic.forcing_table(args.seed, amp=sigma)
+    if args.workload in UNDRIVEN:
+        cfg = oracle.Cfg(N, N, N, k, flags=oracle.POS_LIMITER)
+        u = synthetic.c1_modal_state(args.seed, N)
+        modes = None
+    else:
+        flags = oracle.AV | oracle.PRIM_PROJ | oracle.POS_LIMITER | oracle.FORCING | oracle.FORCE_MEANFREE
+        cfg = oracle.Cfg(N, N, N, k, flags=flags)
+        u = synthetic.turbulent_like(N, N, N, k, mach=mach, seed=args.seed, high_amp=0.02, kmax_frac=0.125)
+        modes = synthetic.forcing_table(args.seed, amp=sigma)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     if N <= 64:
-        nsteps = args.cpu_steps
+        # the 16^3 workload takes milliseconds per step: time enough steps for a stable figure
+        nsteps = max(args.cpu_steps, 200) if args.workload in UNDRIVEN else args.cpu_steps
         t0 = time.perf_counter()
         for _ in range(nsteps):
             dt = oracle.dt_max(cfg, u)
@@ -359,8 +389,11 @@ def main():
         "dtype": "f64" if precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {N}^3 cells, degree {k} ({(k + 1) * (k + 2) * (k + 3) // 6} modes/var, "
-                               f"{(k + 1) ** 3} Gauss points), isothermal Euler, AV + primitive projection + "
-                               f"positivity limiter, mean-free OU driving (target RMS Mach {mach:g})",
+                               f"{(k + 1) ** 3} Gauss points), isothermal Euler, " + (
+                                   "sound wave of amplitude 1e-3, positivity limiter only (launch-latency bound: "
+                                   "the roofline fraction does not measure the kernels)" if args.workload in UNDRIVEN
+                                   else f"AV + primitive projection + positivity limiter, mean-free OU driving "
+                                        f"(target RMS Mach {mach:g})"),
                    "cells": N ** 3, "degree": k, "dof": 4 * ((k + 1) * (k + 2) * (k + 3) // 6) * N ** 3,
                    "parallelism": "single GPU"},
         "roofline": main_run.get("roofline"),

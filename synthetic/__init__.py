@@ -47,6 +47,25 @@ def c1_axis(seed: int) -> int:
     return int(np.random.default_rng(seed).integers(3))
 
 
+def c1_modal_state(seed: int, n: int = 16, amp: float = 1e-3, cs: float = 1.0):
+    """Degree-1 modal state [4][4][n^3] of the 16^3 sound-wave workload for throughput runs:
+    each cell takes the wave's value at its centre as the mean and its local slope as the
+    linear mode along the propagation axis (first-order Taylor form, not a projection).
+    Cells are x fastest; modes in graded order (000), (100), (010), (001)."""
+    axis = c1_axis(seed)
+    h = 1.0 / n
+    idx = np.indices((n, n, n))                          # [z, y, x] grids
+    xc = (idx[2 - axis].reshape(-1) + 0.5) * h          # centre coordinate along the axis
+    s = amp * np.sin(2.0 * np.pi * xc)
+    ds = amp * 2.0 * np.pi * np.cos(2.0 * np.pi * xc) * h / (2.0 * np.sqrt(3.0))
+    u = np.zeros((4, 4, n ** 3))
+    u[0, 0] = 1.0 + s
+    u[0, 1 + axis] = ds
+    u[1 + axis, 0] = cs * s
+    u[1 + axis, 1 + axis] = cs * ds
+    return u
+
+
 def _smooth(rng, shape, kmax: float, slope: float):
     """Unit-variance periodic random field on a grid (nz, ny, nx) with power ~ |k|^-slope, |k| <= kmax."""
     nz, ny, nx = shape
