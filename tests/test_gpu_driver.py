@@ -181,6 +181,30 @@ def test_learned_fused_steps_match_plain_steps_bitwise(precision):
     assert torch.equal(ua, ub)
 
 
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+def test_learned_fused_step_failure_keeps_state_and_viscosity(precision):
+    """A fused learned step that fails its positivity check leaves u^n in place, and the
+    viscosity the step stores is that of u^n (the network runs on u after the stages; with
+    the failure flag raised it projects u afresh instead of reading the stage's projection):
+    the time step afterwards equals dg_sensor_infer + dg_dt_max of u^n."""
+    n, k = 8, 2
+    flags = FLAGS | dg.DG_LEARNED_SENSOR
+    u0 = synthetic.turbulent_like(n, n, n, k, mach=4.0, seed=13, high_amp=0.05, kmax_frac=0.25)
+    ctx = make(n, n, n, k, flags, precision)
+    dg.dg_set_forcing(ctx, synthetic.forcing_table(5, amp=2.0))
+    dg.dg_sensor_set_params(ctx, _flat_params(6))
+    u = dev(u0, ctx)
+    before = u.clone()
+    dg.dg_sensor_infer(ctx, u)
+    dt_ref = dg.dg_dt_max(ctx, u)
+    rc, dt_next = dg.dg_rk_step_next(ctx, u, 300.0 * dt_ref, False)
+    assert rc == dg.DG_RETRY and dt_next is None
+    assert torch.equal(u, before)
+    assert dg.dg_dt_max(ctx, u) == dt_ref
+    rc, _ = dg.dg_rk_step_next(ctx, u, dt_ref, False)
+    assert rc == dg.DG_OK
+
+
 def test_learned_driver_run_with_judge():
     """Driver with the learned sensor: judge every 3 steps, fused steps in between; the run
     stays finite and the judge keeps a count per judgement."""
