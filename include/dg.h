@@ -154,6 +154,23 @@ int dg_rk_step(dg_ctx *ctx, void *u, double dt, int *status_host);
  * of the returned value.  DG_ESTATE when no viscosity is stored yet. */
 int dg_rk_step_next(dg_ctx *ctx, void *u, double dt, int reuse, int *status_host, double *dt_next_host);
 
+/* dg_rk_step_next that also launches the next step's first stage ahead of the caller: when
+ * the step succeeds and *dt_next_host < horizon, the right-hand side, mean acceleration and
+ * stage kernel of the first stage of the next step (from u^(n+1), with *dt_next_host) are
+ * queued before the call returns.  They write only workspace buffers.  The next
+ * dg_rk_step_next or dg_rk_step_next_ahead call on the same array with dt equal to that
+ * time step and reuse = 1 continues from them instead of launching them again, so the GPU
+ * is not idle while the caller prepares the call.  Any other outcome discards them:
+ *   - a different array or time step, or reuse = 0;
+ *   - a state-changing call in between (dg_rhs, dg_rk_step, dg_limit, dg_set_workspace);
+ *   - dg_set_forcing, dg_forcing_ou_advance or dg_forcing_ou_set;
+ *   - any dg_sensor_set_params, dg_sensor_infer, dg_sensor_judge or dg_sensor_set_nu.
+ * The results are the same either way.  horizon <= 0 never launches ahead; a driver passes the
+ * time left before its next driving update, so that no launched stage is discarded for one.
+ * Errors as dg_rk_step_next; DG_EINVAL for a NaN horizon. */
+int dg_rk_step_next_ahead(dg_ctx *ctx, void *u, double dt, int reuse, double horizon, int *status_host,
+                          double *dt_next_host);
+
 /* Time step dt = min(dt_adv, dt_visc), reduced in FP64 over all cells and interior points:
  * dt_adv = cfl h / ((k+1) max sum_d (|m_d/rho| + cs)) (Sec. 7: dt proportional to h/(k+1));
  * with DG_AV and cfl_visc > 0, dt_visc = cfl_visc (h/p)^2 / max nu, the explicit stability

@@ -322,6 +322,7 @@ int dg_set_forcing(dg_ctx *c, const double *modes_host, int nmodes)
         return dg_fail(c, DG_EINVAL, "bad forcing table (nmodes=%d)", nmodes);
     std::memcpy(c->modes_host, modes_host, sizeof(double) * 9 * nmodes);
     c->nmodes = nmodes;
+    c->spec_valid = false;          // a launched next stage used the previous field
     bool sep = true;
     for (int m = 0; m < nmodes; ++m)
         for (int a = 0; a < 3; ++a) {
@@ -475,7 +476,7 @@ struct StagePred {
 
 template <typename T, int K>
 static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt, int *fail_reset = nullptr,
-                      const StagePred *pred = nullptr)
+                      const StagePred *pred = nullptr, const double *dt_dev = nullptr)
 {
     if ((c->cfg.flags & DG_FORCING) && c->forcing_dirty) {
         int rc = launch_forcing_points<T, K>(c);
@@ -506,6 +507,7 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     a.alpha = c->cfg.alpha_visc;
     a.beta = c->cfg.beta_visc;
     a.dt = dt;
+    a.dt_dev = dt_dev;
     int rc = prof_mark(c, 0, 0);
     if (rc) return rc;
     if constexpr (rhs_pair<T, K>()) {
@@ -535,7 +537,8 @@ static int launch_abar(dg_ctx *c)
 template <typename T, int K>
 static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
                         bool skip_if_failed, const double (&coef)[3], double dt, long long *nlim, double *part = nullptr,
-                        void *w = nullptr, const double (&wcoef)[3] = {0.0, 0.0, 0.0})
+                        void *w = nullptr, const double (&wcoef)[3] = {0.0, 0.0, 0.0},
+                        const double *dt_dev = nullptr)
 {
     StageArgs a;
     a.ui = ui;
@@ -561,6 +564,7 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.wb = wcoef[1];
     a.wc = wcoef[2];
     a.dt = dt;
+    a.dt_dev = dt_dev;
     a.rho_floor = c->cfg.rho_floor;
     a.rho_floor_rel = c->cfg.rho_floor_rel;
     int rc = prof_mark(c, 1, 0);
@@ -671,63 +675,90 @@ static const Scheme &scheme_of(const dg_ctx *c)
     return c->k == 1 ? SSPRK2 : (c->k == 2 ? SSPRK3 : SSPRK54);
 }
 
-// One Runge-Kutta step.  reuse: start from the projection kept by the previous step of
-// this context (when it is still valid); dt_next: also compute the time step of the new
-// state in the last stage (its projection is then kept in vh0).
+// Stage s of the scheme: right-hand side, mean acceleration, stage kernel.  reset_fail:
+// this right-hand side clears the failure flag (a first stage starting from a kept
+// projection); want_next: the step also returns the next time step (the last stage keeps the
+// projection of the new state and reduces its time-step maxima).
 template <typename T, int K>
-static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, double *dt_next)
+static int launch_step_stage(dg_ctx *c, void *u, int s, double dt, bool reset_fail, bool want_next,
+                             const double *dt_dev = nullptr)
 {
     const Scheme &S = scheme_of(c);
     void *vh[2] = {c->wp(c->off.vh0), c->wp(c->off.vh1)};
     void *buf[4] = {u, c->wp(c->off.stA), c->wp(c->off.stB), c->wp(c->off.stC)};
+    const StageSpec &g = S.s[s];
+    const bool last = s == S.stages - 1;
+    // learned sensor: the network's viscosity of the new state serves its time step (and the
+    // next step's stages).  The last stage reduces the signal speeds and the fallback cells'
+    // viscosities; the network's forward pass on the new state reduces the learned cells'.
+    const bool learned_next = want_next && (c->cfg.flags & DG_LEARNED_SENSOR);
+    c->prof_first = s == 0;
+    // the last stage writes the caller's array: its failure is decided by its right-hand
+    // side, so that on failure the stage kernel leaves u^n in place (no copy to restore)
+    const StagePred pred{buf[g.un], g.coef};
+    int rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], c->wp(c->off.L), dt, reset_fail ? c->fail() : nullptr,
+                              last ? &pred : nullptr, dt_dev);
+    if (rc) return rc;
+    if (use_meanfree(c)) {
+        rc = launch_abar(c);
+        if (rc) return rc;
+    }
+    void *vnext = !last ? vh[(s + 1) & 1] : (want_next ? vh[0] : nullptr);
+    double *part = (last && want_next) ? (double *)c->wp(c->off.part) : nullptr;
+    c->learned_bounds_later = learned_next && last;
+    rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext, last, g.coef, dt, nullptr,
+                            part, g.w ? buf[g.w] : nullptr, g.wcoef, dt_dev);
+    c->learned_bounds_later = false;
+    return rc;
+}
+
+// One Runge-Kutta step.  reuse: start from the projection kept by the previous step of
+// this context (when it is still valid); dt_next: also compute the time step of the new
+// state in the last stage (its projection is then kept in vh0).  horizon: when the next
+// step is expected to go on without a driving update (1.25 dt < horizon), the first stage of
+// the next step is queued right behind this step's last kernel, reading the new time step
+// from device memory, so that the GPU does not wait for the host; it is kept (spec_valid)
+// when this step succeeds with *dt_next < horizon, and a following step of the same array
+// with that time step and a valid kept projection continues from it.  Calls that change what
+// that stage computes drop it.
+template <typename T, int K>
+static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, double *dt_next, double horizon)
+{
+    const Scheme &S = scheme_of(c);
     const bool cached = reuse && c->vh_cache_u == u && c->vh_cache_gen == c->gen;
+    const bool resume = cached && c->spec_valid && c->spec_u == u && c->spec_dt == dt;
+    const bool ahead = dt_next && 1.25 * dt < horizon;
+    c->spec_valid = false;
     c->gen++;
     c->vh_cache_u = nullptr;
     int rc = DG_OK;
     if (!cached) {
-        rc = launch_project<T, K>(c, u, vh[0], nullptr, c->fail());
+        rc = launch_project<T, K>(c, u, c->wp(c->off.vh0), nullptr, c->fail());
         if (rc) return rc;
     }
-    // learned sensor: the network's viscosity of the new state serves its time step (and the
-    // next step's stages).  The last stage reduces the signal speeds and the fallback cells'
-    // viscosities; the network's forward pass on the new state reduces the learned cells'.
-    const bool learned_next = dt_next && (c->cfg.flags & DG_LEARNED_SENSOR);
+    for (int s = resume ? 1 : 0; s < S.stages; ++s) {
+        rc = launch_step_stage<T, K>(c, u, s, dt, s == 0 && cached, dt_next != nullptr);
+        if (rc) return rc;
+    }
     int st_flag = 0;
     double dt_pub = 0.0;
-    for (int s = 0; s < S.stages; ++s) {
-        const StageSpec &g = S.s[s];
-        const bool last = s == S.stages - 1;
-        c->prof_first = s == 0;
-        // the last stage writes the caller's array: its failure is decided by its right-hand
-        // side, so that on failure the stage kernel leaves u^n in place (no copy to restore)
-        const StagePred pred{buf[g.un], g.coef};
-        rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], c->wp(c->off.L), dt, (s == 0 && cached) ? c->fail() : nullptr,
-                              last ? &pred : nullptr);
-        if (rc) return rc;
-        if (use_meanfree(c)) {
-            rc = launch_abar(c);
-            if (rc) return rc;
-        }
-        void *vnext = !last ? vh[(s + 1) & 1] : (dt_next ? vh[0] : nullptr);
-        double *part = (last && dt_next) ? (double *)c->wp(c->off.part) : nullptr;
-        c->learned_bounds_later = learned_next && last;
-        rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext, last, g.coef, dt,
-                                nullptr, part,
-                                g.w ? buf[g.w] : nullptr, g.wcoef);
-        c->learned_bounds_later = false;
-        if (rc) return rc;
-    }
     if (dt_next) {
         const double *vmax = nullptr;
         int nvmax = 0;
-        if (learned_next) {
+        if (c->cfg.flags & DG_LEARNED_SENSOR) {
             // the last stage left the projection of u^(n+1) in vh0 (unless the step failed)
-            if ((rc = sensor_infer_impl(c, u, &nvmax, vh[0]))) return rc;
+            if ((rc = sensor_infer_impl(c, u, &nvmax, c->wp(c->off.vh0)))) return rc;
             if (proj_args(c).visc) vmax = (const double *)c->wp(c->off.mlp);
         }
         const long long seq = ++c->pub_seq;
         rc = launch_dt_final<T, K>(c, c->scal() + 8, seq, vmax, nvmax);
         if (rc) return rc;
+        if (ahead) {
+            // from u^(n+1) with the time step k_final has just stored; written only into
+            // workspace buffers, and discarded if this step fails
+            rc = launch_step_stage<T, K>(c, u, 0, 0.0, true, true, c->scal() + 8);
+            if (rc) return rc;
+        }
         rc = wait_published(c, seq, &dt_pub, &st_flag);
         if (rc) return rc;
     } else {
@@ -743,6 +774,11 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
         *dt_next = dt_pub;
         c->vh_cache_u = u;
         c->vh_cache_gen = c->gen;
+        if (ahead && dt_pub < horizon) {
+            c->spec_valid = true;
+            c->spec_u = u;
+            c->spec_dt = dt_pub;
+        }
     }
     return DG_OK;
 }
@@ -779,7 +815,7 @@ int dg_rk_step(dg_ctx *c, void *u, double dt, int *status_host)
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
     if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
     if ((rc = learned_ready(c))) return rc;
-    return DISPATCH(c, do_step, c, u, dt, status_host, false, (double *)nullptr);
+    return DISPATCH(c, do_step, c, u, dt, status_host, false, (double *)nullptr, -1.0);
 }
 
 int dg_rk_step_next(dg_ctx *c, void *u, double dt, int reuse, int *status_host, double *dt_next_host)
@@ -790,7 +826,20 @@ int dg_rk_step_next(dg_ctx *c, void *u, double dt, int reuse, int *status_host, 
     if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
     if (!dt_next_host) return dg_fail(c, DG_EINVAL, "dt_next_host is null");
     if ((rc = learned_ready(c))) return rc;
-    return DISPATCH(c, do_step, c, u, dt, status_host, reuse != 0, dt_next_host);
+    return DISPATCH(c, do_step, c, u, dt, status_host, reuse != 0, dt_next_host, -1.0);
+}
+
+int dg_rk_step_next_ahead(dg_ctx *c, void *u, double dt, int reuse, double horizon, int *status_host,
+                          double *dt_next_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
+    if (!(dt > 0.0) || !std::isfinite(dt)) return dg_fail(c, DG_EINVAL, "dt must be positive and finite");
+    if (!dt_next_host) return dg_fail(c, DG_EINVAL, "dt_next_host is null");
+    if (std::isnan(horizon)) return dg_fail(c, DG_EINVAL, "horizon is NaN");
+    if ((rc = learned_ready(c))) return rc;
+    return DISPATCH(c, do_step, c, u, dt, status_host, reuse != 0, dt_next_host, horizon);
 }
 
 template <typename T, int K>

@@ -64,6 +64,11 @@ struct dg_ctx {
     unsigned long gen = 0;
     const void *vh_cache_u = nullptr;
     unsigned long vh_cache_gen = 0;
+    // the first stage of the next step launched ahead by dg_rk_step_next_ahead: for array
+    // spec_u with time step spec_dt, valid while nothing it depends on has changed
+    bool spec_valid = false;
+    const void *spec_u = nullptr;
+    double spec_dt = 0.0;
 
     // cached hipFFT plan of the velocity spectrum (a hipfftHandle) and its grid X, Y, Z
     void *fft_plan = nullptr;

@@ -205,6 +205,7 @@ struct RhsArgs {
     Mesh g;
     int flags;
     double h, cs, alpha, beta, dt;
+    const double *dt_dev;   // the time step in device memory (a stage launched ahead), or NULL: dt
 };
 
 // time-step bound inputs shared by the projection and stage kernels
@@ -236,6 +237,7 @@ struct StageArgs {
     int flags;
     double ca, cb, cc, dt, rho_floor, rho_floor_rel;
     double wa, wb, wc;
+    const double *dt_dev;   // the time step in device memory (a stage launched ahead), or NULL: dt
 };
 
 // ------------------------------------------------------------------ helpers
@@ -252,9 +254,9 @@ __device__ __forceinline__ T stage_value(T ca, T cb, T cdt, T un, T ui, T rhs, b
 // Positivity failure of the last stage decided from its density mean (Sec. 3.1: a cell whose
 // mean is at or below the floor cannot be limited), before the stage writes the state.
 template <typename T>
-__device__ __forceinline__ void predict_failure(const RhsArgs &a, int c, T ui0, T rhs0)
+__device__ __forceinline__ void predict_failure(const RhsArgs &a, double dt, int c, T ui0, T rhs0)
 {
-    const T ca = (T)a.pred_ca, cb = (T)a.pred_cb, cdt = (T)(a.pred_cc * a.dt);
+    const T ca = (T)a.pred_ca, cb = (T)a.pred_cb, cdt = (T)(a.pred_cc * dt);
     const bool use_un = a.pred_ca != 0.0;
     const T un0 = use_un ? ((const T *)a.pred_un)[c] : T(0);
     const double mean = (double)stage_value<T>(ca, cb, cdt, un0, ui0, rhs0, use_un);
@@ -546,7 +548,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const T cs = (T)a.cs, cs2 = (T)(a.cs * a.cs);
     const T hp = (T)(a.h / (K + 1));
     // dt <= 0: no Pi_max cap (a huge finite factor keeps 0 * cap = 0)
-    const T inv_dt = a.dt > 0.0 ? (T)(1.0 / a.dt) : (sizeof(T) == 4 ? T(1e30f) : T(1e300));
+    const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+    const T inv_dt = dt > 0.0 ? (T)(1.0 / dt) : (sizeof(T) == 4 ? T(1e30f) : T(1e300));
     const T alpha = (T)a.alpha, beta = (T)a.beta;
     const T two_h = (T)(2.0 / a.h);
 
@@ -704,7 +707,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
         for (int v = 0; v < 4; ++v)
 #pragma unroll
             for (int l = 0; l < NB; ++l) O.put(v, l, bo, L[v][l] * inv4h);
-        if (a.pred_fail) predict_failure<T>(a, c, mass0, L[0][0] * inv4h);
+        if (a.pred_fail) predict_failure<T>(a, dt, c, mass0, L[0][0] * inv4h);
     }
     if (force && a.part) {
         double acc[4] = {active ? 0.125 * (double)fs0 : 0.0, active ? 0.125 * (double)fs1 : 0.0,
@@ -884,7 +887,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const bool use_hllc = a.flags & F_HLLC;
     const double cs = a.cs, cs2 = a.cs * a.cs;
     const double hp = a.h / (K + 1);
-    const double inv_dt = a.dt > 0.0 ? 1.0 / a.dt : 1e300;
+    const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+    const double inv_dt = dt > 0.0 ? 1.0 / dt : 1e300;
     const double alpha = a.alpha, beta = a.beta;
     const double two_h = 2.0 / a.h;
 
@@ -1034,7 +1038,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int l = 0; l < NB; ++l) ob[((size_t)(2 * h + i) * NB + l) * ncs + c] = L[i][l] * inv4h;
-        if (a.pred_fail && h == 0) predict_failure<double>(a, c, mass0, L[0][0] * inv4h);
+        if (a.pred_fail && h == 0) predict_failure<double>(a, dt, c, mass0, L[0][0] * inv4h);
     }
     if (force && a.part) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1186,14 +1190,15 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
     if (a.L) {
         const Field<T, 4> LF(a.L, NB, nc);
         const Field<T, 4> UN(a.un, NB, nc);
-        const T ca = (T)a.ca, cb = (T)a.cb, cdt = (T)(a.cc * a.dt);
+        const double dt = a.dt_dev ? *a.dt_dev : a.dt;
+        const T ca = (T)a.ca, cb = (T)a.cb, cdt = (T)(a.cc * dt);
         T ab[3] = {T(0), T(0), T(0)};
         if (a.abar) { ab[0] = (T)a.abar[0]; ab[1] = (T)a.abar[1]; ab[2] = (T)a.abar[2]; }
         const bool use_un = a.ca != 0.0;
         const bool side = a.w_out != nullptr;
         const Field<T, 4> WS(side ? a.w_src : a.ui, NB, nc);
         const Field<T, 4> WO(side ? a.w_out : a.ui, NB, nc);
-        const T wa = (T)a.wa, wb = (T)a.wb, wcdt = (T)(a.wc * a.dt);
+        const T wa = (T)a.wa, wb = (T)a.wb, wcdt = (T)(a.wc * dt);
         // momentum first: the removed mean acceleration multiplies the input density
 #pragma unroll
         for (int v = 3; v >= 0; --v)

@@ -557,6 +557,7 @@ int dg_mlp_adam(dg_ctx *c, float *P, const float *G, float *m, float *v, int ste
 int dg_sensor_set_params(dg_ctx *c, const float *P)
 {
     if (!c) return DG_EINVAL;
+    c->spec_valid = false;          // the viscosity or flags a launched next stage used change
     if (!P) return dg_fail(c, DG_EINVAL, "params is null");
     HIPCHK(c, hipMemcpyAsync(c->mlp_bf16, P, sizeof(float) * NPARAM, hipMemcpyDeviceToDevice, c->stream));
     c->have_params = true;
@@ -649,6 +650,7 @@ int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax, const void *vhat)
 int dg_sensor_infer(dg_ctx *c, const void *u)
 {
     if (!c) return DG_EINVAL;
+    c->spec_valid = false;          // the viscosity or flags a launched next stage used change
     if (!u) return dg_fail(c, DG_EINVAL, "u is null");
     return sensor_infer_impl(c, u);
 }
@@ -656,6 +658,7 @@ int dg_sensor_infer(dg_ctx *c, const void *u)
 int dg_sensor_judge(dg_ctx *c, const void *u, double tau, long *nfallback)
 {
     if (!c) return DG_EINVAL;
+    c->spec_valid = false;          // the viscosity or flags a launched next stage used change
     if (!u || !(tau >= 0.0)) return dg_fail(c, DG_EINVAL, "bad judge arguments");
     int rc = sensor_infer_impl(c, u);
     if (rc) return rc;
@@ -682,6 +685,7 @@ int dg_sensor_judge(dg_ctx *c, const void *u, double tau, long *nfallback)
 int dg_sensor_set_nu(dg_ctx *c, const void *nu, const int32_t *fb)
 {
     if (!c) return DG_EINVAL;
+    c->spec_valid = false;          // the viscosity or flags a launched next stage used change
     int rc = need_k2(c);
     if (rc) return rc;
     if (nu) {

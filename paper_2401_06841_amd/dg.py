@@ -53,6 +53,7 @@ _SIGS = {
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _ip]),
     "dg_dt_max": (ctypes.c_int, [_vp, _vp, _dp, ctypes.c_int]),
     "dg_rk_step_next": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]),
+    "dg_rk_step_next_ahead": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]),
     "dg_project_primitive": (ctypes.c_int, [_vp, _vp, _vp]),
     "dg_limit": (ctypes.c_int, [_vp, _vp, _lp]),
     "dg_conserved_sums": (ctypes.c_int, [_vp, _vp, _dp]),
@@ -225,6 +226,18 @@ def dg_rk_step_next(ctx: Context, u, dt: float, reuse: bool):
     dn = ctypes.c_double(0.0)
     rc = ctx._chk(_lib.dg_rk_step_next(ctx.h, _ptr(u), float(dt), 1 if reuse else 0, ctypes.byref(st),
                                        ctypes.byref(dn)), ok=(DG_OK, DG_RETRY))
+    return rc, (dn.value if rc == DG_OK else None)
+
+
+def dg_rk_step_next_ahead(ctx: Context, u, dt: float, reuse: bool, horizon: float):
+    """dg_rk_step_next that, when the returned time step is below horizon, also launches the
+    next step's first stage ahead (continued by the next call with that time step);
+    returns (DG_OK, dt_next) or (DG_RETRY, None)."""
+    ctx._check_state(u)
+    st = ctypes.c_int(0)
+    dn = ctypes.c_double(0.0)
+    rc = ctx._chk(_lib.dg_rk_step_next_ahead(ctx.h, _ptr(u), float(dt), 1 if reuse else 0, float(horizon),
+                                             ctypes.byref(st), ctypes.byref(dn)), ok=(DG_OK, DG_RETRY))
     return rc, (dn.value if rc == DG_OK else None)
 
 

@@ -3,18 +3,22 @@
 One driver step: CFL time step (FP64 reduction on the GPU: the value dg_rk_step_next
 returned with the previous step, so that a step costs one read-back, else dg_dt_max),
 Ornstein-Uhlenbeck driving updates on the host whenever the simulation time crosses the
-next update time (every t_c/100, Sec. 4.2), then dg_rk_step_next; when the step reports a
-positivity failure the state has been restored and the step is retried with half the time
-step (Sec. 3.1).  With the learned sensor the network's viscosity of u^n enters the viscous
+next update time (every t_c/100, Sec. 4.2), then the fused step; when the step reports a
+positivity failure the state is still u^n and the step is retried with half the time step
+(Sec. 3.1).  With the learned sensor the network's viscosity of u^n enters the viscous
 bound and serves the stages (the previous fused step ran the network on this state), and
 every judge_every steps the judge recomputes the plain labels and the fallback flags, after
-which the time step is taken again.  Checkpoints are the raw [var][mode][cell] array plus a
-JSON record of the run parameters, the simulation time and the driving state.
+which the time step is taken again.  With speculate (the default) each step also has the
+library launch the next step's first stage ahead (dg_rk_step_next_ahead) unless a driving
+update or a judgement comes first, so the GPU does not wait for the host between steps; the
+results are the same.  Checkpoints are the raw [var][mode][cell] array plus a JSON record of
+the run parameters, the simulation time and the driving state.
 """
 from __future__ import annotations
 
 import dataclasses
 import json
+import math
 import os
 
 import numpy as np
@@ -44,7 +48,7 @@ def gaussian_draws(seed: int, update: int, n: int):
 
 class Simulation:
     def __init__(self, cfg: dg.Config, u=None, driving: Driving | None = None, retry_limit: int = 30,
-                 sensor_params=None, judge_every: int = 10, tau: float = 0.5):
+                 sensor_params=None, judge_every: int = 10, tau: float = 0.5, speculate: bool = True):
         import torch
         self.cfg = cfg
         self.ctx = dg.dg_init(cfg)
@@ -56,6 +60,7 @@ class Simulation:
         self.nstep = 0
         self.retries = 0
         self.retry_limit = retry_limit
+        self.speculate = speculate
         self.driving = driving
         self.n_drive = 0
         self.next_drive = 0.0
@@ -108,7 +113,12 @@ class Simulation:
         tries = 0
         self._dt_next = None
         while True:
-            rc, dt_next = dg.dg_rk_step_next(self.ctx, self.u, dt, reuse)
+            # launch the next step's first stage ahead unless the next step starts with a
+            # driving update (its time step reaches the next update time) or a judgement
+            horizon = 0.0
+            if self.speculate and not (self.learned and (self.nstep + 1) % self.judge_every == 0):
+                horizon = math.inf if self.driving is None else self.next_drive - (self.t + dt)
+            rc, dt_next = dg.dg_rk_step_next_ahead(self.ctx, self.u, dt, reuse, horizon)
             if rc == dg.DG_OK:
                 break
             self.retries += 1

@@ -218,6 +218,66 @@ def test_learned_driver_run_with_judge():
     assert torch.all(torch.isfinite(sim.u))
 
 
+# ------------------------------------------------ next step's first stage launched ahead
+
+@pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
+def test_launched_ahead_runs_match_plain_runs_bitwise(precision):
+    """Driven runs with and without the first stage launched ahead: same states, times and
+    driving updates, bit for bit (12^3 at Mach 3 updates the driving every few steps, so many
+    launched stages are continued and some are not launched)."""
+    n = 12
+    cfg = dg.Config(n, n, n, degree=2, precision=precision, flags=FLAGS)
+    drv = Driving(3.0, 2.5, seed=7)
+    a = Simulation(cfg, driving=drv, speculate=True)
+    b = Simulation(cfg, driving=drv, speculate=False)
+    for _ in range(40):
+        assert a.step() == b.step()
+    assert torch.equal(a.u, b.u) and a.t == b.t and a.n_drive == b.n_drive
+
+
+def test_launched_ahead_learned_run_with_judge_matches_plain_run():
+    n = 8
+    cfg = dg.Config(n, n, n, degree=2, precision=dg.DG_FP32, flags=FLAGS | dg.DG_LEARNED_SENSOR)
+    runs = [Simulation(cfg, driving=Driving(3.0, 2.5, seed=1), sensor_params=_flat_params(4), judge_every=3,
+                       speculate=s) for s in (True, False)]
+    for _ in range(12):
+        assert runs[0].step() == runs[1].step()
+    assert torch.equal(runs[0].u, runs[1].u)
+    assert runs[0].fallback_counts == runs[1].fallback_counts
+
+
+def test_launched_stage_is_dropped_when_its_inputs_change():
+    """A stage launched ahead is continued only by the same array with the returned time
+    step; a new driving table in between, another time step or a torch write all discard it
+    and the step is computed afresh (compared with a context that never launches ahead)."""
+    n, k = 10, 2
+    u0 = synthetic.turbulent_like(n, n, n, k, mach=3.0, seed=14, high_amp=0.02, kmax_frac=0.125)
+    t1, t2 = synthetic.forcing_table(1, amp=3.0), synthetic.forcing_table(2, amp=3.0)
+    ctx_a, ctx_b = make(n, n, n, k, FLAGS), make(n, n, n, k, FLAGS)
+    for c in (ctx_a, ctx_b):
+        dg.dg_set_forcing(c, t1)
+    ua, ub = dev(u0, ctx_a), dev(u0, ctx_b)
+    dta = dg.dg_dt_max(ctx_a, ua)
+    dtb = dta
+    reuse = False
+    for i in range(8):
+        rc, dta_n = dg.dg_rk_step_next_ahead(ctx_a, ua, dta, reuse, float("inf"))
+        rcb, dtb_n = dg.dg_rk_step_next(ctx_b, ub, dtb, reuse)
+        assert rc == rcb == dg.DG_OK and dta_n == dtb_n
+        dta, dtb = dta_n, dtb_n
+        reuse = True
+        if i == 2:                                   # new table: the launched stage is stale
+            for c in (ctx_a, ctx_b):
+                dg.dg_set_forcing(c, t2)
+        if i == 4:                                   # another time step than the returned one
+            dta = dtb = 0.5 * dta
+        if i == 6:                                   # a write the library does not see: reuse = 0
+            ua.mul_(1.0)
+            ub.mul_(1.0)
+            reuse = False
+    assert torch.equal(ua, ub)
+
+
 # ------------------------------------------------------------- instrumentation levels
 
 def test_profile_levels_count_the_bracketed_launches():
@@ -226,8 +286,8 @@ def test_profile_levels_count_the_bracketed_launches():
     n = 8
     cfg = dg.Config(n, n, n, degree=2, precision=dg.DG_FP64, flags=FLAGS)
     drv = Driving(3.0, 2.5, seed=1)
-    plain = Simulation(cfg, driving=drv)
-    timed = Simulation(cfg, driving=drv)
+    plain = Simulation(cfg, driving=drv, speculate=False)
+    timed = Simulation(cfg, driving=drv, speculate=False)
     for level, steps in ((1, 5), (2, 4)):
         dg.dg_profile(timed.ctx, level)
         r0 = timed.retries
