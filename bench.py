@@ -44,7 +44,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DG DOF-updates/sec per RK stage (3D, order p) + % HBM/MFMA roofline vs FP64"
 PEAK_FP64_TFLOPS = 78.6      # MI355X vector = matrix FP64 peak
 PEAK_FP32_TFLOPS = 157.3     # MI355X published FP32 vector peak (packed issue)
-FP32_UNPACKED_TFLOPS = 78.6  # issue limit without packed FP32, which this build does not emit
+FP32_UNPACKED_TFLOPS = 78.6  # issue limit without packed FP32, which the library's kernels do not emit
 PEAK_HBM_TBPS = 8.0          # MI355X HBM3E
 
 WORKLOADS = {

@@ -307,8 +307,8 @@ static void flux(int d, double rho, const double m[3], double p, double F[NV])
 /* Rusanov (local Lax-Friedrichs) flux across a face with normal +e_d between the
  * low-side state L and the high-side state R: half the sum of the two physical
  * fluxes minus half the largest signal speed times the jump.  Speed = largest
- * |v_d| of the two sides plus cs.  (The paper uses HLLC; the Rusanov flux is the
- * interface solver fixed for this build, Sec. 2.2 numerical flux.) */
+ * |v_d| of the two sides plus cs.  (The paper uses HLLC, available below as the
+ * alternative; Rusanov is the default interface solver, Sec. 2.2 numerical flux.) */
 void orc_rusanov(int d, double cs, const double uL[NV], const double uR[NV], double Fh[NV])
 {
     double FL[NV], FR[NV];
