@@ -4,6 +4,7 @@ step that returns the next time step (one read-back per step).
 A driven run interrupted by a checkpoint and resumed in a fresh context must continue
 bitwise identically to the uninterrupted run (same OU state, same update counters, same
 kernels in the same order)."""
+import ctypes
 import os
 
 import numpy as np
@@ -276,6 +277,21 @@ def test_launched_stage_is_dropped_when_its_inputs_change():
             ub.mul_(1.0)
             reuse = False
     assert torch.equal(ua, ub)
+
+
+def test_launched_ahead_argument_errors():
+    n, k = 6, 2
+    ctx = make(n, n, n, k, FLAGS)
+    u = dev(synthetic.turbulent_like(n, n, n, k, mach=2.0, seed=3), ctx)
+    with pytest.raises(dg.DGError):
+        dg.dg_rk_step_next_ahead(ctx, u, 1e-4, False, float("nan"))
+    with pytest.raises(dg.DGError):
+        dg.dg_rk_step_next_ahead(ctx, u, 0.0, False, 1.0)
+    st = ctypes.c_int(0)
+    assert dg._lib.dg_rk_step_next_ahead(ctx.h, ctypes.c_void_p(u.data_ptr()), 1e-4, 0, 1.0, ctypes.byref(st),
+                                         None) == dg.DG_EINVAL
+    rc, dt_next = dg.dg_rk_step_next_ahead(ctx, u, 1e-5, False, 0.0)     # horizon 0: plain step
+    assert rc == dg.DG_OK and dt_next > 0
 
 
 # ------------------------------------------------------------- instrumentation levels
