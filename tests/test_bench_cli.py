@@ -14,3 +14,23 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_c1_cpu_baseline_runs_the_oracle_on_the_sound_wave():
+    """The 16^3 degree-1 workload's CPU leg: the oracle on the modal sound wave, limiter
+    only, enough steps for a stable figure; the state stays a small-amplitude wave."""
+    import types
+
+    import numpy as np
+
+    sys.path.insert(0, ROOT)
+    import bench
+    import synthetic
+    args = types.SimpleNamespace(workload="c1", seed=1, cpu_steps=10)
+    rec = bench.run_cpu_baseline(args)
+    assert rec["kind"] == "oracle" and rec["value"] > 0 and "200 SSP-RK3 steps" in rec["sample"]
+    u = synthetic.c1_modal_state(1)
+    assert u.shape == (4, 4, 16 ** 3)
+    axis = synthetic.c1_axis(1)
+    assert np.allclose(u[1 + axis, 0], u[0, 0] - 1.0)             # m = cs (rho - 1) for cs = 1
+    assert np.abs(u[0, 0] - 1.0).max() <= 1e-3
