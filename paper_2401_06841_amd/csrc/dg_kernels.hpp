@@ -350,6 +350,37 @@ __device__ __forceinline__ void project_component(const T (&W)[4][Shape<K>::NB],
     }
 }
 
+// project_component for d = 0 that also takes the largest signal speed sum_d |v_d| + cs
+// over the points from the same point values (the time-step bound)
+template <typename T, int K>
+__device__ __forceinline__ void project_first_with_speed(const T (&W)[4][Shape<K>::NB], ctab<T> *tab,
+                                                         T (&V)[Shape<K>::NB], double cs, double &sm)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+#pragma unroll
+    for (int l = 0; l < S::NB; ++l) V[l] = T(0);
+#pragma unroll 1
+    for (int q = 0; q < S::NQ; ++q) {
+        ctab<T> *ph = tab + TL::VPHI + q * S::NB;
+        T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) {
+            const T p = ph[l];
+            rho += W[0][l] * p;
+            m0 += W[1][l] * p;
+            m1 += W[2][l] * p;
+            m2 += W[3][l] * p;
+        }
+        const T ir = rcp(rho);
+        const double sp = (double)fabs(m0 * ir) + (double)fabs(m1 * ir) + (double)fabs(m2 * ir) + 3.0 * cs;
+        sm = fmax(sm, sp);
+        const T a = T(0.125) * tab[TL::VW + q] * (m0 * ir);
+#pragma unroll
+        for (int l = 0; l < S::NB; ++l) V[l] += a * ph[l];
+    }
+}
+
 // FP64 kernels project one velocity component at a time (fewer live registers, four
 // waves per SIMD); FP32 ones have registers to spare and project all three at once
 template <typename T>
@@ -1070,7 +1101,9 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
     constexpr Modes<K> M = make_modes<K>();
     constexpr int NB = S::NB;
     double sm = 0.0;
-    if (part) {
+    // the split projection's first pass takes the signal speed along
+    const bool speed_in_projection = split_projection<T>() && (vh || (part && pa.visc));
+    if (part && !speed_in_projection) {
         // largest signal speed sum_d |v_d| + cs over the interior points
 #pragma unroll 1
         for (int q = 0; q < S::NQ; ++q) {
@@ -1111,7 +1144,10 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 T V[NB];
-                project_component<T, K>(W, tab, d, V);
+                if (d == 0 && part)
+                    project_first_with_speed<T, K>(W, tab, V, pa.cs, sm);
+                else
+                    project_component<T, K>(W, tab, d, V);
                 if (vh && active)
 #pragma unroll
                     for (int l = 0; l < NB; ++l) VO.put(d, l, bo, V[l]);
