@@ -284,7 +284,7 @@ __device__ __forceinline__ void store_field(const Field<T, NV> &f, unsigned bo, 
 // projected velocity of one cell from its weights (Sec. 3.2): vh_{d,l} = 1/8 sum_q w_q phi_l v_d
 template <typename T, int K>
 __device__ __forceinline__ void project_cell(const T (&W)[4][Shape<K>::NB], ctab<T> *tab,
-                                             T (&V)[3][Shape<K>::NB], double *smax, T cs)
+                                             T (&V)[3][Shape<K>::NB], double *smax, double cs)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -307,7 +307,7 @@ __device__ __forceinline__ void project_cell(const T (&W)[4][Shape<K>::NB], ctab
         const T ir = rcp(rho);
         const T v0 = m0 * ir, v1 = m1 * ir, v2 = m2 * ir;
         if (smax) {
-            const double s = (double)fabs(v0) + (double)fabs(v1) + (double)fabs(v2) + 3.0 * (double)cs;
+            const double s = (double)fabs(v0) + (double)fabs(v1) + (double)fabs(v2) + 3.0 * cs;
             sm = fmax(sm, s);
         }
         const T wq = T(0.125) * tab[TL::VW + q];
@@ -1101,8 +1101,8 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
     constexpr Modes<K> M = make_modes<K>();
     constexpr int NB = S::NB;
     double sm = 0.0;
-    // the split projection's first pass takes the signal speed along
-    const bool speed_in_projection = split_projection<T>() && (vh || (part && pa.visc));
+    // the projection takes the signal speed along from its own point values
+    const bool speed_in_projection = vh || (part && pa.visc);
     if (part && !speed_in_projection) {
         // largest signal speed sum_d |v_d| + cs over the interior points
 #pragma unroll 1
@@ -1155,7 +1155,10 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
             }
         } else {
             T V[3][NB];
-            project_cell<T, K>(W, tab, V, nullptr, T(0));
+            if (part)   // two calls, so that sm stays in registers
+                project_cell<T, K>(W, tab, V, &sm, pa.cs);
+            else
+                project_cell<T, K>(W, tab, V, nullptr, pa.cs);
             if (vh && active) store_field<T, K, 3>(VO, bo, V);
             if (visc)
 #pragma unroll

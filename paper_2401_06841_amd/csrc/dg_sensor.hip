@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(BLOCK) k_features(const void *u_, float *__res
         load_field<T, K, 3>(Field<T, 3>(vhat, NB, nc), bo, V);
     } else {
         load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
-        project_cell<T, K>(W, as_tab<T>(tab_), V, nullptr, T(0));
+        project_cell<T, K>(W, as_tab<T>(tab_), V, nullptr, 0.0);
     }
     if (!active) return;
     const double r0 = (double)W[0][0];
@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(BLOCK) k_labels(const void *u_, OUT *__restric
     T W[4][NB];
     load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
     T V[3][NB];
-    project_cell<T, K>(W, tab, V, nullptr, T(0));
+    project_cell<T, K>(W, tab, V, nullptr, 0.0);
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll 1
     for (int q = 0; q < S::NQ; ++q) {
