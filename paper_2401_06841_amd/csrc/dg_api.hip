@@ -171,6 +171,9 @@ static void layout(dg_ctx *c, size_t *total)
     // per-block partials: the FP64 degree-3 right-hand side runs two lanes per cell (twice
     // the blocks)
     c->off.part = o; o += align_up((size_t)c->nblk * 2 * 4 * 8);
+    // the step's last stage: per-block time-step maxima (apart from the right-hand side's
+    // partials, which the same stage reads)
+    c->off.spart = o; o += align_up((size_t)c->nblk * 2 * 8);
     c->off.scal = o; o += align_up(64 * 8);
     c->off.iflags = o; o += align_up(64 * 4);
     *total = o;
@@ -521,6 +524,9 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     return prof_mark(c, 0, 1);
 }
 
+// the largest count of right-hand-side blocks whose partials a stage block reduces itself
+constexpr int ABAR_IN_STAGE_BLOCKS = 1024;
+
 static bool use_meanfree(const dg_ctx *c)
 {
     return (c->cfg.flags & DG_FORCING) && (c->cfg.flags & DG_FORCE_MEANFREE) && c->nmodes > 0;
@@ -548,7 +554,12 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.vh_out = vh_out;
     a.skip_flag = skip_if_failed ? c->fail() : nullptr;
     a.tab = c->tab;
-    a.abar = (L && use_meanfree(c)) ? c->abar() : nullptr;
+    // abar_in_stage: every block reduces the right-hand side's partials to the removed mean
+    // acceleration itself (no separate reduction kernel)
+    const bool mf = L && use_meanfree(c);
+    a.abar = mf && !c->abar_in_stage ? c->abar() : nullptr;
+    a.abar_part = mf && c->abar_in_stage ? (const double *)c->wp(c->off.part) : nullptr;
+    a.abar_np = c->rhs_nblk;
     a.fail = c->fail();
     a.nlim = nlim;
     a.part = part;
@@ -594,11 +605,12 @@ static int do_rhs(dg_ctx *c, const void *u, void *dudt, double dt)
 // seq > 0: also publish the time step and the failure flag to the host (dg_ctx::PUB);
 // vmax: np2 further partial maxima of the viscosity (the learned cells'), or NULL
 template <typename T, int K>
-static int launch_dt_final(dg_ctx *c, double *dst, long long seq = 0, const double *vmax = nullptr, int np2 = 0)
+static int launch_dt_final(dg_ctx *c, const double *src, double *dst, long long seq = 0, const double *vmax = nullptr,
+                           int np2 = 0)
 {
     const double hp = c->cfg.h / (K + 1);
     volatile long long *pub = seq > 0 ? (volatile long long *)(c->pinned + dg_ctx::PUB) : nullptr;
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->nblk, 2,
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, src, c->nblk, 2,
                        c->cfg.cfl * c->cfg.h / (K + 1), c->cfg.cfl_visc > 0.0 ? c->cfg.cfl_visc * hp * hp : 0.0,
                        dst, (const int *)c->fail(), pub, seq, vmax, np2);
     LAUNCHCHK(c);
@@ -699,16 +711,22 @@ static int launch_step_stage(dg_ctx *c, void *u, int s, double dt, bool reset_fa
     int rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], c->wp(c->off.L), dt, reset_fail ? c->fail() : nullptr,
                               last ? &pred : nullptr, dt_dev);
     if (rc) return rc;
-    if (use_meanfree(c)) {
+    // mean-free driving: with few right-hand-side blocks every stage block reduces their
+    // partials itself (at most 32 KB of reads per block, no reduction kernel); with more, one
+    // k_final reduces them once, as the repeated reads would grow with the square of the mesh
+    const bool in_stage = c->rhs_nblk <= ABAR_IN_STAGE_BLOCKS;
+    if (use_meanfree(c) && !in_stage) {
         rc = launch_abar(c);
         if (rc) return rc;
     }
     void *vnext = !last ? vh[(s + 1) & 1] : (want_next ? vh[0] : nullptr);
-    double *part = (last && want_next) ? (double *)c->wp(c->off.part) : nullptr;
+    double *part = (last && want_next) ? (double *)c->wp(c->off.spart) : nullptr;
     c->learned_bounds_later = learned_next && last;
+    c->abar_in_stage = in_stage;
     rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext, last, g.coef, dt, nullptr,
                             part, g.w ? buf[g.w] : nullptr, g.wcoef, dt_dev);
     c->learned_bounds_later = false;
+    c->abar_in_stage = false;
     return rc;
 }
 
@@ -751,7 +769,7 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
             if (proj_args(c).visc) vmax = (const double *)c->wp(c->off.mlp);
         }
         const long long seq = ++c->pub_seq;
-        rc = launch_dt_final<T, K>(c, c->scal() + 8, seq, vmax, nvmax);
+        rc = launch_dt_final<T, K>(c, (const double *)c->wp(c->off.spart), c->scal() + 8, seq, vmax, nvmax);
         if (rc) return rc;
         if (ahead) {
             // from u^(n+1) with the time step k_final has just stored; written only into
@@ -849,7 +867,7 @@ static int do_dt(dg_ctx *c, const void *u, double *dt_out, int on_host)
     int rc = launch_project<T, K>(c, u, nullptr, part, nullptr);
     if (rc) return rc;
     double *dst = on_host ? c->scal() + 8 : dt_out;
-    rc = launch_dt_final<T, K>(c, dst);
+    rc = launch_dt_final<T, K>(c, part, dst);
     if (rc) return rc;
     if (on_host) {
         HIPCHK(c, hipMemcpyAsync(c->pinned, dst, sizeof(double), hipMemcpyDeviceToHost, c->stream));

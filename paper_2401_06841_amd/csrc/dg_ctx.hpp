@@ -11,7 +11,7 @@
 constexpr int MLP_PART_ROWS = 1024;
 
 struct dg_offsets {
-    size_t stA, stB, stC, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, scal, iflags;
+    size_t stA, stB, stC, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, spart, scal, iflags;
 };
 
 struct dg_ctx {
@@ -49,6 +49,7 @@ struct dg_ctx {
     bool have_params = false;
     bool have_nu = false;
     bool learned_bounds_later = false;   // see proj_args
+    bool abar_in_stage = false;          // see launch_stage
     // kernel timing (dg_profile)
     static constexpr int NEV = 64;
     int prof = 0;                      // 0 off, 1 first-stage right-hand sides, 2 every launch

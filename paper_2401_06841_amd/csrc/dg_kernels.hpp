@@ -58,6 +58,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
         for (int i = 0; i < NV; ++i) v[i] = ((lds[i] + lds[NV + i]) + (lds[2 * NV + i] + lds[3 * NV + i]));
 }
 
+// totals of per-block partials part[4 i + k], i < np, over the threads of one block of
+// BLOCK threads (thread t adds i = t, t + BLOCK, ... in order, then the block sum); the
+// totals end in thread 0.  Every reduction of such partials uses this one order.
+__device__ __forceinline__ void block_partial_sums4(const double *part, int np, double (&s)[4], double *lds)
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s[k] = 0.0;
+    for (int i = threadIdx.x; i < np; i += BLOCK)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += part[4 * i + k];
+    block_sum<4>(s, lds);
+}
+
 __device__ __forceinline__ double block_max(double v, double *lds)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -227,6 +240,8 @@ struct StageArgs {
     const int *skip_flag;   // the last stage: the failure flag (write nothing when raised), or NULL
     const void *tab;
     const double *abar;     // removed mean acceleration (3), or NULL
+    const double *abar_part; // or, when not NULL: the right-hand side's per-block partials
+    int abar_np;            //   (abar_np blocks of 4), reduced to it in every block
     int *fail;              // positivity failure flag
     long long *nlim;        // count of failing cells (may be NULL)
     double *part;           // with vh_out: per-block time-step maxima of u^(i+1), or NULL
@@ -1213,6 +1228,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
     constexpr Modes<K> M = make_modes<K>();
     constexpr int NB = S::NB;
     __shared__ double lds[4];
+    __shared__ double lds_ab[20];
     const int nc = a.g.nc;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int c0 = blk * BLOCK + threadIdx.x;
@@ -1233,6 +1249,18 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         const T ca = (T)a.ca, cb = (T)a.cb, cdt = (T)(a.cc * dt);
         T ab[3] = {T(0), T(0), T(0)};
         if (a.abar) { ab[0] = (T)a.abar[0]; ab[1] = (T)a.abar[1]; ab[2] = (T)a.abar[2]; }
+        if (a.abar_part) {
+            // the mass-weighted mean acceleration, as k_final computes it
+            double sum[4];
+            block_partial_sums4(a.abar_part, a.abar_np, sum, lds_ab);
+            if (threadIdx.x == 0)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) lds_ab[16 + k] = sum[k] / sum[3];
+            __syncthreads();
+            ab[0] = (T)lds_ab[16];
+            ab[1] = (T)lds_ab[17];
+            ab[2] = (T)lds_ab[18];
+        }
         const bool use_un = a.ca != 0.0;
         const bool side = a.w_out != nullptr;
         const Field<T, 4> WS(side ? a.w_src : a.ui, NB, nc);
@@ -1531,11 +1559,8 @@ static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int 
         }
         return;
     }
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < np; i += BLOCK)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s[k] += part[4 * i + k];
-    block_sum<4>(s, lds);
+    double s[4];
+    block_partial_sums4(part, np, s, lds);
     if (threadIdx.x == 0) {
         if (mode == 0) {
 #pragma unroll
