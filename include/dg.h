@@ -96,6 +96,14 @@ void dg_free(dg_ctx *ctx);
 /* Text of the last error on this context (static storage inside the context). */
 const char *dg_last_error(const dg_ctx *ctx);
 
+/* Wall-clock bound, in seconds, of the host wait inside dg_rk_step_next and
+ * dg_rk_step_next_ahead for the step's published status (default 300).  When the bound is
+ * exceeded the call returns DG_EHIP while the step's kernels may still be running on the
+ * stream: the caller must synchronise the stream before using or discarding the state.
+ * The step, once finished, leaves the state it would have left.  Errors: DG_EINVAL
+ * (seconds not positive; +infinity waits without a bound). */
+int dg_set_wait_limit(dg_ctx *ctx, double seconds);
+
 /* Bytes of device scratch the caller must provide (traces, projected velocity, Runge-Kutta
  * temporaries, driving field at the quadrature points, reduction partials, flags). */
 size_t dg_workspace_bytes(const dg_ctx *ctx);
@@ -189,8 +197,11 @@ int dg_project_primitive(dg_ctx *ctx, const void *u, void *vhat);
  * *nfail_host = number of cells whose mean is at or below the floor. */
 int dg_limit(dg_ctx *ctx, void *u, long *nfail_host);
 
-/* Conserved totals (mass, momentum x/y/z) = h^3 sum_cells W_v,0, FP64 fixed-order
- * reduction; out_host[4] host memory; synchronises. */
+/* Conserved totals (mass, momentum x/y/z) = h^3 sum_cells W_v,0 (Sec. 2.2: the basis is
+ * orthonormal with phi_0 = 1, so the weight W_v,0 is the cell average of variable v and
+ * |K| W_v,0 its content; the weak form conserves these totals), FP64 fixed-order
+ * reduction; u is [4][nb][ncell] device memory; out_host[4] host memory; synchronises.
+ * Errors: DG_EINVAL (null or misaligned pointer), DG_ENOMEM (no workspace). */
 int dg_conserved_sums(dg_ctx *ctx, const void *u, double *out_host);
 
 /* Instrumentation: launches issued by dg_rhs / dg_rk_step / dg_rk_step_next are bracketed

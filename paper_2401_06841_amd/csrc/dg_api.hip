@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -287,6 +288,14 @@ void dg_free(dg_ctx *c)
 }
 
 const char *dg_last_error(const dg_ctx *c) { return c ? c->err : "null context"; }
+
+int dg_set_wait_limit(dg_ctx *c, double seconds)
+{
+    if (!c) return DG_EINVAL;
+    if (!(seconds > 0.0)) return dg_fail(c, DG_EINVAL, "wait limit must be positive (got %g)", seconds);
+    c->wait_limit_s = seconds;
+    return DG_OK;
+}
 
 size_t dg_workspace_bytes(const dg_ctx *c) { return c ? c->ws_need : 0; }
 
@@ -617,27 +626,37 @@ static int launch_dt_final(dg_ctx *c, const double *src, double *dst, long long 
     return DG_OK;
 }
 
-// Wait until the kernel launched by launch_dt_final(c, dst, seq) has published: spin on the
-// sequence number in pinned memory (far lower latency than a copy back and a stream
-// synchronisation), bounded by the stream's own completion.  Should the stream complete
-// without the number showing, the values are copied back the ordinary way.
+// Wait until the kernel launched by launch_dt_final(c, c->scal() + 8, seq) has published:
+// spin on the sequence number in pinned memory (far lower latency than a copy back and a
+// stream synchronisation), bounded by the stream's own completion and by the context's
+// wall-clock limit.  Should the stream complete without the number showing, the values are
+// copied back from the device slots k_final filled (time step and the step's own failure
+// flag: the live flag may already have been cleared by a stage queued behind it).
 static int wait_published(dg_ctx *c, long long seq, double *dt, int *fail_flag)
 {
     volatile long long *pub = (volatile long long *)(c->pinned + dg_ctx::PUB);
+    const auto t0 = std::chrono::steady_clock::now();
     for (unsigned it = 1;; ++it) {
         if (pub[0] == seq) break;
         if ((it & 63) == 0) {
             const hipError_t q = hipStreamQuery(c->stream);
             if (q == hipSuccess) {
                 if (pub[0] == seq) break;
-                HIPCHK(c, hipMemcpy(c->pinned + dg_ctx::PUB + 1, c->scal() + 8, sizeof(double), hipMemcpyDeviceToHost));
-                int f = 0;
-                HIPCHK(c, hipMemcpy(&f, c->fail(), sizeof(int), hipMemcpyDeviceToHost));
-                pub[2] = f;
+                double vals[2];
+                HIPCHK(c, hipMemcpy(vals, c->scal() + 8, sizeof(vals), hipMemcpyDeviceToHost));
+                long long bits;
+                std::memcpy(&bits, &vals[0], sizeof(bits));
+                pub[1] = bits;
+                pub[2] = (long long)vals[1];
                 break;
             }
             if (q != hipErrorNotReady)
                 return dg_fail(c, DG_EHIP, "stream query while waiting for the step failed: %s", hipGetErrorString(q));
+            const double waited = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (waited > c->wait_limit_s)
+                return dg_fail(c, DG_EHIP,
+                               "the step did not complete within %.3g s (the stream is still running: synchronise it "
+                               "before using the state)", c->wait_limit_s);
         }
     }
     std::atomic_thread_fence(std::memory_order_acquire);

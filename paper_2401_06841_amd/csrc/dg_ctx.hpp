@@ -37,6 +37,7 @@ struct dg_ctx {
     // flag} written by the device (k_final), and the last sequence number issued
     static constexpr int PUB = 16;
     long long pub_seq = 0;
+    double wait_limit_s = 300.0;   // wall-clock bound of the host wait for a published step
     char *ws = nullptr;            // caller's workspace
     size_t ws_need = 0;
     dg_offsets off{};

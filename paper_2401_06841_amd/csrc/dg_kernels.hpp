@@ -1528,7 +1528,9 @@ __global__ void __launch_bounds__(BLOCK) k_sums(const void *u_, Mesh g, double *
 // Publication (mode 2, pub != null): the time step and the step's failure flag are also
 // stored into pub (pinned host memory: pub[1] = the bits of dt, pub[2] = *fail), and then
 // pub[0] = seq, each store made visible to the host before the next; the host waits for
-// pub[0] == seq instead of copying the values back and synchronising the stream.
+// pub[0] == seq instead of copying the values back and synchronising the stream.  The flag
+// is also kept in out[1] (device memory), because a stage launched behind this kernel may
+// clear *fail before the host reads it.
 static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int np, int mode, double scale, double scale2,
                                                  double *out, const int *fail, volatile long long *pub,
                                                  long long seq, const double *part2, int np2)
@@ -1550,8 +1552,10 @@ static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int 
             if (scale2 > 0.0 && n > 0.0) dt = fmin(dt, scale2 / n);
             out[0] = dt;
             if (pub) {
+                const int f = *fail;
+                out[1] = (double)f;
                 pub[1] = __double_as_longlong(dt);
-                pub[2] = *fail;
+                pub[2] = f;
                 __threadfence_system();
                 pub[0] = seq;
                 __threadfence_system();

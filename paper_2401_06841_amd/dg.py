@@ -46,6 +46,7 @@ _SIGS = {
     "dg_init": (ctypes.c_int, [ctypes.POINTER(dg_config), ctypes.POINTER(_vp)]),
     "dg_free": (None, [_vp]),
     "dg_last_error": (ctypes.c_char_p, [_vp]),
+    "dg_set_wait_limit": (ctypes.c_int, [_vp, ctypes.c_double]),
     "dg_workspace_bytes": (ctypes.c_size_t, [_vp]),
     "dg_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "dg_set_forcing": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
@@ -197,6 +198,12 @@ def dg_init(cfg: Config, stream=None) -> Context:
 
 def dg_free(ctx: Context):
     ctx.close()
+
+
+def dg_set_wait_limit(ctx: Context, seconds: float):
+    """Wall-clock bound of the host wait for a fused step's published status (DG_EHIP when
+    exceeded; synchronise the stream before using the state then)."""
+    ctx._chk(_lib.dg_set_wait_limit(ctx.h, float(seconds)))
 
 
 def dg_set_forcing(ctx: Context, modes):

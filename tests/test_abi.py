@@ -59,6 +59,7 @@ def test_entry_points_reject_a_null_context_without_gpu():
     assert L.dg_rk_step_next(None, None, 1e-3, 0, None, dp) == dg.DG_EINVAL
     assert L.dg_rk_step_next_ahead(None, None, 1e-3, 0, 1.0, None, dp) == dg.DG_EINVAL
     assert L.dg_rhs(None, None, None, 1e-3) == dg.DG_EINVAL
+    assert L.dg_set_wait_limit(None, 1.0) == dg.DG_EINVAL
     assert L.dg_workspace_bytes(None) == 0
 
 
