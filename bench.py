@@ -3,36 +3,35 @@
 
 A step is one pass of the whole hot path over the state: time step (CFL and viscous
 bound, FP64 reduction on the GPU), driving-mode update when due (host Ornstein-Uhlenbeck
-+ table upload + driving field at the quadrature points), and one SSP-RK3 step
-(projection, three right-hand sides with viscosity, driving and Rusanov faces, three
-stage combinations with the positivity limiter).  The metric is DG degree-of-freedom
-updates per second per Runge-Kutta stage: 3 * 4 * nb * N^3 per step divided by the
-wall time of the timed steps.
++ table upload), and one SSP-RK3 step (projection, three right-hand sides with viscosity,
+driving and Rusanov faces, three stage combinations with the positivity limiter).  The
+metric is DG degree-of-freedom updates per second per Runge-Kutta stage: 3 * 4 * nb * N^3
+per step divided by the wall time of the timed steps.
 
-Default workload (c2): 64^3 cells, degree 2 (10 modes per variable, 27 Gauss points),
+Default workload (c5): 256^3 cells, degree 2 (10 modes per variable, 27 Gauss points),
 FP64, artificial viscosity + primitive projection + positivity limiter, mean-free
-solenoidal OU driving on 1 <= |n| <= 2 aimed at RMS Mach ~3 (t_c = T = 1/(2 Mach)),
-starting from density 1 at rest.  The untimed warm-up steps spin the turbulence up
-(the default 4000 warm-up steps reach t ~ 0.45, about 2.7 eddy turnover times); then
-exactly K steps are timed with the state resident in HBM.
+solenoidal OU driving on 1 <= |n| <= 2 aimed at RMS Mach ~10 (t_c = T = 1/(2 Mach)).
+A warm-up as long as the workload's spin-up (c5: 1500 steps) starts from density 1 at
+rest; a shorter one (the default 5) starts from the seeded turbulence-like state of the
+CPU leg (velocity RMS at the target Mach, log-normal density) and runs the warm-up steps
+from there.  Then exactly K steps are timed with the state resident in HBM.
 
-Comparison legs, from the same spun-up state and driving, timed the same way:
-  * the other precision with the plain sensor (FP32 bulk mode for the default workload);
+Comparison legs, from the same state and driving, timed the same way:
+  * the other precision with the plain sensor (FP32 bulk mode for the FP64 workloads);
   * FP32 with the learned sensor (degree 2), whose network is trained by the library's
-    kernels on sensor snapshots taken during the last part of the warm-up.
+    kernels on sensor snapshots taken during the warm-up (at least its last state).
 Each leg reports its throughput, its k_rhs roofline and the difference of its final state
 from the main run's: per-field relative L2, density-PDF L1 distance and velocity-spectrum
 log distance (the FP32 legs' statistics error against the FP64 path).
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c1|c2|c3|c4|c5]
                        [--precision fp64|fp32] [--no-compare] [--no-learned] [--no-cpu]
-                       [--no-stats]
+                       [--no-stats] [--rho-floor-rel R]
 """
 from __future__ import annotations
 
 import argparse
 import dataclasses
-import hashlib
 import json
 import os
 import sys
@@ -48,7 +47,7 @@ FP32_UNPACKED_TFLOPS = 78.6  # issue limit without packed FP32, which the librar
 PEAK_HBM_TBPS = 8.0          # MI355X HBM3E
 
 WORKLOADS = {
-    # name: (N, degree, default precision, target Mach, driving sigma, default warm-up steps)
+    # name: (N, degree, default precision, target Mach, driving sigma, spin-up steps from rest)
     # sigma: stationary standard deviation of each OU component, from spin-up runs at 64^3
     # (RMS Mach grows as (sigma^2 t_c)^(1/3), Sec. 4.2; the calibration is statistical):
     # sigma 2.5 gives Mach 3.07 at t = 2.7 t_c, sigma 28 gives Mach 9.1 at t = 2.4 t_c
@@ -57,8 +56,22 @@ WORKLOADS = {
     "c2": (64, 2, "fp64", 3.0, 2.5, 4000),
     "c3": (128, 3, "fp32", 10.0, 28.0, 1000),
     "c4": (128, 2, "fp32", 10.0, 28.0, 1000),
-    "c5": (256, 2, "fp32", 10.0, 28.0, 1500),
+    "c5": (256, 2, "fp64", 10.0, 28.0, 1500),
 }
+DEFAULT_WORKLOAD = "c5"
+DEFAULT_WARMUP = 5
+# log-normal width of the seeded start state's density: that of Mach 3 (a wider one puts
+# cell means of the 256^3 mesh below the density floor, which no time step can repair)
+START_DENSITY_MACH = 3.0
+
+
+def start_state(workload, seed):
+    """The seeded turbulence-like start state of a driven workload (numpy, FP64), shared by
+    the GPU run (short warm-up) and the CPU leg."""
+    import synthetic
+    N, k, _, mach, _, _ = WORKLOADS[workload]
+    return synthetic.turbulent_like(N, N, N, k, mach=mach, seed=seed, high_amp=0.02, kmax_frac=0.125,
+                                    density_mach=min(mach, START_DENSITY_MACH))
 
 
 # workloads without driving, artificial viscosity or projection: the 16^3 degree-1 sound wave
@@ -74,32 +87,37 @@ def workload_flags(workload):
     return dg.DG_AV | dg.DG_PRIM_PROJ | dg.DG_POS_LIMITER | dg.DG_FORCING | dg.DG_FORCE_MEANFREE
 
 
-# the sources that define and launch the step kernels (the counters in profiles/ are valid
-# while these are unchanged)
-STEP_SOURCES = ("dg_api.hip", "dg_basis.hpp", "dg_ctx.hpp", "dg_kernels.hpp")
-
-
 def source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2401_06841_amd", "csrc")
-    for f in STEP_SOURCES:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    """Hash of the step kernels' sources (the counters in profiles/ are valid while it holds)."""
+    from paper_2401_06841_amd.profiling import source_hash as h
+    return h()
 
 
-def traffic_from_profiles(kernel, workload, precision, launches_unit):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or None when the
-    kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_traffic.json")
+def _profile_record(kernel, workload, precision, what):
+    """A committed rocprofv3 counter summary (profiles/<kernel>_<workload>_<precision>_<what>.json),
+    or None when it is missing or the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{precision}_{what}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("source_hash") != source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec
+
+
+def traffic_from_profiles(kernel, workload, precision, launches_unit=1):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, calibrated with a plain copy)."""
+    rec = _profile_record(kernel, workload, precision, "traffic")
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def executed_flops_from_profiles(kernel, workload, precision):
+    """Floating-point operations the kernel executes per launch, from the SQ counters of its
+    VALU additions, multiplications, fused multiply-adds (2) and transcendentals, 64 lanes
+    per wave instruction."""
+    rec = _profile_record(kernel, workload, precision, "flops")
+    return rec.get("flops_per_launch") if rec else None
 
 
 def _timed(sim, steps, measure_profile):
@@ -147,6 +165,12 @@ def _summary(args, sim, precision, wall, prof, retries, dt_min):
                            "traffic": traffic_from_profiles("k_rhs", args.workload, precision, 1)}
         if precision == "fp32":
             out["roofline"]["frac_of_unpacked_fp32"] = achieved / FP32_UNPACKED_TFLOPS
+        executed = executed_flops_from_profiles("k_rhs", args.workload, precision)
+        if executed:
+            # the flops the kernel issues (counted), beside the model count of Sec. 7
+            out["roofline"]["executed_flops_per_launch"] = executed
+            out["roofline"]["executed_TFLOP_s"] = executed / (avg * 1e-3) / 1e12
+            out["roofline"]["executed_frac"] = out["roofline"]["executed_TFLOP_s"] / peak
         traffic = out["roofline"]["traffic"]
         if traffic:
             # HBM rate implied by the counted bytes per launch over the live launch time
@@ -222,16 +246,19 @@ def run_gpu(args, precision, measure_profile=True):
     from paper_2401_06841_amd import analysis, dg, sensor
     from paper_2401_06841_amd.driver import Driving, Simulation
 
-    N, k, _, mach, sigma, _ = WORKLOADS[args.workload]
+    N, k, _, mach, sigma, spinup = WORKLOADS[args.workload]
     flags = workload_flags(args.workload)
     prec = dg.DG_FP64 if precision == "fp64" else dg.DG_FP32
-    cfg = dg.Config(N, N, N, degree=k, precision=prec, flags=flags)
+    cfg = dg.Config(N, N, N, degree=k, precision=prec, flags=flags, rho_floor_rel=args.rho_floor_rel)
+    dtype = torch.float64 if prec == dg.DG_FP64 else torch.float32
     if args.workload in UNDRIVEN:
         import synthetic
         drv = None
-        u = torch.as_tensor(synthetic.c1_modal_state(args.seed, N), device="cuda").to(
-            torch.float64 if prec == dg.DG_FP64 else torch.float32).contiguous()
+        u = torch.as_tensor(synthetic.c1_modal_state(args.seed, N), device="cuda").to(dtype).contiguous()
         sim = Simulation(cfg, u=u, driving=None)
+    elif args.start_state is not None:
+        drv = Driving(mach, sigma, seed=args.seed)
+        sim = Simulation(cfg, u=torch.as_tensor(args.start_state, device="cuda").to(dtype).contiguous(), driving=drv)
     else:
         drv = Driving(mach, sigma, seed=args.seed)
         sim = Simulation(cfg, driving=drv)
@@ -288,12 +315,26 @@ def run_gpu(args, precision, measure_profile=True):
     return main, compare
 
 
+def _omp_threads(n=None):
+    """The OpenMP thread count of the oracle's parallel loops (set when n is given)."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    if n is not None:
+        gomp.omp_set_num_threads(int(n))
+    return int(gomp.omp_get_max_threads())
+
+
 def run_cpu_baseline(args):
     """The oracle as it stands, timed on the host cores on a bounded sample of the same
-    workload (same mesh, degree, flags and driving), from the seeded synthetic
-    turbulence-like state (the oracle's cost does not depend on the flow): whole SSP-RK3
-    steps where they take seconds (64^3), otherwise one right-hand side of the whole mesh
-    (the dominant work of one stage; the stage combination is a few operations per DOF)."""
+    workload (same mesh, degree, flags and driving), from the seeded start state the GPU run
+    uses for short warm-ups (the oracle's cost does not depend on the flow): whole SSP-RK3
+    steps where they take seconds (64^3 and below), otherwise one right-hand side of the whole
+    mesh (the dominant work of one stage; the stage combination is a few operations per DOF).
+    Also on one core: the per-cell right-hand side over a seeded sample of cells, timed with
+    one thread and with all of them (the per-cell form also projects the velocity of the six
+    neighbours, so its rate is below the whole-mesh form's)."""
+    import numpy as np
+
     import oracle
     import synthetic
 
@@ -304,10 +345,12 @@ def run_cpu_baseline(args):
         modes = None
     else:
         flags = oracle.AV | oracle.PRIM_PROJ | oracle.POS_LIMITER | oracle.FORCING | oracle.FORCE_MEANFREE
-        cfg = oracle.Cfg(N, N, N, k, flags=flags)
-        u = synthetic.turbulent_like(N, N, N, k, mach=mach, seed=args.seed, high_amp=0.02, kmax_frac=0.125)
+        cfg = oracle.Cfg(N, N, N, k, flags=flags, rho_floor_rel=args.rho_floor_rel)
+        u = args.start_state if args.start_state is not None else start_state(args.workload, args.seed)
         modes = synthetic.forcing_table(args.seed, amp=sigma)
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.lib()
+    cores = _omp_threads()
+    dof = 4 * cfg.nb * cfg.ncell
     if N <= 64:
         # the 16^3 workload takes milliseconds per step: time enough steps for a stable figure
         nsteps = max(args.cpu_steps, 200) if args.workload in UNDRIVEN else args.cpu_steps
@@ -316,16 +359,31 @@ def run_cpu_baseline(args):
             dt = oracle.dt_max(cfg, u)
             u, st = oracle.rk_step(cfg, u, dt, modes)
         wall = time.perf_counter() - t0
-        dof = 4 * cfg.nb * cfg.ncell
-        return {"value": 3.0 * dof * nsteps / wall, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
-                "sample": f"{nsteps} SSP-RK3 steps ({3 * nsteps} stages) of the {N}^3 degree-{k} workload, "
-                          f"FP64 C oracle with OpenMP over cells, {wall:.1f} s"}
-    t0 = time.perf_counter()
-    oracle.rhs(cfg, u, 1e-5, modes)
-    wall = time.perf_counter() - t0
-    return {"value": 4 * cfg.nb * cfg.ncell / wall, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
-            "sample": f"one right-hand side of the whole {N}^3 degree-{k} mesh (the work of one stage without the "
-                      f"stage combination), FP64 C oracle with OpenMP over cells, {wall:.1f} s"}
+        rec = {"value": 3.0 * dof * nsteps / wall, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+               "sample": f"{nsteps} SSP-RK3 steps ({3 * nsteps} stages) of the {N}^3 degree-{k} workload, "
+                         f"FP64 C oracle with OpenMP over cells, {wall:.1f} s"}
+    else:
+        t0 = time.perf_counter()
+        oracle.rhs(cfg, u, 1e-5, modes)
+        wall = time.perf_counter() - t0
+        rec = {"value": dof / wall, "unit": "DOF-updates/s", "cores": cores, "kind": "oracle",
+               "sample": f"one right-hand side of the whole {N}^3 degree-{k} mesh (the work of one stage without "
+                         f"the stage combination), FP64 C oracle with OpenMP over cells, {wall:.1f} s"}
+    ns = min(cfg.ncell, args.cpu_cells)
+    cells = np.sort(np.random.default_rng(args.seed).choice(cfg.ncell, ns, replace=False))
+    abar = oracle.forcing_mean(cfg, u, modes) if modes is not None else None
+    rates = {}
+    for threads in (1, cores):
+        _omp_threads(threads)
+        t0 = time.perf_counter()
+        oracle.rhs_cells(cfg, u, cells, 1e-5, modes, abar)
+        rates[threads] = 4 * cfg.nb * ns / (time.perf_counter() - t0)
+    _omp_threads(cores)
+    rec["one_core"] = {"value": rates[1], "unit": "DOF-updates/s", "cores": 1,
+                       "all_cores_same_sample": rates[cores],
+                       "sample": f"per-cell right-hand side (orc_rhs_cells) of {ns} seeded cells of the same state, "
+                                 f"with its six neighbours' projections; 1 thread and {cores} threads"}
+    return rec
 
 
 def copy_calibration():
@@ -344,10 +402,16 @@ def copy_calibration():
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=None)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=DEFAULT_WARMUP)
     p.add_argument("--verbose", action="store_true")
-    p.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    p.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
+    p.add_argument("--start", default="auto", choices=["auto", "rest", "turbulent"],
+                   help="driven workloads: start at rest, or from the seeded turbulence-like state "
+                        "(auto: the latter when the warm-up is shorter than the workload's spin-up)")
+    p.add_argument("--rho-floor-rel", type=float, default=0.1,
+                   help="relative part of the limiter's target density max(1e-3, R * cell mean)")
+    p.add_argument("--cpu-cells", type=int, default=50000)
     p.add_argument("--precision", default=None, choices=["fp64", "fp32"])
     p.add_argument("--seed", type=int, default=1)
     p.add_argument("--no-compare", action="store_true")
@@ -369,10 +433,11 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    N, k, default_prec, mach, sigma, default_warmup = WORKLOADS[args.workload]
-    if args.warmup is None:
-        args.warmup = default_warmup
+    N, k, default_prec, mach, sigma, spinup = WORKLOADS[args.workload]
     precision = args.precision or default_prec
+    turbulent_start = args.workload not in UNDRIVEN and (
+        args.start == "turbulent" or (args.start == "auto" and args.warmup < spinup))
+    args.start_state = start_state(args.workload, args.seed) if turbulent_start else None
     main_run, compare = run_gpu(args, precision)
     cpu = None if args.no_cpu else run_cpu_baseline(args)
     rec = {
@@ -392,8 +457,13 @@ def main():
                                f"{(k + 1) ** 3} Gauss points), isothermal Euler, " + (
                                    "sound wave of amplitude 1e-3, positivity limiter only (launch-latency bound: "
                                    "the roofline fraction does not measure the kernels)" if args.workload in UNDRIVEN
-                                   else f"AV + primitive projection + positivity limiter, mean-free OU driving "
-                                        f"(target RMS Mach {mach:g})"),
+                                   else f"AV + primitive projection + positivity limiter (target max(1e-3, "
+                                        f"{args.rho_floor_rel:g} x cell mean)), mean-free OU driving (target RMS "
+                                        f"Mach {mach:g}), " + (
+                                            f"timed after {args.warmup} warm-up steps from a seeded turbulence-like "
+                                            f"state (velocity RMS Mach {mach:g}, log-normal density of the Mach "
+                                            f"{min(mach, START_DENSITY_MACH):g} width)" if turbulent_start else
+                                            f"timed after a spin-up of {args.warmup} steps from rest")),
                    "cells": N ** 3, "degree": k, "dof": 4 * ((k + 1) * (k + 2) * (k + 3) // 6) * N ** 3,
                    "parallelism": "single GPU"},
         "roofline": main_run.get("roofline"),

@@ -109,11 +109,34 @@ def power_spectrum(v):
     return np.bincount(shell.reshape(-1), weights=e.reshape(-1))
 
 
-def spectrum_distance(e_test, e_ref, kmax: int) -> float:
-    a = np.asarray(e_test)[1:kmax + 1]
-    b = np.asarray(e_ref)[1:kmax + 1]
-    ok = (a > 0) & (b > 0)
-    return float(np.mean(np.abs(np.log10(a[ok]) - np.log10(b[ok])))) if ok.any() else float("nan")
+# shells whose reference power is below this fraction of the spectrum's peak hold rounding
+# noise, not flow (FP32 rounding of the velocity leaves about 1e-14 of the peak power there)
+SPECTRUM_FLOOR = 1e-10
+
+
+def _spectrum_shells(e_test, e_ref, kmax: int, floor: float):
+    a = np.asarray(e_test, dtype=np.float64)[1:kmax + 1]
+    b = np.asarray(e_ref, dtype=np.float64)[1:kmax + 1]
+    ok = (a > 0) & (b > 0) & (b >= floor * b.max()) if b.size else np.zeros(0, bool)
+    return a[ok], b[ok]
+
+
+def spectrum_distance(e_test, e_ref, kmax: int, floor: float = SPECTRUM_FLOOR) -> float:
+    """Mean |log10 E_test - log10 E_ref| over the shells 1..kmax whose reference power is at
+    least floor times the reference peak (shells at the rounding level are left out)."""
+    a, b = _spectrum_shells(e_test, e_ref, kmax, floor)
+    return float(np.mean(np.abs(np.log10(a) - np.log10(b)))) if a.size else float("nan")
+
+
+def spectrum_distance_energy_weighted(e_test, e_ref, kmax: int, floor: float = SPECTRUM_FLOOR) -> float:
+    """|log10 E_test - log10 E_ref| averaged over the same shells with the reference power as
+    the weight (the error where the kinetic energy is)."""
+    a, b = _spectrum_shells(e_test, e_ref, kmax, floor)
+    return float(np.sum(b * np.abs(np.log10(a) - np.log10(b))) / np.sum(b)) if a.size else float("nan")
+
+
+def spectrum_shells_used(e_ref, kmax: int, floor: float = SPECTRUM_FLOOR) -> int:
+    return int(_spectrum_shells(e_ref, e_ref, kmax, floor)[0].size)
 
 
 SF_BINS, SF_PAIRS, SF_SEED = 100, 100000, 0x5F3759DF
@@ -202,6 +225,8 @@ def compare(u_test, u_ref, k: int, n: tuple[int, int, int], ctx_test=None, ctx_r
         return {"l2_rel_rho": rho, "l2_rel_m": mom, "density_pdf_l1": pdf_distance(pa, pb),
                 "spectrum_samples_per_cell": p,
                 "spectrum_log10_mean_abs": spectrum_distance(ea, eb, min(n) * p // 2),
+                "spectrum_log10_energy_weighted": spectrum_distance_energy_weighted(ea, eb, min(n) * p // 2),
+                "spectrum_shells_used": spectrum_shells_used(eb, min(n) * p // 2),
                 "spectrum_log10_mean_abs_cell_scales": spectrum_distance(ea, eb, min(n) // 2),
                 "structure_function_log10_mean_abs": log_distance(va, vb)}
     # k+1 samples per cell (the paper's N p grid), fewer on large meshes so that the grid
@@ -213,4 +238,6 @@ def compare(u_test, u_ref, k: int, n: tuple[int, int, int], ctx_test=None, ctx_r
     return {"l2_rel_rho": rho, "l2_rel_m": mom, "density_pdf_l1": pdf_distance(pa, pb),
             "spectrum_samples_per_cell": p,
             "spectrum_log10_mean_abs": spectrum_distance(ea, eb, kmax),
+            "spectrum_log10_energy_weighted": spectrum_distance_energy_weighted(ea, eb, kmax),
+            "spectrum_shells_used": spectrum_shells_used(eb, kmax),
             "spectrum_log10_mean_abs_cell_scales": spectrum_distance(ea, eb, min(n) // 2)}

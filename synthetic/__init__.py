@@ -82,11 +82,14 @@ def _smooth(rng, shape, kmax: float, slope: float):
 
 
 def turbulent_like(nx: int, ny: int, nz: int, k: int, mach: float, seed: int,
-                   high_amp: float = 0.08, kmax_frac: float = 0.25, dtype=np.float64):
+                   high_amp: float = 0.08, kmax_frac: float = 0.25, dtype=np.float64,
+                   density_mach: float | None = None):
     """Random modal state [4][nb][ncell] resembling driven isothermal turbulence.
 
-    Cell means: log-normal density with variance ln(1 + (mach/3)^2) (solenoidal driving),
-    velocity of RMS |v| = mach.  Higher modes: random density modes of relative amplitude
+    Cell means: log-normal density with variance ln(1 + (M_rho/3)^2) (solenoidal driving),
+    M_rho = density_mach if given else mach, velocity of RMS |v| = mach.  (A narrower
+    density than the target Mach's keeps every cell mean of a large mesh above a density
+    floor: at Mach 10 on 256^3 cells the full width reaches means of 1e-4.)  Higher modes: random density modes of relative amplitude
     high_amp/(1 + l/4) scaled by the local contrast, random velocity modes of amplitude
     high_amp/(1 + l/4) times the local speed, and momentum modes built as the first-order
     product of the two (m_l = v_mean rho_l + rho_mean v_l), so that the velocity m/rho stays
@@ -95,7 +98,7 @@ def turbulent_like(nx: int, ny: int, nz: int, k: int, mach: float, seed: int,
     rng = np.random.default_rng(seed)
     shape = (nz, ny, nx)
     kmax = max(2.0, min(nx, ny, nz) * kmax_frac)
-    sig2 = np.log(1.0 + (mach / 3.0) ** 2)
+    sig2 = np.log(1.0 + ((mach if density_mach is None else density_mach) / 3.0) ** 2)
     s = np.sqrt(sig2) * _smooth(rng, shape, kmax, 2.0)
     rho = np.exp(s - 0.5 * sig2)
     vel = [mach / np.sqrt(3.0) * _smooth(rng, shape, kmax, 2.0) for _ in range(3)]

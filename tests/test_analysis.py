@@ -80,3 +80,28 @@ def test_sonic_scale_of_a_power_law():
     assert analysis.sonic_scale(l, v) == pytest.approx(0.5 / 16, rel=1e-12)
     assert analysis.sonic_scale(l, 0.5 * np.ones_like(l)) is None    # subsonic everywhere
     assert analysis.sonic_scale(l, 2.0 * np.ones_like(l)) is None    # supersonic at every bin
+
+
+def test_spectrum_distance_ignores_shells_at_the_rounding_level():
+    """Two velocity fields that agree to FP32 rounding: the smooth field has power in a few
+    shells only, every other shell holds rounding noise (about 1e-30 of the peak in FP64,
+    about 1e-14 after FP32 rounding).  Over all shells the mean log distance is of order 1;
+    over the shells above the floor it is near 0, and so is the energy-weighted one.  A
+    real difference (a mode's amplitude 10 % off) still shows."""
+    m = 32
+    z, y, x = np.meshgrid(*(np.arange(m) / m,) * 3, indexing="ij")
+    v = np.zeros((3, m, m, m))
+    v[0] = np.sin(2 * np.pi * y) + 0.3 * np.sin(2 * np.pi * 4 * z)
+    v[1] = 0.5 * np.cos(2 * np.pi * 2 * x)
+    w = v.astype(np.float32).astype(np.float64)
+    ev, ew = analysis.power_spectrum(v), analysis.power_spectrum(w)
+    a, b = ew[1:m // 2 + 1], ev[1:m // 2 + 1]
+    ok = (a > 0) & (b > 0)
+    assert np.mean(np.abs(np.log10(a[ok]) - np.log10(b[ok]))) > 0.5      # the unfiltered mean
+    assert analysis.spectrum_distance(ew, ev, m // 2) < 1e-6
+    assert analysis.spectrum_distance_energy_weighted(ew, ev, m // 2) < 1e-6
+    assert analysis.spectrum_shells_used(ev, m // 2) == 3
+    v2 = v.copy()
+    v2[1] *= 1.1
+    d = analysis.spectrum_distance(analysis.power_spectrum(v2), ev, m // 2)
+    assert abs(d - np.log10(1.21) / 3) < 1e-9                                # one shell of three

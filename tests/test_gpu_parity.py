@@ -12,7 +12,7 @@ import torch
 
 import oracle
 import synthetic
-from gpu_util import dev, field_rel, host, make
+from gpu_util import assert_state_close, dev, dof_rel, field_rel, host, make
 from paper_2401_06841_amd import dg
 
 pytestmark = pytest.mark.gpu
@@ -176,18 +176,20 @@ def test_projection_and_dt(k, precision):
     assert host(dbuf)[0] == dt
 
 
+@pytest.mark.parametrize("rel", [0.1, 0.0])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_limiter_and_sums(k):
+def test_limiter_and_sums(k, rel):
     u = synthetic.turbulent_like(10, 6, 5, k, mach=4.0, seed=21, high_amp=0.6)
-    ocfg = _orc_cfg(10, 6, 5, k, ALL)
+    ocfg = oracle.Cfg(10, 6, 5, k, flags=ALL, rho_floor_rel=rel)
     lim, nfail, theta = oracle.limit(ocfg, u)
     assert nfail == 0 and (theta < 1).sum() > 5      # the limiter acts on several cells
-    ctx = make(10, 6, 5, k, ALL)
+    ctx = make(10, 6, 5, k, ALL, rho_floor_rel=rel)
     ud = dev(u, ctx)
     n = dg.dg_limit(ctx, ud)
     assert n == 0
     got = host(ud)
     assert max(field_rel(got, lim, lim)) < 1e-13
+    assert max(dof_rel(got, lim, lim)) < 1e-13
     s = dg.dg_conserved_sums(ctx, ud)
     np.testing.assert_allclose(s, oracle.conserved_sums(ocfg, lim), rtol=1e-13, atol=1e-15)
     bad = u.copy()
@@ -196,9 +198,10 @@ def test_limiter_and_sums(k):
     assert dg.dg_limit(ctx, bd) == 1
 
 
+@pytest.mark.parametrize("rel", [0.1, 0.0])
 @pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_limiter_waves_that_skip_the_point_sums(k, precision):
+def test_limiter_waves_that_skip_the_point_sums(k, precision, rel):
     """64 x 3 x 2 cells, so that every wave holds one x line: five smooth lines, where a
     modal bound already shows that no point can fall below the target (those waves skip the
     point evaluations), and one line with strong high modes that the limiter must scale."""
@@ -208,15 +211,16 @@ def test_limiter_waves_that_skip_the_point_sums(k, precision):
     u[:, :, line] = rough[:, :, line]
     if precision == dg.DG_FP32:
         u = u.astype(np.float32).astype(np.float64)
-    ocfg = _orc_cfg(64, 3, 2, k, ALL)
+    ocfg = oracle.Cfg(64, 3, 2, k, flags=ALL, rho_floor_rel=rel)
     lim, nfail, theta = oracle.limit(ocfg, u)
     assert nfail == 0
     assert (theta[line] < 1).sum() > 3 and np.all(theta[64:] == 1)
-    ctx = make(64, 3, 2, k, ALL, precision)
+    ctx = make(64, 3, 2, k, ALL, precision, rho_floor_rel=rel)
     ud = dev(u, ctx)
     assert dg.dg_limit(ctx, ud) == 0
     got = host(ud)
     assert max(field_rel(got, lim, lim)) < (1e-13 if precision == dg.DG_FP64 else 1e-6)
+    assert max(dof_rel(got, lim, lim)) < (1e-13 if precision == dg.DG_FP64 else 1e-6)
     assert np.array_equal(got[:, :, 64:], host(dev(u, ctx))[:, :, 64:])   # smooth lines untouched
 
 
@@ -237,8 +241,7 @@ def test_c1_sound_wave_20_steps():
             u, st = oracle.rk_step(ocfg, u, dt)
             assert st == oracle.OK
             assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_OK
-        e = field_rel(host(ud), u, u)
-        assert max(e) < 1e-12, e
+        assert_state_close(host(ud), u, 1e-12, f"C1 seed {seed}")
         # the increment over 20 steps is reproduced too (not just the background)
         de = field_rel(host(ud) - u0, u - u0, u - u0)
         assert max(de) < 1e-9, de
@@ -261,8 +264,7 @@ def test_rk_step_turbulent_with_forcing(precision):
         u, st = oracle.rk_step(ocfg, u, dt, modes)
         assert st == oracle.OK
         assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_OK
-    e = field_rel(host(ud), u, u)
-    assert max(e) < TOL[precision], e
+    assert_state_close(host(ud), u, TOL[precision], "3 driven steps")
 
 
 def test_rk_step_retry_restores_state():
@@ -281,8 +283,10 @@ def test_rk_step_retry_restores_state():
 
 # States and time steps whose SSP-RK3 step passes the positivity check in its first two
 # stages and fails it in the last (found with the oracle: 6 x 5 x 4 cells, Mach 4, seed 0,
-# the given multiple of the CFL time step).
-LAST_STAGE_FAILURES = {1: 10.75, 2: 4.5, 3: 25.5}
+# the given multiple of the CFL time step), for the limiter target max(floor, 0.1 mean) and
+# for the absolute floor alone (relative part 0: the limiter acts only where a point
+# density falls below the floor, as in Sec. 3.1).
+LAST_STAGE_FAILURES = {0.1: {1: 10.75, 2: 4.5, 3: 25.5}, 0.0: {1: 10.5, 2: 2.75, 3: 24.0}}
 _SSPRK3 = [(0.0, 1.0, 1.0), (0.75, 0.25, 0.25), (1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0)]
 
 
@@ -296,21 +300,22 @@ def _oracle_stage_minima(ocfg, u, dt):
     return out
 
 
+@pytest.mark.parametrize("rel", [0.1, 0.0])
 @pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_last_stage_failure_leaves_state(k, precision):
+def test_last_stage_failure_leaves_state(k, precision, rel):
     """Only the last stage writes the caller's array, and its failure is decided from the
     stage's density means before it writes: on DG_RETRY the array is bitwise the input."""
-    print(f"last-stage failure k={k} precision={precision}", flush=True)
+    print(f"last-stage failure k={k} precision={precision} rel={rel}", flush=True)
     u = synthetic.turbulent_like(6, 5, 4, k, mach=4.0, seed=0)
     if precision == dg.DG_FP32:
         u = u.astype(np.float32).astype(np.float64)
-    ocfg = _orc_cfg(6, 5, 4, k, ALL)
-    dt = LAST_STAGE_FAILURES[k] * oracle.dt_max(ocfg, u)
+    ocfg = oracle.Cfg(6, 5, 4, k, flags=ALL, rho_floor_rel=rel)
+    dt = LAST_STAGE_FAILURES[rel][k] * oracle.dt_max(ocfg, u)
     m = _oracle_stage_minima(ocfg, u, dt)
     assert m[0] > 1e-2 and m[1] > 1e-2 and m[2] < -1e-2, m
     assert oracle.rk_step(ocfg, u, dt)[1] == oracle.RETRY
-    ctx = make(6, 5, 4, k, ALL, precision)
+    ctx = make(6, 5, 4, k, ALL, precision, rho_floor_rel=rel)
     ud = dev(u, ctx)
     before = ud.clone()
     assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_RETRY
@@ -322,7 +327,7 @@ def test_last_stage_failure_leaves_state(k, precision):
     rc, _ = dg.dg_rk_step_next(ctx, ud, 0.25 * dt, False)
     ref, st = oracle.rk_step(ocfg, u, 0.25 * dt)
     assert rc == dg.DG_OK and st == oracle.OK
-    assert max(field_rel(host(ud), ref, ref)) < TOL[precision]
+    assert_state_close(host(ud), ref, TOL[precision], "retried step")
 
 
 def test_bitwise_determinism():
@@ -397,8 +402,7 @@ def test_c2_full_size_fused_step(precision):
     rc, dt_next = dg.dg_rk_step_next(ctx, ud, dt, False)
     assert rc == dg.DG_OK
     tol = 1e-12 if precision == dg.DG_FP64 else 1e-5
-    e = field_rel(host(ud), ref, ref)
-    assert max(e) < tol, e
+    assert_state_close(host(ud), ref, tol, "64^3 fused step")
     dref = oracle.dt_max(ocfg, ref)
     assert abs(dt_next - dref) <= tol * dref, (dt_next, dref)
 
@@ -428,8 +432,7 @@ def test_rk_steps_hllc():
         u, st = oracle.rk_step(ocfg, u, dt, modes)
         assert st == oracle.OK
         assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_OK
-    e = field_rel(host(ud), u, u)
-    assert max(e) < TOL[dg.DG_FP64], e
+    assert_state_close(host(ud), u, TOL[dg.DG_FP64], "HLLC steps")
 
 
 def test_stationary_shear_layer_is_steady_with_hllc():
@@ -479,8 +482,7 @@ def test_rk_by_order_steps(k, precision):
         else:
             rc, _ = dg.dg_rk_step_next(ctx, ud, dt, False)
             assert rc == dg.DG_OK
-    e = field_rel(host(ud), u, u)
-    assert max(e) < TOL[precision], e
+    assert_state_close(host(ud), u, TOL[precision], f"scheme by degree k={k}")
     # the scheme really differs from the default three-stage one at degrees 1 and 3
     if k != 2:
         ref3 = u0.copy()
