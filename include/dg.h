@@ -189,6 +189,20 @@ int dg_rk_step_next_ahead(dg_ctx *ctx, void *u, double dt, int reuse, double hor
  * *dt_out is device memory (8 bytes). */
 int dg_dt_max(dg_ctx *ctx, const void *u, double *dt_out, int on_host);
 
+/* dg_dt_max for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same time step, bit for bit,
+ * without a workspace.  Its per-block maxima and the reduced value live in a static device
+ * array of the library (1 MiB + 256 bytes per GPU, held until the process ends), so the call
+ * allocates nothing and needs no dg_set_workspace.  Limit: at most 16,777,216 cells (65,536
+ * blocks of 256 cells), DG_EINVAL beyond.  The array is shared by every context on a GPU
+ * and keeps the last call's contents (nothing in it needs clearing): calls that overlap in
+ * time on one GPU race, so issue them on one stream or serialise them.  The device current
+ * at the call must be the context's.  on_host = 1: *dt_out is host memory and the call
+ * synchronises; on_host = 0: *dt_out is device memory (8 bytes).  Errors: DG_EINVAL (null or
+ * misaligned pointer, mesh too large, other device current), DG_EUNSUPPORTED (learned
+ * sensor, whose viscosity lives in the workspace), DG_EHIP. */
+int dg_dt_max_noalloc(dg_ctx *ctx, const void *u, double *dt_out, int on_host);
+
 /* Projected velocity (Sec. 3.2, eq. weights_equation with the interior rule):
  * vhat_{d,l} = (1/8) sum_q w_q phi_l(q) m_d(q)/rho(q); vhat is [3][nb][ncell] device. */
 int dg_project_primitive(dg_ctx *ctx, const void *u, void *vhat);

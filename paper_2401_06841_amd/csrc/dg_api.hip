@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -16,6 +17,36 @@
 #include "dg_kernels.hpp"
 
 using namespace dg;
+
+// ------------------------------------------------------------ static scratch
+// Device memory of dg_dt_max_noalloc, for callers that cannot allocate: the per-block
+// time-step maxima (two doubles per block) and the reduced time step.  Every GPU the
+// library runs on holds its own copy for the life of the process.  In host code the array's
+// name is not a device address: its address on each device is looked up once, at the first
+// dg_init with that device current, and only that address is handed to kernels.
+constexpr int NOALLOC_MAX_BLOCKS = 65536;                        // 16,777,216 cells
+constexpr int NOALLOC_DT_SLOT = 2 * NOALLOC_MAX_BLOCKS;
+static __device__ __align__(256) double scratch[NOALLOC_DT_SLOT + 32];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+double *noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// address of this device's copy of the scratch array (looked up once per device)
+int noalloc_setup(dg_ctx *c, int dev)
+{
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return DG_OK;      // the entry point reports it
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_ptr[dev]) return DG_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return dg_fail(c, DG_EHIP, "hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+    noalloc_ptr[dev] = (double *)ptr;
+    return DG_OK;
+}
+}  // namespace
 
 // ------------------------------------------------------------------ errors
 int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...)
@@ -239,6 +270,11 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
             c->ncu = ncu;
+        c->device = dev;
+        if (noalloc_setup(c, dev) != DG_OK) {
+            delete c;
+            return DG_EHIP;
+        }
     }
     layout(c, &c->ws_need);
 
@@ -621,7 +657,7 @@ static int launch_dt_final(dg_ctx *c, const double *src, double *dst, long long 
     volatile long long *pub = seq > 0 ? (volatile long long *)(c->pinned + dg_ctx::PUB) : nullptr;
     hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, src, c->nblk, 2,
                        c->cfg.cfl * c->cfg.h / (K + 1), c->cfg.cfl_visc > 0.0 ? c->cfg.cfl_visc * hp * hp : 0.0,
-                       dst, (const int *)c->fail(), pub, seq, vmax, np2);
+                       dst, (const int *)(pub ? c->fail() : nullptr), pub, seq, vmax, np2);
     LAUNCHCHK(c);
     return DG_OK;
 }
@@ -904,6 +940,42 @@ int dg_dt_max(dg_ctx *c, const void *u, double *dt_out, int on_host)
     if (!dt_out) return dg_fail(c, DG_EINVAL, "dt_out is null");
     if ((rc = learned_ready(c))) return rc;
     return DISPATCH(c, do_dt, c, u, dt_out, on_host);
+}
+
+template <typename T, int K>
+static int do_dt_noalloc(dg_ctx *c, const void *u, double *dt_out, int on_host, double *scr)
+{
+    int rc = launch_project<T, K>(c, u, nullptr, scr, nullptr);
+    if (rc) return rc;
+    double *dst = on_host ? scr + NOALLOC_DT_SLOT : dt_out;
+    rc = launch_dt_final<T, K>(c, scr, dst);
+    if (rc) return rc;
+    if (on_host) {
+        HIPCHK(c, hipMemcpyAsync(c->pinned, dst, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *dt_out = ((volatile double *)c->pinned)[0];
+    }
+    return DG_OK;
+}
+
+int dg_dt_max_noalloc(dg_ctx *c, const void *u, double *dt_out, int on_host)
+{
+    if (!c) return DG_EINVAL;
+    int rc;
+    if ((rc = check_ptr(c, u, "u"))) return rc;
+    if (!dt_out) return dg_fail(c, DG_EINVAL, "dt_out is null");
+    if (c->cfg.flags & DG_LEARNED_SENSOR)
+        return dg_fail(c, DG_EUNSUPPORTED, "dg_dt_max_noalloc: the learned sensor's viscosity lives in the workspace");
+    if (c->nblk > NOALLOC_MAX_BLOCKS)
+        return dg_fail(c, DG_EINVAL, "dg_dt_max_noalloc: %d cells need %d blocks of partials, the static scratch holds %d "
+                                     "(%d cells)", c->nc, c->nblk, NOALLOC_MAX_BLOCKS, NOALLOC_MAX_BLOCKS * BLOCK);
+    int dev = -1;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev != c->device)
+        return dg_fail(c, DG_EINVAL, "dg_dt_max_noalloc: device %d is current, the context was created on %d", dev, c->device);
+    double *scr = (dev >= 0 && dev < NOALLOC_MAX_DEVICES) ? noalloc_ptr[dev] : nullptr;
+    if (!scr) return dg_fail(c, DG_EHIP, "dg_dt_max_noalloc: no static scratch on device %d", dev);
+    return DISPATCH(c, do_dt_noalloc, c, u, dt_out, on_host, scr);
 }
 
 template <typename T, int K>

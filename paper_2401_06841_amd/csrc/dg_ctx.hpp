@@ -19,6 +19,7 @@ struct dg_ctx {
     int k = 0, nb = 0, nq = 0, nc = 0, nblk = 0;
     int rhs_nblk = 0;              // blocks of the last right-hand-side launch (its partial sums)
     int ncu = 256;                 // compute units of the device (grid sizing of persistent-style kernels)
+    int device = 0;                // HIP device current at dg_init
     size_t es = 8;                 // element size of the state (8 = FP64, 4 = FP32)
     hipStream_t stream = nullptr;
     void *tab = nullptr;           // quadrature tables (element type of the state)

@@ -53,6 +53,7 @@ _SIGS = {
     "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double]),
     "dg_rk_step": (ctypes.c_int, [_vp, _vp, ctypes.c_double, _ip]),
     "dg_dt_max": (ctypes.c_int, [_vp, _vp, _dp, ctypes.c_int]),
+    "dg_dt_max_noalloc": (ctypes.c_int, [_vp, _vp, _dp, ctypes.c_int]),
     "dg_rk_step_next": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp]),
     "dg_rk_step_next_ahead": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_double, _ip, _dp]),
     "dg_project_primitive": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -255,6 +256,18 @@ def dg_dt_max(ctx: Context, u, out_dev=None) -> float:
         return None
     v = ctypes.c_double()
     ctx._chk(_lib.dg_dt_max(ctx.h, _ptr(u), ctypes.byref(v), 1))
+    return v.value
+
+
+def dg_dt_max_noalloc(ctx: Context, u, out_dev=None) -> float:
+    """dg_dt_max without the workspace: the library's static device scratch instead."""
+    ctx._check_state(u)
+    if out_dev is not None:
+        _need(ctx, out_dev, torch.float64, 1, "out_dev")
+        ctx._chk(_lib.dg_dt_max_noalloc(ctx.h, _ptr(u), ctypes.cast(ctypes.c_void_p(out_dev.data_ptr()), _dp), 0))
+        return None
+    v = ctypes.c_double()
+    ctx._chk(_lib.dg_dt_max_noalloc(ctx.h, _ptr(u), ctypes.byref(v), 1))
     return v.value
 
 
