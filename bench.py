@@ -120,6 +120,11 @@ def executed_flops_from_profiles(kernel, workload, precision):
     return rec.get("flops_per_launch") if rec else None
 
 
+def _log(msg):
+    """Progress on stderr (the JSON line is the only output on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def _timed(sim, steps, measure_profile):
     import torch
 
@@ -273,12 +278,15 @@ def run_gpu(args, precision, measure_profile=True):
             ds.add(sim.ctx, sim.u)
         if args.verbose and (i + 1) % 1000 == 0:
             print(f"warm-up step {i + 1}: t={sim.t:.4f} rms Mach {sim.rms_mach():.3f}", file=sys.stderr, flush=True)
+    _log(f"warm-up done: {args.warmup} steps, t = {sim.t:.4g}, rms Mach {sim.rms_mach():.3f}")
     u0 = sim.u.clone()
     drive0 = sim.driving_state() if drv is not None else None
     wall, prof, retries, dt_min = _timed(sim, args.steps, measure_profile)
     main = _summary(args, sim, precision, wall, prof, retries, dt_min)
+    _log(f"timed {args.steps} steps ({precision}): {main['ms_per_step']:.3f} ms per step")
     if not args.no_stats:
         main["statistics"] = _statistics(sim)
+        _log("flow statistics done")
     compare = None
     if not args.no_compare:
         compare = {}
@@ -309,6 +317,7 @@ def run_gpu(args, precision, measure_profile=True):
                     rec["judge_every"] = sim2.judge_every
                 compare[name] = rec
                 sim2.ctx.close()
+                _log(f"leg {name}: {rec['ms_per_step']:.3f} ms per step")
             except Exception as exc:  # report, do not hide the main measurement
                 compare[name] = {"error": str(exc)}
     sim.ctx.close()
@@ -438,8 +447,11 @@ def main():
     turbulent_start = args.workload not in UNDRIVEN and (
         args.start == "turbulent" or (args.start == "auto" and args.warmup < spinup))
     args.start_state = start_state(args.workload, args.seed) if turbulent_start else None
+    _log(f"workload {args.workload}, {precision}, start {'seeded turbulence-like state' if turbulent_start else 'rest'}")
     main_run, compare = run_gpu(args, precision)
     cpu = None if args.no_cpu else run_cpu_baseline(args)
+    if cpu:
+        _log(f"CPU oracle: {cpu['value']:.3e} DOF-updates/s on {cpu['cores']} threads")
     rec = {
         "metric": METRIC,
         "value": main_run["value"],

@@ -11,7 +11,7 @@
 constexpr int MLP_PART_ROWS = 1024;
 
 struct dg_offsets {
-    size_t stA, stB, stC, L, vh0, vh1, apts, nu, fb, feat, lab, mlp, part, spart, scal, iflags;
+    size_t stA, stB, stC, L, vh0, vh1, ftab, nu, fb, feat, lab, mlp, part, spart, scal, iflags;
 };
 
 struct dg_ctx {
@@ -26,7 +26,7 @@ struct dg_ctx {
     double *modes_dev = nullptr;   // driving mode table [64][9]
     double modes_host[64 * 9] = {};
     int nmodes = 0;
-    bool modes_sep = false;        // integer wavevectors with components in [-2, 2]
+    bool modes_sep = false;        // every n_x an integer in [-2, 2] (pencil form of the driving field)
     bool forcing_dirty = false;
     // pinned staging slots of the asynchronous table uploads, each with the event of its copy
     static constexpr int MODE_SLOTS = 4;

@@ -11,6 +11,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dg_basis.hpp"
 
 namespace dg {
@@ -26,6 +28,23 @@ __device__ __forceinline__ int xcd_remap(int b, int n)
     const int per = n >> 3;
     if (b >= (per << 3)) return b;
     return (b & 7) * per + (b >> 3);
+}
+
+// Order in which the right-hand-side kernels sweep their cell blocks: in tiles of zt
+// z-planes, the planes of a tile interleaved block by block (blocks per plane bpp; identity
+// when zt < 2 or blocks straddle planes).  A block's z-neighbour lines are then swept a few
+// blocks before or after it, while they are still in the XCD's L2, instead of a whole plane
+// of blocks later.  The partial sums stay indexed by the cell block, so every reduction is
+// unchanged.
+__device__ __forceinline__ int plane_tiled(int b, int bpp, int nplanes, int zt)
+{
+    if (zt < 2 || bpp <= 0) return b;
+    const int per_tile = bpp * zt;
+    const int t = b / per_tile;
+    const int p0 = t * zt;
+    const int tl = min(zt, nplanes - p0);
+    const int r = b - t * per_tile;
+    return (p0 + r % tl) * bpp + r / tl;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -204,7 +223,9 @@ struct RhsArgs {
     const void *vh;         // [3][NB][nc] projected velocity of u
     void *out;              // [4][NB][nc] right-hand side
     const void *tab;        // quadrature tables (TabLayout)
-    const void *apts;       // [3][NQ][nc] driving acceleration at the volume points
+    const void *ftab;       // driving field in pencil form (PencilLayout), element type T
+    const double *modes;    // driving-mode table [nmodes][9] (direct evaluation of other tables)
+    int nmodes;
     const void *nu;         // [nc] learned viscosity
     const int *fb;          // [nc] fallback flags
     double *part;           // [nblocks][4] driving partial sums (mode-0 source, mass)
@@ -219,6 +240,7 @@ struct RhsArgs {
     int flags;
     double h, cs, alpha, beta, dt;
     const double *dt_dev;   // the time step in device memory (a stage launched ahead), or NULL: dt
+    int bpp, zt;            // block sweep order (plane_tiled): blocks per z-plane, planes per tile
 };
 
 // time-step bound inputs shared by the projection and stage kernels
@@ -559,6 +581,79 @@ __device__ __forceinline__ void face_shared(const T *share, int slot, ctab<T> *t
     }
 }
 
+// ------------------------------------------------------------ driving field
+// The driving acceleration a(x) = sum_m Re[a_m exp(2 pi i n_m . x)] (Sec. 4.2) at the volume
+// points of a cell.  For tables whose wavevectors have integer x components n_x in [-2, 2]
+// (the driving shell 1 <= |n| <= 2), a term with n_x < 0 equals the real part of its
+// conjugate (-n, conj a_m), so with X = exp(2 pi i x)
+//     a_d(x, y, z) = G0_d(y, z) + Re[G1_d(y, z) X] + Re[G2_d(y, z) X^2],
+// where G_nd(y, z) sums a_m,d exp(2 pi i (n_y y + n_z z)) over the modes with n_x = n.  The G
+// depend only on the cell's y-z pencil (j, l) and the point's (t_y, t_z): the pencil table
+// holds them (about 1 KB per pencil in FP64 at degree 2, built once per table update), and
+// X = P E_t with P = exp(2 pi i (i + 1/2) h) per cell and E_t = exp(pi i xi_t h) from the
+// table header.  The 64 cells of a wave usually share one pencil: their G are then read with
+// scalar loads.  Other tables are evaluated mode by mode at every point (k_rhs's direct form).
+template <int K>
+struct PencilLayout {
+    static constexpr int N1 = K + 1;
+    static constexpr int HDR = 16;                  // (cos, sin)(pi xi_t h) for t < N1, padded
+    static constexpr int ENT = 16;                  // per (t_y, t_z): 3 x (G0, Re G1, Im G1, Re G2, Im G2), padded
+    static constexpr int STRIDE = N1 * N1 * ENT;    // reals per pencil
+};
+
+// a at volume point q (q = t_x + N1 (t_y + N1 t_z)) from the pencil table: g = this pencil's
+// block, (pr, pi) = the cell's phase P
+template <typename T, int K>
+__device__ __forceinline__ void pencil_accel(ctab<T> *ft, ctab<T> *g, int q, T pr, T pim, T (&acc)[3])
+{
+    using PL = PencilLayout<K>;
+    const int tx = q % PL::N1, tt = q / PL::N1;
+    const T er = ft[2 * tx], ei = ft[2 * tx + 1];
+    const T xr = pr * er - pim * ei;
+    const T xi = pr * ei + pim * er;
+    const T x2r = xr * xr - xi * xi;
+    const T x2i = T(2) * xr * xi;
+    ctab<T> *e = g + tt * PL::ENT;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        acc[d] = e[5 * d] + e[5 * d + 1] * xr - e[5 * d + 2] * xi + e[5 * d + 3] * x2r - e[5 * d + 4] * x2i;
+}
+
+// a at the point with reference coordinates xi of cell (i, j, l), mode by mode (any table)
+template <typename T>
+__device__ __forceinline__ void direct_accel(const double *modes, int nmodes, const int (&ijk)[3], T xq, T yq, T zq,
+                                             double h, T (&acc)[3])
+{
+    const double x = (ijk[0] + 0.5 + 0.5 * (double)xq) * h;
+    const double y = (ijk[1] + 0.5 + 0.5 * (double)yq) * h;
+    const double z = (ijk[2] + 0.5 + 0.5 * (double)zq) * h;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int m = 0; m < nmodes; ++m) {
+        const double *e = modes + 9 * m;
+        double sp, cp;
+        sincospi(2.0 * (e[0] * x + e[1] * y + e[2] * z), &sp, &cp);
+        ax += e[3] * cp - e[4] * sp;
+        ay += e[5] * cp - e[6] * sp;
+        az += e[7] * cp - e[8] * sp;
+    }
+    acc[0] = (T)ax;
+    acc[1] = (T)ay;
+    acc[2] = (T)az;
+}
+
+// the cell's x phase P = exp(2 pi i (i + 1/2) h)
+template <typename T>
+__device__ __forceinline__ void cell_phase(int i, double h, T &pr, T &pim)
+{
+    double sp, cp;
+    sincospi(2.0 * (i + 0.5) * h, &sp, &cp);
+    pr = (T)cp;
+    pim = (T)sp;
+}
+
+// Driving field forms of the right-hand-side kernels' volume loop
+enum : int { FM_LANE = 0, FM_UNIFORM = 1, FM_DIRECT = 2 };
+
 // ------------------------------------------------------------------ RHS kernel
 // dw/dt = (1/(4h)) [ sum_q w_q grad_xi(phi) . F(q) - sum_faces +- sum_r w_r phi F*(r) ]
 //         + (1/8) sum_q w_q phi rho a (Sec. 2.2 weight evolution; Sec. 3.1; Sec. 4.2)
@@ -570,7 +665,7 @@ __device__ __forceinline__ void face_shared(const T *share, int slot, ctab<T> *t
 template <typename T, int K>
 constexpr int rhs_waves() { return sizeof(T) == 8 ? (K <= 2 ? 2 : 1) : (K <= 2 ? 4 : 2); }
 
-template <typename T, int K>
+template <typename T, int K, bool FDIRECT>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K>()))) k_rhs(RhsArgs a)
 {
     using S = Shape<K>;
@@ -581,7 +676,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     __shared__ T fsh[S::NF * 4 * BLOCK];        // point fluxes of the low faces, [r][v][thread]
     ctab<T> *tab = as_tab<T>(a.tab);
     const int nc = a.g.nc;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = plane_tiled(xcd_remap(blockIdx.x, gridDim.x), a.bpp, a.g.nz, a.zt);
     const int c0 = blk * BLOCK + threadIdx.x;
     const bool active = c0 < nc;
     const int c = active ? c0 : 0;
@@ -637,83 +732,98 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
 #pragma unroll
         for (int l = 0; l < NB; ++l) L[v][l] = T(0);
     T fs0 = T(0), fs1 = T(0), fs2 = T(0);
-    const Field<T, 3> AP(a.apts, S::NQ, nc);
     const T half_h = (T)(0.5 * a.h);
+    // driving field: the cell's pencil (j, l) and x phase (pencil form) or indices (direct form)
+    const int pencil = c / a.g.nx;
+    const int cijk[3] = {c % a.g.nx, pencil % a.g.ny, pencil / a.g.ny};
+    T pr = T(0), pim = T(0);
+    if (force && !FDIRECT) cell_phase<T>(cijk[0], a.h, pr, pim);
+    ctab<T> *ft = as_tab<T>(a.ftab);
 
     // ---- volume integral
-    // the driving acceleration of the next point is requested one iteration ahead, so
-    // its memory latency overlaps the arithmetic of the current point
-    T an0 = T(0), an1 = T(0), an2 = T(0);
-    if (force) { an0 = AP.get(0, 0, bo); an1 = AP.get(1, 0, bo); an2 = AP.get(2, 0, bo); }
+    auto volume = [&](auto form, int pen) {
+        constexpr int FM = decltype(form)::value;
+        ctab<T> *g = ft + PencilLayout<K>::HDR + (size_t)pen * PencilLayout<K>::STRIDE;
 #pragma unroll 1
-    for (int q = 0; q < S::NQ; ++q) {
-        const T ac0 = an0, ac1 = an1, ac2 = an2;
-        if (force && q + 1 < S::NQ) {
-            an0 = AP.get(0, q + 1, bo);
-            an1 = AP.get(1, q + 1, bo);
-            an2 = AP.get(2, q + 1, bo);
-        }
-        ctab<T> *ph = tab + TL::VPHI + q * NB;
-        ctab<T> *dph = tab + TL::VDPHI + q * 3 * ND;
-        const T wq = tab[TL::VW + q];
-        T rho = T(0), m[3] = {T(0), T(0), T(0)};
-#pragma unroll
-        for (int l = 0; l < NB; ++l) {
-            const T p = ph[l];
-            rho += W[0][l] * p;
-            m[0] += W[1][l] * p;
-            m[1] += W[2][l] * p;
-            m[2] += W[3][l] * p;
-        }
-        T pi = T(0);
-        if (av) {
-            T div = T(0);
-#pragma unroll
-            for (int m = 0; m < NDIV; ++m) div += Dv[m] * ph[m];
-            div *= two_h;
-            const T pv = vnr_pi<T>(rho, div, hp, alpha, beta, cs, inv_dt);
-            // learned sensor: the cell's bulk viscosity nu in place of the vNR one,
-            // Pi = rho nu s at compressed points, with the Pi_max cap of the point
-            const T sq = -div;
-            T pl = fmin(rho * nu * sq, T(0.5) * rho * hp * hp * sq * inv_dt);
-            pl = (sq > T(0) && nu > T(0)) ? pl : T(0);
-            pi = learned ? pl : pv;
-        }
-        const T ir = rcp(rho);
-        const T pw = (cs2 * rho + pi) * wq;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T md = m[d] * wq;
-            const T mdr = md * ir;
-            T F[4];
-            F[0] = md;
-            F[1] = mdr * m[0];
-            F[2] = mdr * m[1];
-            F[3] = mdr * m[2];
-            F[1 + d] += pw;
-#pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                if (M.dj[d][l] < 0) continue;
-                const T dp = dph[d * ND + M.dj[d][l]];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) L[v][l] += dp * F[v];
-            }
-        }
-        if (force) {
-            const T rw = rho * wq;
-            const T s0 = rw * ac0;
-            const T s1 = rw * ac1;
-            const T s2 = rw * ac2;
-            fs0 += s0; fs1 += s1; fs2 += s2;
-            const T t0 = s0 * half_h, t1 = s1 * half_h, t2 = s2 * half_h;
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<T> *ph = tab + TL::VPHI + q * NB;
+            ctab<T> *dph = tab + TL::VDPHI + q * 3 * ND;
+            const T wq = tab[TL::VW + q];
+            T rho = T(0), m[3] = {T(0), T(0), T(0)};
 #pragma unroll
             for (int l = 0; l < NB; ++l) {
                 const T p = ph[l];
-                L[1][l] += t0 * p;
-                L[2][l] += t1 * p;
-                L[3][l] += t2 * p;
+                rho += W[0][l] * p;
+                m[0] += W[1][l] * p;
+                m[1] += W[2][l] * p;
+                m[2] += W[3][l] * p;
+            }
+            T pi = T(0);
+            if (av) {
+                T div = T(0);
+#pragma unroll
+                for (int mm = 0; mm < NDIV; ++mm) div += Dv[mm] * ph[mm];
+                div *= two_h;
+                const T pv = vnr_pi<T>(rho, div, hp, alpha, beta, cs, inv_dt);
+                // learned sensor: the cell's bulk viscosity nu in place of the vNR one,
+                // Pi = rho nu s at compressed points, with the Pi_max cap of the point
+                const T sq = -div;
+                T pl = fmin(rho * nu * sq, T(0.5) * rho * hp * hp * sq * inv_dt);
+                pl = (sq > T(0) && nu > T(0)) ? pl : T(0);
+                pi = learned ? pl : pv;
+            }
+            const T ir = rcp(rho);
+            const T pw = (cs2 * rho + pi) * wq;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T md = m[d] * wq;
+                const T mdr = md * ir;
+                T F[4];
+                F[0] = md;
+                F[1] = mdr * m[0];
+                F[2] = mdr * m[1];
+                F[3] = mdr * m[2];
+                F[1 + d] += pw;
+#pragma unroll
+                for (int l = 0; l < NB; ++l) {
+                    if (M.dj[d][l] < 0) continue;
+                    const T dp = dph[d * ND + M.dj[d][l]];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) L[v][l] += dp * F[v];
+                }
+            }
+            if (force) {
+                T ac[3];
+                if constexpr (FM == FM_DIRECT)
+                    direct_accel<T>(a.modes, a.nmodes, cijk, tab[TL::VXI + 3 * q], tab[TL::VXI + 3 * q + 1],
+                                    tab[TL::VXI + 3 * q + 2], a.h, ac);
+                else
+                    pencil_accel<T, K>(ft, g, q, pr, pim, ac);
+                const T rw = rho * wq;
+                const T s0 = rw * ac[0];
+                const T s1 = rw * ac[1];
+                const T s2 = rw * ac[2];
+                fs0 += s0; fs1 += s1; fs2 += s2;
+                const T t0 = s0 * half_h, t1 = s1 * half_h, t2 = s2 * half_h;
+#pragma unroll
+                for (int l = 0; l < NB; ++l) {
+                    const T p = ph[l];
+                    L[1][l] += t0 * p;
+                    L[2][l] += t1 * p;
+                    L[3][l] += t2 * p;
+                }
             }
         }
+    };
+    if constexpr (FDIRECT) {
+        volume(std::integral_constant<int, FM_DIRECT>{}, 0);
+    } else {
+        // the wave's cells share one pencil (x lines of at least 64 cells): scalar table loads
+        const int p0 = __shfl(pencil, 0, 64);
+        if (force && __all(!active || pencil == p0))
+            volume(std::integral_constant<int, FM_UNIFORM>{}, __builtin_amdgcn_readfirstlane(p0));
+        else
+            volume(std::integral_constant<int, FM_LANE>{}, pencil);
     }
     const T mass0 = W[0][0];
 
@@ -907,7 +1017,7 @@ __device__ __forceinline__ void face_shared_pair(const double *share, int slot, 
 template <int K>
 constexpr int rhs_pair_waves() { return K <= 2 ? 3 : 2; }   // at K = 3: 256 VGPRs, 14 of them spilled
 
-template <int K>
+template <int K, bool FDIRECT>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_pair_waves<K>()))) k_rhs_pair(RhsArgs a)
 {
     using S = Shape<K>;
@@ -920,7 +1030,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     ctab<double> *tab = as_tab<double>(a.tab);
     const int nc = a.g.nc;
     const size_t ncs = (size_t)nc;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int blk = plane_tiled(xcd_remap(blockIdx.x, gridDim.x), a.bpp, a.g.nz, a.zt);
     const int h = threadIdx.x & 1;                 // variables 2h and 2h+1
     const int cb = threadIdx.x >> 1;
     const int c0 = blk * CB + cb;
@@ -979,76 +1089,95 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int l = 0; l < NB; ++l) L[i][l] = 0.0;
-    double fs0 = 0.0, fs1 = 0.0, fs2 = 0.0;
-    const Field<double, 3> AP(a.apts, S::NQ, nc);
+    // driving source sums of the lane's own momentum components: lane 0 the x one (fsa),
+    // lane 1 the y and z ones (fsa, fsb)
+    double fsa = 0.0, fsb = 0.0;
     const double half_h = 0.5 * a.h;
+    const int pencil = c / a.g.nx;
+    const int cijk[3] = {c % a.g.nx, pencil % a.g.ny, pencil / a.g.ny};
+    double pr = 0.0, pim = 0.0;
+    if (force && !FDIRECT) cell_phase<double>(cijk[0], a.h, pr, pim);
+    ctab<double> *ft = as_tab<double>(a.ftab);
 
-    // ---- volume integral (the driving acceleration of the next point requested ahead)
-    double an0 = 0.0, an1 = 0.0, an2 = 0.0;
-    if (force) { an0 = AP.get(0, 0, bo); an1 = AP.get(1, 0, bo); an2 = AP.get(2, 0, bo); }
+    // ---- volume integral
+    auto volume = [&](auto form, int pen) {
+        constexpr int FM = decltype(form)::value;
+        ctab<double> *g = ft + PencilLayout<K>::HDR + (size_t)pen * PencilLayout<K>::STRIDE;
 #pragma unroll 1
-    for (int q = 0; q < S::NQ; ++q) {
-        const double ac0 = an0, ac1 = an1, ac2 = an2;
-        if (force && q + 1 < S::NQ) {
-            an0 = AP.get(0, q + 1, bo);
-            an1 = AP.get(1, q + 1, bo);
-            an2 = AP.get(2, q + 1, bo);
-        }
-        ctab<double> *ph = tab + TL::VPHI + q * NB;
-        ctab<double> *dph = tab + TL::VDPHI + q * 3 * ND;
-        const double wq = tab[TL::VW + q];
-        double x0 = 0.0, x1 = 0.0;
-#pragma unroll
-        for (int l = 0; l < NB; ++l) {
-            x0 += W[0][l] * ph[l];
-            x1 += W[1][l] * ph[l];
-        }
-        double xv[4];
-        pair_assemble(h, x0, x1, pair_swap(x0), pair_swap(x1), xv);
-        const double rho = xv[0];
-        const double m[3] = {xv[1], xv[2], xv[3]};
-        double pi = 0.0;
-        if (av) {
-            double div = 0.0;
-#pragma unroll
-            for (int mm = 0; mm < NDIV; ++mm) div += Dv[mm] * ph[mm];
-            div *= two_h;
-            const double pv = vnr_pi<double>(rho, div, hp, alpha, beta, cs, inv_dt);
-            const double sq = -div;
-            double pl = fmin(rho * nu * sq, 0.5 * rho * hp * hp * sq * inv_dt);
-            pl = (sq > 0.0 && nu > 0.0) ? pl : 0.0;
-            pi = learned ? pl : pv;
-        }
-        const double ir = rcp(rho);
-        const double pw = (cs2 * rho + pi) * wq;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const double md = m[d] * wq;
-            const double mdr = md * ir;
-            // lane 0: (rho, m_x) fluxes; lane 1: (m_y, m_z)
-            const double fa = h ? mdr * m[1] + (d == 1 ? pw : 0.0) : md;
-            const double fb = h ? mdr * m[2] + (d == 2 ? pw : 0.0) : mdr * m[0] + (d == 0 ? pw : 0.0);
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<double> *ph = tab + TL::VPHI + q * NB;
+            ctab<double> *dph = tab + TL::VDPHI + q * 3 * ND;
+            const double wq = tab[TL::VW + q];
+            double x0 = 0.0, x1 = 0.0;
 #pragma unroll
             for (int l = 0; l < NB; ++l) {
-                if (M.dj[d][l] < 0) continue;
-                const double dp = dph[d * ND + M.dj[d][l]];
-                L[0][l] += dp * fa;
-                L[1][l] += dp * fb;
+                x0 += W[0][l] * ph[l];
+                x1 += W[1][l] * ph[l];
             }
-        }
-        if (force) {
-            const double rw = rho * wq;
-            const double s0 = rw * ac0, s1 = rw * ac1, s2 = rw * ac2;
-            fs0 += s0; fs1 += s1; fs2 += s2;
-            const double ta = h ? s1 * half_h : 0.0;
-            const double tb = h ? s2 * half_h : s0 * half_h;
+            double xv[4];
+            pair_assemble(h, x0, x1, pair_swap(x0), pair_swap(x1), xv);
+            const double rho = xv[0];
+            const double m[3] = {xv[1], xv[2], xv[3]};
+            double pi = 0.0;
+            if (av) {
+                double div = 0.0;
 #pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                const double p = ph[l];
-                L[0][l] += ta * p;
-                L[1][l] += tb * p;
+                for (int mm = 0; mm < NDIV; ++mm) div += Dv[mm] * ph[mm];
+                div *= two_h;
+                const double pv = vnr_pi<double>(rho, div, hp, alpha, beta, cs, inv_dt);
+                const double sq = -div;
+                double pl = fmin(rho * nu * sq, 0.5 * rho * hp * hp * sq * inv_dt);
+                pl = (sq > 0.0 && nu > 0.0) ? pl : 0.0;
+                pi = learned ? pl : pv;
+            }
+            const double ir = rcp(rho);
+            const double pw = (cs2 * rho + pi) * wq;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double md = m[d] * wq;
+                const double mdr = md * ir;
+                // lane 0: (rho, m_x) fluxes; lane 1: (m_y, m_z)
+                const double fa = h ? mdr * m[1] + (d == 1 ? pw : 0.0) : md;
+                const double fb = h ? mdr * m[2] + (d == 2 ? pw : 0.0) : mdr * m[0] + (d == 0 ? pw : 0.0);
+#pragma unroll
+                for (int l = 0; l < NB; ++l) {
+                    if (M.dj[d][l] < 0) continue;
+                    const double dp = dph[d * ND + M.dj[d][l]];
+                    L[0][l] += dp * fa;
+                    L[1][l] += dp * fb;
+                }
+            }
+            if (force) {
+                double ac[3];
+                if constexpr (FM == FM_DIRECT)
+                    direct_accel<double>(a.modes, a.nmodes, cijk, tab[TL::VXI + 3 * q], tab[TL::VXI + 3 * q + 1],
+                                         tab[TL::VXI + 3 * q + 2], a.h, ac);
+                else
+                    pencil_accel<double, K>(ft, g, q, pr, pim, ac);
+                const double rw = rho * wq;
+                const double sa = rw * (h ? ac[1] : ac[0]);
+                const double sb = h ? rw * ac[2] : 0.0;
+                fsa += sa;
+                fsb += sb;
+                const double ta = h ? sa * half_h : 0.0;
+                const double tb = h ? sb * half_h : sa * half_h;
+#pragma unroll
+                for (int l = 0; l < NB; ++l) {
+                    const double p = ph[l];
+                    L[0][l] += ta * p;
+                    L[1][l] += tb * p;
+                }
             }
         }
+    };
+    if constexpr (FDIRECT) {
+        volume(std::integral_constant<int, FM_DIRECT>{}, 0);
+    } else {
+        const int p0 = __shfl(pencil, 0, 64);
+        if (force && __all(!active || pencil == p0))
+            volume(std::integral_constant<int, FM_UNIFORM>{}, __builtin_amdgcn_readfirstlane(p0));
+        else
+            volume(std::integral_constant<int, FM_LANE>{}, pencil);
     }
     const double mass0 = W[0][0];                   // cell mean density (lane 0)
 
@@ -1089,9 +1218,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     if (force && a.part) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         if (active) {
-            acc[0] = h ? 0.0 : 0.125 * fs0;
-            acc[1] = h ? 0.125 * fs1 : 0.0;
-            acc[2] = h ? 0.125 * fs2 : 0.0;
+            acc[0] = h ? 0.0 : 0.125 * fsa;
+            acc[1] = h ? 0.125 * fsa : 0.0;
+            acc[2] = h ? 0.125 * fsb : 0.0;
             acc[3] = h ? 0.0 : mass0;
         }
         block_sum<4>(acc, lds);
@@ -1379,124 +1508,58 @@ __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, co
     project_and_bounds<T, K>(W, tab, vh_, nc, bo, c, active, pa, part, blk, lds);
 }
 
-// driving acceleration a(x) = sum_m Re[a_m exp(2 pi i n_m.x)] at every volume point (Sec. 4.2)
+// Pencil table of the driving field (see PencilLayout): one thread per pencil and (t_y, t_z)
+// point pair; the header (thread 0) holds (cos, sin)(pi xi_t h).  Modes with n_x < 0 enter as
+// their conjugates; their y-z phase is evaluated directly, so n_y and n_z may be any reals.
+// Only tables whose every n_x is an integer in [-2, 2] take this form.
 template <typename T, int K>
-__global__ void __launch_bounds__(BLOCK) k_forcing_points(void *apts_, const double *modes, int nmodes,
-                                                          const void *tab_, Mesh g, double h)
+__global__ void __launch_bounds__(BLOCK) k_forcing_pencils(void *ft_, const double *modes, int nmodes,
+                                                           const void *tab_, Mesh g, double h)
 {
-    using S = Shape<K>;
     using TL = TabLayout<K>;
-    const int nc = g.nc;
-    const int c = blockIdx.x * BLOCK + threadIdx.x;
-    if (c >= nc) return;
+    using PL = PencilLayout<K>;
+    constexpr int N1 = PL::N1;
     ctab<T> *tab = as_tab<T>(tab_);
-    const int i = c % g.nx, r = c / g.nx, j = r % g.ny, l = r / g.ny;
-    T *ap = (T *)apts_;
-    for (int q = 0; q < S::NQ; ++q) {
-        const double x = (i + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + 0]) * h;
-        const double y = (j + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + 1]) * h;
-        const double z = (l + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + 2]) * h;
-        double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int m = 0; m < nmodes; ++m) {
-            const double *e = modes + 9 * m;
+    T *ft = (T *)ft_;
+    const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    const long long nt = (long long)g.ny * g.nz * N1 * N1;
+    if (t == 0)
+        for (int k = 0; k < N1; ++k) {
             double sp, cp;
-            sincospi(2.0 * (e[0] * x + e[1] * y + e[2] * z), &sp, &cp);
-            ax += e[3] * cp - e[4] * sp;
-            ay += e[5] * cp - e[6] * sp;
-            az += e[7] * cp - e[8] * sp;
+            sincospi((double)tab[TL::VXI + 3 * k] * h, &sp, &cp);      // xi of the 1D point k
+            ft[2 * k] = (T)cp;
+            ft[2 * k + 1] = (T)sp;
         }
-        ap[(0 * S::NQ + q) * (size_t)nc + c] = (T)ax;
-        ap[(1 * S::NQ + q) * (size_t)nc + c] = (T)ay;
-        ap[(2 * S::NQ + q) * (size_t)nc + c] = (T)az;
+    if (t >= nt) return;
+    const int pen = (int)(t / (N1 * N1)), tt = (int)(t % (N1 * N1));
+    const int j = pen % g.ny, l = pen / g.ny;
+    const int ty = tt % N1, tz = tt / N1;
+    const double y = (j + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * ty]) * h;
+    const double z = (l + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * tz]) * h;
+    double G[3][5] = {};
+    for (int m = 0; m < nmodes; ++m) {
+        const double *e = modes + 9 * m;
+        const double sg = e[0] < 0.0 ? -1.0 : 1.0;       // conjugate term for n_x < 0
+        const int nx = (int)(sg * e[0]);
+        double sp, cp;
+        sincospi(2.0 * sg * (e[1] * y + e[2] * z), &sp, &cp);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const double ar = e[3 + 2 * d], ai = sg * e[4 + 2 * d];
+            const double cr = ar * cp - ai * sp, ci = ar * sp + ai * cp;
+            G[d][0] += nx == 0 ? cr : 0.0;
+            G[d][1] += nx == 1 ? cr : 0.0;
+            G[d][2] += nx == 1 ? ci : 0.0;
+            G[d][3] += nx == 2 ? cr : 0.0;
+            G[d][4] += nx == 2 ? ci : 0.0;
+        }
     }
-}
-
-// The same field for tables whose wavevectors have integer components of magnitude at most
-// 2 (the driving shell 1 <= |n| <= 2).  The volume points form a tensor product, so
-// exp(2 pi i n.x) = X^nx Y^ny Z^nz with X = exp(2 pi i x) at the N1 coordinates of each axis:
-// 3 N1 sine-cosine pairs per cell instead of one per point and mode.  Per z layer and mode
-// the z factor and then each x factor are folded into the mode's coefficients, so a point
-// costs two multiply-adds per component and mode.  Modes are summed in table order.
-template <typename T, int K>
-__global__ void __launch_bounds__(BLOCK) k_forcing_sep(void *apts_, const double *modes, int nmodes,
-                                                       const void *tab_, Mesh g, double h)
-{
-    using S = Shape<K>;
-    using TL = TabLayout<K>;
-    constexpr int N1 = S::N1;
-    const int nc = g.nc;
-    const int c = blockIdx.x * BLOCK + threadIdx.x;
-    if (c >= nc) return;
-    ctab<T> *tab = as_tab<T>(tab_);
-    const int cell[3] = {c % g.nx, (c / g.nx) % g.ny, c / g.nx / g.ny};
-    // fr/fi[a][t][p]: real and imaginary parts of X_a(t)^(p+1), p = 0, 1
-    double fr[3][N1][2], fi[3][N1][2];
+    T *o = ft + PL::HDR + (size_t)pen * PL::STRIDE + tt * PL::ENT;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+    for (int d = 0; d < 3; ++d)
 #pragma unroll
-        for (int t = 0; t < N1; ++t) {
-            const int q = a == 0 ? t : (a == 1 ? N1 * t : N1 * N1 * t);     // point (t,0,0), (0,t,0), (0,0,t)
-            const double x = (cell[a] + 0.5 + 0.5 * (double)tab[TL::VXI + 3 * q + a]) * h;
-            double sn, cs;
-            sincospi(2.0 * x, &sn, &cs);
-            fr[a][t][0] = cs;
-            fi[a][t][0] = sn;
-            fr[a][t][1] = cs * cs - sn * sn;
-            fi[a][t][1] = 2.0 * cs * sn;
-        }
-    // X_a(t)^n for an integer n in [-2, 2] (negative powers are conjugates)
-    auto power = [&](int a, int t, int n, double &re, double &im) {
-        const int m = n < 0 ? -n : n;
-        re = m == 2 ? fr[a][t][1] : (m == 1 ? fr[a][t][0] : 1.0);
-        im = m == 2 ? fi[a][t][1] : (m == 1 ? fi[a][t][0] : 0.0);
-        if (n < 0) im = -im;
-    };
-    T *ap = (T *)apts_;
-#pragma unroll
-    for (int tz = 0; tz < N1; ++tz) {
-        double acc[3][N1 * N1];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int p = 0; p < N1 * N1; ++p) acc[k][p] = 0.0;
-#pragma unroll 1
-        for (int m = 0; m < nmodes; ++m) {
-            const double *e = modes + 9 * m;
-            const int nx = (int)e[0], ny = (int)e[1], nz = (int)e[2];
-            double zr, zi;
-            power(2, tz, nz, zr, zi);
-            double ar[3], ai[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double re = e[3 + 2 * k], im = e[4 + 2 * k];
-                ar[k] = re * zr - im * zi;
-                ai[k] = re * zi + im * zr;
-            }
-            double yr[N1], yi[N1];
-#pragma unroll
-            for (int ty = 0; ty < N1; ++ty) power(1, ty, ny, yr[ty], yi[ty]);
-#pragma unroll
-            for (int tx = 0; tx < N1; ++tx) {
-                double xr, xi;
-                power(0, tx, nx, xr, xi);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    const double br = ar[k] * xr - ai[k] * xi;
-                    const double bi = ar[k] * xi + ai[k] * xr;
-#pragma unroll
-                    for (int ty = 0; ty < N1; ++ty) acc[k][tx + N1 * ty] += br * yr[ty] - bi * yi[ty];
-                }
-            }
-        }
-#pragma unroll
-        for (int ty = 0; ty < N1; ++ty)
-#pragma unroll
-            for (int tx = 0; tx < N1; ++tx) {
-                const int q = tx + N1 * (ty + N1 * tz);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) ap[(k * S::NQ + q) * (size_t)nc + c] = (T)acc[k][tx + N1 * ty];
-            }
-    }
+        for (int k = 0; k < 5; ++k) o[5 * d + k] = (T)G[d][k];
+    o[15] = T(0);
 }
 
 // per-block sums of the cell means (conservation totals, Sec. 2.2: w_0 is the mean)

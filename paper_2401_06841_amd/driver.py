@@ -92,7 +92,8 @@ class Simulation:
         to self.u by other means than torch in-place operations, which are detected)."""
         self._dt_next = None
 
-    def step(self):
+    def step(self, dt_cap: float | None = None):
+        """One step; dt_cap (optional) shortens the time step, e.g. to land on an output time."""
         reuse = self._dt_next is not None and self._u_version == self.u._version
         if self.learned:
             # the network's viscosity of u^n serves the time step and the stages: the fused
@@ -104,6 +105,8 @@ class Simulation:
             elif not reuse:
                 dg.dg_sensor_infer(self.ctx, self.u)
         dt = self._dt_next if (reuse and self._dt_next is not None) else dg.dg_dt_max(self.ctx, self.u)
+        if dt_cap is not None:
+            dt = min(dt, dt_cap)
         if not (dt > 0.0 and np.isfinite(dt)):
             raise RuntimeError(f"invalid time step {dt} at step {self.nstep}")
         if self.driving is not None:

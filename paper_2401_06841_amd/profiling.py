@@ -97,7 +97,7 @@ def counters(d: str):
         res[k] = {"dispatches": n}
         for c, v in cs.items():
             res[k][c] = v / n
-        res[k]["resources"] = names[next(iter(disps[k]))] if disps[k] else {}
+        res[k]["resources"] = names[(k, next(iter(disps[k])))] if disps[k] else {}
     return res
 
 

@@ -92,3 +92,15 @@ def test_retry_halves_the_step_and_drops_reuse(monkeypatch):
     reuses = [c[1] for c in stub.calls]
     assert dts == [0.02, 0.02, 0.01] and reuses == [False, True, False]
     assert sim.retries == 1 and sim.t == pytest.approx(0.03)
+
+
+def test_time_step_cap_lands_on_an_output_time(monkeypatch):
+    """step(dt_cap) takes the smaller of the stable step and the cap, so a run can stop
+    exactly at an output time."""
+    stub = _Stub(dt_next=0.3)
+    sim = _sim(monkeypatch, stub)
+    t_end = 1.0
+    while sim.t < t_end * (1 - 1e-12):
+        sim.step(dt_cap=t_end - sim.t)
+    assert [c[0] for c in stub.calls] == pytest.approx([0.3, 0.3, 0.3, 0.1])
+    assert sim.t == pytest.approx(1.0, abs=1e-15)

@@ -5,9 +5,13 @@ benchmark times; the oracle computes a seeded sample of cells one by one (with t
 periodic corner cells always included).  Cases:
   * 128^3, degree 3, FP32 and FP64, Mach-10-like state with viscosity, projection, driving;
   * 128^3, degree 2, FP32, learned sensor with prescribed per-cell viscosity and fallback;
-  * 256^3, degree 2, FP32 and FP64, Mach-10-like state with viscosity, projection, driving.
-The mean-free driving correction needs a sum over the whole mesh (too slow for the oracle
-at these sizes); it is covered at 64^3 in the parity tests, so the driving here is plain.
+  * 256^3, degree 2, FP32 and FP64, Mach-10-like state with viscosity, projection, driving;
+  * 256^3, degree 3, FP64 (the driving field is evaluated inside the right-hand side from a
+    table of about 1 KB per y-z pencil, so no per-point field of 4 x 64 x 16.8M values is
+    stored and every variable block stays below the 4 GiB of a buffer descriptor).
+The mean-free driving correction needs a sum over the whole mesh (too slow for the oracle's
+one-by-one cells at these sizes); whole-mesh steps with it are compared in
+test_gpu_step_paths.py (up to 128^3), so the driving here is plain.
 Bar: 1e-12 (FP64) / 1e-5 (FP32) state-relative per cell, as everywhere.
 """
 import numpy as np
@@ -30,6 +34,7 @@ CASES = {
     "128-k2-learned-fp32": (128, 2, dg.DG_FP32, ALL | dg.DG_LEARNED_SENSOR, True),
     "256-k2-fp32": (256, 2, dg.DG_FP32, DRIVE, False),
     "256-k2-fp64": (256, 2, dg.DG_FP64, DRIVE, False),
+    "256-k3-fp64": (256, 3, dg.DG_FP64, DRIVE, False),
 }
 
 
