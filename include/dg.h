@@ -56,9 +56,14 @@ enum dg_flags {
     DG_HLLC = 64,              /* HLLC-type interface flux instead of Rusanov: the isothermal counterpart of
                                   the HLLC solver of Sec. 2.2 (HLL for density and normal momentum,
                                   tangential momentum carried by the mass flux, upwinded) */
-    DG_RK_BY_ORDER = 128       /* SSP Runge-Kutta scheme by degree (Sec. 7: k+1 stages per step): two stages
+    DG_RK_BY_ORDER = 128,      /* SSP Runge-Kutta scheme by degree (Sec. 7: k+1 stages per step): two stages
                                   (second order) at degree 1, three at degree 2, five stages of fourth order
                                   at degree 3; without it every degree uses three stages (third order) */
+    DG_VOLUME_MFMA = 256       /* FP32 at degree 2 only (DG_EUNSUPPORTED otherwise): the volume integral's
+                                  evaluation at the points and its flux and driving contractions (Sec. 2.2,
+                                  Sec. 7: the dominant dense products) on the matrix cores instead of the
+                                  vector units; same results within the FP32 tolerance; tables off the
+                                  driving shell keep the vector form */
 };
 
 typedef struct dg_config {

@@ -174,6 +174,41 @@ void build_tables(std::vector<double> &t)
                 }
 }
 
+// A-operand tables of the matrix-core volume integral at degree 2 (MfmaTab) from the host
+// tables t: lane = 16 g + j; padded points take point 0's values for evaluations and zero
+// weights for the contractions; padded modes are zero.
+void build_mfma_tables(const std::vector<double> &t, std::vector<float> &mt)
+{
+    using S = Shape<2>;
+    using TL = TabLayout<2>;
+    constexpr Modes<2> M = make_modes<2>();
+    mt.assign(MfmaTab::SIZE, 0.0f);
+    auto phi = [&](int q, int l) { return t[TL::VPHI + q * S::NB + l]; };
+    auto dphi = [&](int q, int d, int l) {
+        return M.dj[d][l] < 0 ? 0.0 : t[TL::VDPHI + (q * 3 + d) * S::ND + M.dj[d][l]];
+    };
+    for (int lane = 0; lane < 64; ++lane) {
+        const int g = lane / 16, j = lane % 16;
+        for (int P = 0; P < 2; ++P) {
+            const int qa = 16 * P + j, qae = qa < S::NQ ? qa : 0;
+            for (int st = 0; st < 3; ++st) {
+                const int mode = 4 * st + g;
+                mt[MfmaTab::EV + (P * 3 + st) * 64 + lane] = mode < S::NB ? (float)phi(qae, mode) : 0.0f;
+            }
+            mt[MfmaTab::DV + P * 64 + lane] = (float)phi(qae, g);
+            for (int r = 0; r < 4; ++r) {
+                const int q = 16 * P + 4 * g + r;
+                const bool ok = q < S::NQ && j < S::NB;
+                const double w = q < S::NQ ? t[TL::VW + q] : 0.0;
+                for (int d = 0; d < 3; ++d)
+                    mt[MfmaTab::CT + ((d * 2 + P) * 4 + r) * 64 + lane] = ok ? (float)(w * dphi(q, d, j)) : 0.0f;
+                mt[MfmaTab::FT + (P * 4 + r) * 64 + lane] = ok ? (float)(w * phi(q, j)) : 0.0f;
+                mt[MfmaTab::WQ + (P * 4 + r) * 64 + lane] = (float)w;
+            }
+        }
+    }
+}
+
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
@@ -247,8 +282,9 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
         !(cfg->rho_floor >= 0.0) || !(cfg->rho_floor_rel >= 0.0) || !(cfg->rho_floor_rel < 1.0))
         return DG_EINVAL;
     const int known = DG_AV | DG_PRIM_PROJ | DG_FORCING | DG_POS_LIMITER | DG_LEARNED_SENSOR | DG_FORCE_MEANFREE |
-                      DG_HLLC | DG_RK_BY_ORDER;
+                      DG_HLLC | DG_RK_BY_ORDER | DG_VOLUME_MFMA;
     if (cfg->flags & ~known) return DG_EINVAL;
+    if ((cfg->flags & DG_VOLUME_MFMA) && !(cfg->precision == DG_FP32 && cfg->degree == 2)) return DG_EUNSUPPORTED;
     if ((cfg->flags & DG_LEARNED_SENSOR) && cfg->degree != 2) return DG_EUNSUPPORTED;
     {
         // each [var] block of nb mode planes is addressed through one buffer descriptor
@@ -303,6 +339,12 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
     if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned, 256, hipHostMallocCoherent);
     if (e == hipSuccess) std::memset(c->pinned, 0, 256);
     if (e == hipSuccess) e = hipMalloc((void **)&c->mlp_bf16, 8 * DG_MLP_NPARAM);
+    if (e == hipSuccess && (c->cfg.flags & DG_VOLUME_MFMA)) {
+        std::vector<float> mt;
+        build_mfma_tables(t, mt);
+        e = hipMalloc((void **)&c->mfma_tab, mt.size() * sizeof(float));
+        if (e == hipSuccess) e = hipMemcpy(c->mfma_tab, mt.data(), mt.size() * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) rc = DG_EHIP;
     if (rc != DG_OK) { dg_free(c); return rc; }
     *out = c;
@@ -322,6 +364,7 @@ void dg_free(dg_ctx *c)
         if (c->modes_ev[i]) (void)hipEventDestroy(c->modes_ev[i]);
     if (c->modes_stage) (void)hipHostFree(c->modes_stage);
     if (c->mlp_bf16) (void)hipFree(c->mlp_bf16);
+    if (c->mfma_tab) (void)hipFree(c->mfma_tab);
     stats_release(c);
     delete c;
 }
@@ -570,6 +613,7 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     if (rc) return rc;
     // tables off the pencil form: the kernel's direct (mode by mode) driving field
     const bool direct = (a.flags & DG_FORCING) && !c->modes_sep;
+    a.mfma = c->mfma_tab;
     // sweep order: tiles of planes when whole blocks make up a plane
     {
         const int cpb = rhs_pair<T, K>() ? BLOCK / 2 : BLOCK;
@@ -583,8 +627,18 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
         else hipLaunchKernelGGL((k_rhs_pair<K, false>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
     } else {
         c->rhs_nblk = c->nblk;
-        if (direct) hipLaunchKernelGGL((k_rhs<T, K, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_rhs<T, K, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+        bool done = false;
+        if constexpr (sizeof(T) == 4 && K == 2) {
+            // volume integral on the matrix cores (tables in the pencil form or no driving)
+            if ((c->cfg.flags & DG_VOLUME_MFMA) && !direct) {
+                hipLaunchKernelGGL((k_rhs<T, K, false, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+                done = true;
+            }
+        }
+        if (!done) {
+            if (direct) hipLaunchKernelGGL((k_rhs<T, K, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+            else hipLaunchKernelGGL((k_rhs<T, K, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+        }
     }
     LAUNCHCHK(c);
     return prof_mark(c, 0, 1);

@@ -48,6 +48,7 @@ struct dg_ctx {
     int ou_ready = 0;
     // learned sensor
     void *mlp_bf16 = nullptr;      // device copy of the parameters (fp32 master + bf16 weights)
+    float *mfma_tab = nullptr;     // A-operand tables of the matrix-core volume integral (DG_VOLUME_MFMA)
     bool have_params = false;
     bool have_nu = false;
     bool learned_bounds_later = false;   // see proj_args

@@ -17,7 +17,8 @@
 
 namespace dg {
 
-enum : int { F_AV = 1, F_PRIM = 2, F_FORCE = 4, F_LIMIT = 8, F_LEARNED = 16, F_MEANFREE = 32, F_HLLC = 64 };
+enum : int { F_AV = 1, F_PRIM = 2, F_FORCE = 4, F_LIMIT = 8, F_LEARNED = 16, F_MEANFREE = 32, F_HLLC = 64,
+             F_VOLUME_MFMA = 256 };
 
 constexpr int BLOCK = 256;
 
@@ -241,6 +242,7 @@ struct RhsArgs {
     double h, cs, alpha, beta, dt;
     const double *dt_dev;   // the time step in device memory (a stage launched ahead), or NULL: dt
     int bpp, zt;            // block sweep order (plane_tiled): blocks per z-plane, planes per tile
+    const float *mfma;      // A-operand tables of the matrix-core volume integral (MfmaTab), or NULL
 };
 
 // time-step bound inputs shared by the projection and stage kernels
@@ -654,6 +656,204 @@ __device__ __forceinline__ void cell_phase(int i, double h, T &pr, T &pim)
 // Driving field forms of the right-hand-side kernels' volume loop
 enum : int { FM_LANE = 0, FM_UNIFORM = 1, FM_DIRECT = 2 };
 
+// ------------------------------------------- volume integral on the matrix cores (FP32)
+// A variant of the volume integral of the FP32 degree-2 right-hand side with both dense
+// contractions on v_mfma_f32_16x16x4f32, 16 cells of the wave at a time (a tile), cells
+// along the N dimension of every product:
+//   * evaluation at the points, U[pt][cell] = sum_l phi_l(pt) W[l][cell] for each variable:
+//     A = phi (16 points x 4 modes per step, 27 points padded to 32, 10 modes to 12),
+//     B = the tile's weights (4 modes x 16 cells);
+//   * the divergence of the projected velocity at the points from its 4 modal coefficients;
+//   * the flux and driving contraction L[l][cell] += sum_(d,pt) w ∂_d phi_l(pt) F_d(pt, cell)
+//     + sum_pt (h/2) w phi_l(pt) rho a(pt): A = the weighted basis tables (16 modes x 4 points
+//     per step, the modes padded from 10 to 16), B = the point fluxes (4 points x 16 cells).
+// The point fluxes, the viscous pressure and the driving source are formed on the VALU in
+// the accumulator layout of the evaluation: lane (g, j) = (lane / 16, lane % 16) holds points
+// 16P + 4g + r (r < 4) of cell j, which is exactly the operand layout the contraction takes
+// when a step's K index g stands for point 16P + 4g + r.  Padded points read point 0's
+// values (finite) and carry zero weights.  The accumulators of tile t end in lane (g, j) as
+// modes 4g + r of cell j; lane permutes hand them to the lane that owns the cell in the face
+// pass (lane 16t + j).
+//
+// Measured against the one-lane VALU volume loop: see the design notes; at degree 2 the
+// contraction keeps about 21 % of the matrix core's work useful (10 of 16 mode rows, 27 of
+// 32 points, and per axis only 4 of 10 modes with a nonzero derivative).
+typedef float f4_t __attribute__((ext_vector_type(4)));
+#ifndef MFMA_WAVES
+#define MFMA_WAVES 2
+#endif
+
+// A-operand tables of the matrix-core volume integral, per lane (64 lanes), FP32:
+//   EV[P][s][lane]   phi_(4s+g)(pt 16P + j)                    (6 x 64)
+//   DV[P][lane]      phi_g(pt 16P + j), g < 4 (divergence modes) (2 x 64)
+//   CT[d][P][r][lane] w ∂_d phi_j(pt 16P + 4g + r)              (24 x 64)
+//   FT[P][r][lane]   (h/2) w phi_j(pt 16P + 4g + r)             (8 x 64; h/2 applied in the kernel)
+// with g = lane / 16, j = lane % 16, modes >= 10 and points >= 27 zero in CT/FT, points >= 27
+// replaced by point 0 in EV/DV.
+//   WQ[P][r][lane]   w(pt 16P + 4g + r), zero for points >= 27     (8 x 64)
+struct MfmaTab {
+    static constexpr int EV = 0, DV = EV + 6 * 64, CT = DV + 2 * 64, FT = CT + 24 * 64, WQ = FT + 8 * 64,
+                         SIZE = WQ + 8 * 64;
+};
+
+__device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+
+// The volume integral of one block's FP32 degree-2 right-hand side on the matrix cores: each
+// wave takes its 64 cells as four tiles of 16.  lds: the block's face-flux buffer, free until
+// the face pass, holding the A tables (MfmaTab) and each wave's pencil of the driving table.
+// L, fs0..fs2: the lane's own cell's accumulators and driving sums, as the VALU loop leaves them.
+__device__ __forceinline__ void volume_mfma(const RhsArgs &a, ctab<float> *tab, float *lds, int blk, bool active,
+                                            int pencil, float (&L)[4][10], float &fs0, float &fs1, float &fs2)
+{
+    using S = Shape<2>;
+    using TL = TabLayout<2>;
+    using PL = PencilLayout<2>;
+    constexpr Modes<2> M = make_modes<2>();
+    constexpr DivMap<2> DM = make_divmap<2>();
+    constexpr int NB = S::NB, NQ = S::NQ;
+    const int nc = a.g.nc;
+    const bool av = a.flags & F_AV, force = a.flags & F_FORCE, learned_on = a.flags & F_LEARNED;
+    const float cs = (float)a.cs, cs2 = (float)(a.cs * a.cs), hp = (float)(a.h / 3.0);
+    const double dtv = a.dt_dev ? *a.dt_dev : a.dt;
+    const float inv_dt = dtv > 0.0 ? (float)(1.0 / dtv) : 1e30f;
+    const float alpha = (float)a.alpha, beta = (float)a.beta, two_h = (float)(2.0 / a.h), half_h = (float)(0.5 * a.h);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+    // stage the A tables and, when the wave's cells share a pencil, its driving-table block
+    for (int i = threadIdx.x; i < MfmaTab::SIZE; i += BLOCK) lds[i] = a.mfma[i];
+    float *lgw = lds + MfmaTab::SIZE + wv * PL::STRIDE;
+    ctab<float> *ft = as_tab<float>(a.ftab);
+    const int p0 = __shfl(pencil, 0, 64);
+    const bool uni = force && __all(!active || pencil == p0);
+    if (uni)
+        for (int i = lane; i < PL::STRIDE; i += 64) lgw[i] = ft[PL::HDR + (size_t)p0 * PL::STRIDE + i];
+    __syncthreads();
+    const Field<float, 4> U(a.u, NB, nc);
+    const Field<float, 3> VH(a.vh, NB, nc);
+    const int wc0 = blk * BLOCK + wv * 64;
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+        const int ct0 = wc0 + 16 * t + j;
+        const bool tact = ct0 < nc;
+        const int ct = tact ? ct0 : 0;
+        const unsigned bt = (unsigned)ct * 4u;
+        // the tile cells' weights as the B operands of the evaluation (modes 4 st + g)
+        float bw[4][3];
+#pragma unroll
+        for (int st = 0; st < 3; ++st) {
+            const int mode = 4 * st + g;
+            const int mm = mode < NB ? mode : NB - 1;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float b = U.get(v, mm, bt);
+                bw[v][st] = mode < NB ? b : 0.f;
+            }
+        }
+        // divergence of the projected velocity: this lane supplies coefficient g of cell j
+        float dvg = 0.f, nu = 0.f;
+        bool learned = false;
+        if (av) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int l = 0; l < NB; ++l)
+                    if (M.e[l][d] >= 1) {
+                        const float v = VH.get(d, l, bt);
+#pragma unroll
+                        for (int q = 0; q < DivMap<2>::MAXT; ++q)
+                            if (DM.m[d][l][q] >= 0)
+                                dvg += DM.m[d][l][q] == g ? v * float(__builtin_sqrt(double(DM.f[d][l][q]))) : 0.f;
+                    }
+            if (learned_on) {
+                learned = a.fb[ct] == 0;
+                nu = ((const float *)a.nu)[ct];
+            }
+        }
+        // driving field: this tile cell's x phase and pencil block
+        float pr = 0.f, pim = 0.f;
+        const float *gb = lgw;
+        if (force) {
+            const int ci = ct % a.g.nx;
+            cell_phase<float>(ci, a.h, pr, pim);
+            if (!uni) gb = (const float *)(a.ftab) + PL::HDR + (size_t)(ct / a.g.nx) * PL::STRIDE;
+        }
+        f4_t C[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) C[v] = f4_t{0.f, 0.f, 0.f, 0.f};
+        float sa0 = 0.f, sa1 = 0.f, sa2 = 0.f;
+#pragma unroll
+        for (int P = 0; P < 2; ++P) {
+            // point values: E[v] holds points 16P + 4g + r of cell j
+            f4_t E[4], Dd = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                E[v] = f4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int st = 0; st < 3; ++st) E[v] = mfma4(lds[MfmaTab::EV + (P * 3 + st) * 64 + lane], bw[v][st], E[v]);
+            }
+            if (av) Dd = mfma4(lds[MfmaTab::DV + P * 64 + lane], dvg, Dd);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = 16 * P + 4 * g + r;
+                const int qe = q < NQ ? q : 0;
+                const float rho = E[0][r];
+                const float m[3] = {E[1][r], E[2][r], E[3][r]};
+                float pi = 0.f;
+                if (av) {
+                    const float div = Dd[r] * two_h;
+                    const float pv = vnr_pi<float>(rho, div, hp, alpha, beta, cs, inv_dt);
+                    const float sq = -div;
+                    float pl = fminf(rho * nu * sq, 0.5f * rho * hp * hp * sq * inv_dt);
+                    pl = (sq > 0.f && nu > 0.f) ? pl : 0.f;
+                    pi = learned ? pl : pv;
+                }
+                const float ir = rcp(rho);
+                const float pw = cs2 * rho + pi;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const float mdr = m[d] * ir;
+                    float F[4] = {m[d], mdr * m[0], mdr * m[1], mdr * m[2]};
+                    F[1 + d] += pw;
+                    const float ac = lds[MfmaTab::CT + ((d * 2 + P) * 4 + r) * 64 + lane];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) C[v] = mfma4(ac, F[v], C[v]);
+                }
+                if (force) {
+                    const int tx = qe % 3, tt = qe / 3;
+                    const float er = ft[2 * tx], ei = ft[2 * tx + 1];
+                    const float xr = pr * er - pim * ei, xi = pr * ei + pim * er;
+                    const float x2r = xr * xr - xi * xi, x2i = 2.f * xr * xi;
+                    const float *e = gb + tt * PL::ENT;
+                    float acc[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d)
+                        acc[d] = e[5 * d] + e[5 * d + 1] * xr - e[5 * d + 2] * xi + e[5 * d + 3] * x2r - e[5 * d + 4] * x2i;
+                    const float af = lds[MfmaTab::FT + (P * 4 + r) * 64 + lane] * half_h;
+                    const float wq = lds[MfmaTab::WQ + (P * 4 + r) * 64 + lane];
+                    const float s0 = rho * acc[0], s1 = rho * acc[1], s2 = rho * acc[2];
+                    C[1] = mfma4(af, s0, C[1]);
+                    C[2] = mfma4(af, s1, C[2]);
+                    C[3] = mfma4(af, s2, C[3]);
+                    if (tact) { sa0 += wq * s0; sa1 += wq * s1; sa2 += wq * s2; }
+                }
+            }
+        }
+        fs0 += sa0; fs1 += sa1; fs2 += sa2;
+        // hand modes 4g + r of cell j to the cell's own lane (16t + j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const float x = __shfl(C[v][l & 3], 16 * (l >> 2) + j, 64);
+                L[v][l] = g == t ? x : L[v][l];
+            }
+    }
+    __syncthreads();      // the face pass reuses the buffer
+}
+
 // ------------------------------------------------------------------ RHS kernel
 // dw/dt = (1/(4h)) [ sum_q w_q grad_xi(phi) . F(q) - sum_faces +- sum_r w_r phi F*(r) ]
 //         + (1/8) sum_q w_q phi rho a (Sec. 2.2 weight evolution; Sec. 3.1; Sec. 4.2)
@@ -662,11 +862,11 @@ enum : int { FM_LANE = 0, FM_UNIFORM = 1, FM_DIRECT = 2 };
 // waves and FP32 four (two at degree 3) without spilling.  FP64 at degree 3 (160 values
 // of coefficients and accumulators) cannot fit 256 VGPRs: one wave per SIMD lets the
 // compiler keep the overflow in accumulation registers instead of scratch memory.
-template <typename T, int K>
-constexpr int rhs_waves() { return sizeof(T) == 8 ? (K <= 2 ? 2 : 1) : (K <= 2 ? 4 : 2); }
+template <typename T, int K, bool VMFMA = false>
+constexpr int rhs_waves() { return VMFMA ? MFMA_WAVES : (sizeof(T) == 8 ? (K <= 2 ? 2 : 1) : (K <= 2 ? 4 : 2)); }
 
-template <typename T, int K, bool FDIRECT>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K>()))) k_rhs(RhsArgs a)
+template <typename T, int K, bool FDIRECT, bool VMFMA = false>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K, VMFMA>()))) k_rhs(RhsArgs a)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -698,7 +898,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const Field<T, 4> U(a.u, NB, nc);
     const Field<T, 3> VH(a.vh, NB, nc);
     T W[4][NB];
-    load_field<T, K, 4>(U, bo, W);
+    if constexpr (!VMFMA) load_field<T, K, 4>(U, bo, W);
+    else W[0][0] = U.get(0, 0, bo);
 
     // divergence of the projected velocity (Sec. 3.1) as a degree-(K-1) polynomial:
     // its NDIV modal coefficients from the exact derivatives of the Legendre basis
@@ -709,7 +910,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     for (int m = 0; m < NDIV; ++m) Dv[m] = T(0);
     bool learned = false;
     T nu = T(0);
-    if (av) {
+    if (av && !VMFMA) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -815,7 +1016,10 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
             }
         }
     };
-    if constexpr (FDIRECT) {
+    if constexpr (VMFMA) {
+        static_assert(sizeof(T) == 4 && K == 2 && !FDIRECT, "matrix-core volume integral: FP32, degree 2");
+        volume_mfma(a, tab, (float *)fsh, blk, active, pencil, L, fs0, fs1, fs2);
+    } else if constexpr (FDIRECT) {
         volume(std::integral_constant<int, FM_DIRECT>{}, 0);
     } else {
         // the wave's cells share one pencil (x lines of at least 64 cells): scalar table loads
@@ -866,8 +1070,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
         if (a.pred_fail) predict_failure<T>(a, dt, c, mass0, L[0][0] * inv4h);
     }
     if (force && a.part) {
-        double acc[4] = {active ? 0.125 * (double)fs0 : 0.0, active ? 0.125 * (double)fs1 : 0.0,
-                         active ? 0.125 * (double)fs2 : 0.0, active ? (double)mass0 : 0.0};
+        const bool fsok = active || VMFMA;     // the matrix-core sums are masked per tile cell
+        double acc[4] = {fsok ? 0.125 * (double)fs0 : 0.0, fsok ? 0.125 * (double)fs1 : 0.0,
+                         fsok ? 0.125 * (double)fs2 : 0.0, active ? (double)mass0 : 0.0};
         block_sum<4>(acc, lds);
         if (threadIdx.x == 0)
 #pragma unroll

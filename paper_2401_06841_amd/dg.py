@@ -21,7 +21,7 @@ DG_OK, DG_RETRY = 0, 1
 DG_EINVAL, DG_EUNSUPPORTED, DG_EHIP, DG_ENOMEM, DG_ESTATE = -1, -2, -3, -4, -5
 DG_FP64, DG_FP32 = 0, 1
 DG_AV, DG_PRIM_PROJ, DG_FORCING, DG_POS_LIMITER, DG_LEARNED_SENSOR, DG_FORCE_MEANFREE = 1, 2, 4, 8, 16, 32
-DG_HLLC, DG_RK_BY_ORDER = 64, 128
+DG_HLLC, DG_RK_BY_ORDER, DG_VOLUME_MFMA = 64, 128, 256
 DG_MLP_NIN, DG_MLP_NHID = 20, 64
 DG_MLP_NPARAM = 64 * 20 + 64 + 64 * 64 + 64 + 64 + 1
 
