@@ -448,7 +448,12 @@ def main():
         args.start == "turbulent" or (args.start == "auto" and args.warmup < spinup))
     args.start_state = start_state(args.workload, args.seed) if turbulent_start else None
     _log(f"workload {args.workload}, {precision}, start {'seeded turbulence-like state' if turbulent_start else 'rest'}")
-    main_run, compare = run_gpu(args, precision)
+    try:
+        main_run, compare = run_gpu(args, precision)
+    except RuntimeError as exc:        # e.g. positivity retries exhausted: report, no figure
+        print(json.dumps({"metric": METRIC, "value": None, "unit": "DOF-updates/s", "n_gpus": 1,
+                          "workload": args.workload, "rho_floor_rel": args.rho_floor_rel, "error": str(exc)}))
+        sys.exit(1)
     cpu = None if args.no_cpu else run_cpu_baseline(args)
     if cpu:
         _log(f"CPU oracle: {cpu['value']:.3e} DOF-updates/s on {cpu['cores']} threads")
