@@ -19,6 +19,11 @@
  *   - state u: the weights, stored [var][mode][cell] (var = rho, m_x, m_y, m_z), contiguous,
  *     element type double (DG_FP64) or float (DG_FP32), in DEVICE memory owned by the caller.
  *   - projected velocity vhat: [dir][mode][cell], same element type.
+ *   - every device array an entry point is handed (state, output, workspace, scratch) must
+ *     lie inside one allocation the HIP runtime tracks (hipMalloc, hipMallocManaged,
+ *     hipHostMalloc, pools and mapped ranges), aligned to its element size: a null pointer,
+ *     a pointer the runtime cannot place in an allocation, or an array that would run past
+ *     the end of its allocation is rejected with DG_EINVAL before anything is launched.
  *   - every call is asynchronous on the stream given in the configuration unless it says
  *     it synchronises.  Calls on one context must not overlap in time (one stream).
  *   - return value: DG_OK (0); DG_RETRY (1, recoverable); negative on error, with a
@@ -37,7 +42,8 @@ extern "C" {
 enum dg_status {
     DG_OK = 0,
     DG_RETRY = 1,          /* positivity failure: retry the step with a smaller dt (Sec. 3.1) */
-    DG_EINVAL = -1,        /* null / misaligned pointer, bad size or parameter */
+    DG_EINVAL = -1,        /* null / misaligned / unallocated pointer, array past its allocation's end,
+                              bad size or parameter */
     DG_EUNSUPPORTED = -2,  /* degree outside 1..3, feature not available for this degree */
     DG_EHIP = -3,          /* a HIP runtime call failed (text in dg_last_error) */
     DG_ENOMEM = -4,        /* workspace missing or too small */

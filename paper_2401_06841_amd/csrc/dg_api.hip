@@ -2,6 +2,7 @@
 // layout, kernel launches and the C ABI declared in include/dg.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -228,10 +229,11 @@ static void layout(dg_ctx *c, size_t *total)
     c->off.L = o; o += state;
     c->off.vh0 = o; o += vh;
     c->off.vh1 = o; o += vh;
-    // driving field in pencil form: header + (k+1)^2 entries of 16 values per y-z pencil
+    // driving field in pencil form: header, (k+1)^2 entries of 16 values per y-z pencil, and
+    // the x phases (PencilLayout)
     c->off.ftab = o;
     o += (c->cfg.flags & DG_FORCING)
-             ? align_up((16 + (size_t)c->cfg.ny * c->cfg.nz * (c->k + 1) * (c->k + 1) * 16) * es)
+             ? align_up((16 + (size_t)c->cfg.ny * c->cfg.nz * (c->k + 1) * (c->k + 1) * 16 + 2 * (size_t)c->cfg.nx) * es)
              : 0;
     const bool learned = c->cfg.flags & DG_LEARNED_SENSOR;
     c->off.nu = o; o += align_up(nc * es);
@@ -388,6 +390,7 @@ int dg_set_workspace(dg_ctx *c, void *ws, size_t bytes)
     if ((uintptr_t)ws & 255) return dg_fail(c, DG_EINVAL, "workspace must be 256-byte aligned");
     if (bytes < c->ws_need)
         return dg_fail(c, DG_ENOMEM, "workspace too small: %zu < %zu bytes", bytes, c->ws_need);
+    if (int rc = dg_check_array(c, ws, c->ws_need, 256, "workspace")) return rc;
     c->ws = (char *)ws;
     c->gen++;
     c->forcing_dirty = c->nmodes > 0;
@@ -402,11 +405,28 @@ static int need_ws(dg_ctx *c)
     return DG_OK;
 }
 
-static int check_ptr(dg_ctx *c, const void *p, const char *name)
+int dg_check_array(dg_ctx *c, const void *p, size_t bytes, size_t align, const char *name)
 {
     if (!p) return dg_fail(c, DG_EINVAL, "%s is null", name);
-    if ((uintptr_t)p & (c->es - 1)) return dg_fail(c, DG_EINVAL, "%s is misaligned", name);
+    if ((uintptr_t)p & (align - 1)) return dg_fail(c, DG_EINVAL, "%s is misaligned", name);
+    // the extent of the allocation that holds p (the lookup's error is cleared: it is
+    // reported here, not by a later call)
+    void *base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void *>(p)) != hipSuccess || !base) {
+        (void)hipGetLastError();
+        return dg_fail(c, DG_EINVAL, "%s (%p) is not inside an allocation of the HIP runtime", name, p);
+    }
+    const uintptr_t off = (uintptr_t)p - (uintptr_t)base;
+    if ((uintptr_t)p < (uintptr_t)base || off > size || bytes > size - off)
+        return dg_fail(c, DG_EINVAL, "%s: %zu bytes at offset %zu of an allocation of %zu bytes overrun it", name,
+                       bytes, (size_t)off, size);
     return DG_OK;
+}
+
+static int check_ptr(dg_ctx *c, const void *p, const char *name, int nvar = 4)
+{
+    return dg_check_array(c, p, dg_state_bytes(c, nvar), c->es, name);
 }
 
 int dg_set_forcing(dg_ctx *c, const double *modes_host, int nmodes)
@@ -519,7 +539,7 @@ static int launch_forcing_table(dg_ctx *c)
 {
     if (!c->modes_sep) return DG_OK;
     const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
-    const long long nt = (long long)c->cfg.ny * c->cfg.nz * (K + 1) * (K + 1);
+    const long long nt = std::max((long long)c->cfg.ny * c->cfg.nz * (K + 1) * (K + 1), (long long)c->cfg.nx);
     const int nb = (int)((nt + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL((k_forcing_pencils<T, K>), dim3(nb), dim3(BLOCK), 0, c->stream, c->wp(c->off.ftab),
                        c->modes_dev, c->nmodes, c->tab, g, c->cfg.h);
@@ -1013,6 +1033,7 @@ int dg_dt_max(dg_ctx *c, const void *u, double *dt_out, int on_host)
     int rc;
     if ((rc = need_ws(c)) || (rc = check_ptr(c, u, "u"))) return rc;
     if (!dt_out) return dg_fail(c, DG_EINVAL, "dt_out is null");
+    if (!on_host && (rc = dg_check_array(c, dt_out, sizeof(double), sizeof(double), "dt_out"))) return rc;
     if ((rc = learned_ready(c))) return rc;
     return DISPATCH(c, do_dt, c, u, dt_out, on_host);
 }
@@ -1036,14 +1057,15 @@ static int do_dt_noalloc(dg_ctx *c, const void *u, double *dt_out, int on_host, 
 int dg_dt_max_noalloc(dg_ctx *c, const void *u, double *dt_out, int on_host)
 {
     if (!c) return DG_EINVAL;
-    int rc;
-    if ((rc = check_ptr(c, u, "u"))) return rc;
-    if (!dt_out) return dg_fail(c, DG_EINVAL, "dt_out is null");
     if (c->cfg.flags & DG_LEARNED_SENSOR)
         return dg_fail(c, DG_EUNSUPPORTED, "dg_dt_max_noalloc: the learned sensor's viscosity lives in the workspace");
     if (c->nblk > NOALLOC_MAX_BLOCKS)
         return dg_fail(c, DG_EINVAL, "dg_dt_max_noalloc: %d cells need %d blocks of partials, the static scratch holds %d "
                                      "(%d cells)", c->nc, c->nblk, NOALLOC_MAX_BLOCKS, NOALLOC_MAX_BLOCKS * BLOCK);
+    int rc;
+    if ((rc = check_ptr(c, u, "u"))) return rc;
+    if (!dt_out) return dg_fail(c, DG_EINVAL, "dt_out is null");
+    if (!on_host && (rc = dg_check_array(c, dt_out, sizeof(double), sizeof(double), "dt_out"))) return rc;
     int dev = -1;
     HIPCHK(c, hipGetDevice(&dev));
     if (dev != c->device)
@@ -1063,7 +1085,7 @@ int dg_project_primitive(dg_ctx *c, const void *u, void *vhat)
 {
     if (!c) return DG_EINVAL;
     int rc;
-    if ((rc = check_ptr(c, u, "u")) || (rc = check_ptr(c, vhat, "vhat"))) return rc;
+    if ((rc = check_ptr(c, u, "u")) || (rc = check_ptr(c, vhat, "vhat", 3))) return rc;
     return DISPATCH(c, do_proj, c, u, vhat);
 }
 

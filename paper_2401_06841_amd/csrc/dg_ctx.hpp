@@ -86,6 +86,13 @@ struct dg_ctx {
 
 int dg_fail(dg_ctx *ctx, int code, const char *fmt, ...);
 
+// a device array of `bytes` bytes at p, checked before any launch reads or writes it: not
+// null, aligned to `align`, and inside one allocation the HIP runtime tracks (DG_EINVAL
+// otherwise)
+int dg_check_array(dg_ctx *ctx, const void *p, size_t bytes, size_t align, const char *name);
+// the state array [nvar][modes][cells] in the context's precision
+inline size_t dg_state_bytes(const dg_ctx *c, int nvar = 4) { return (size_t)nvar * c->nb * c->nc * c->es; }
+
 // return a DG_EHIP error with the failing call and its place from a host function
 #define HIPCHK(ctx, call)                                                                         \
     do {                                                                                          \

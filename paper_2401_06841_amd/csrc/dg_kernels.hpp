@@ -431,13 +431,16 @@ template <int D, typename T>
 __device__ __forceinline__ void rusanov(T cs, T cs2, const T (&uL)[4], const T (&vL)[3], const T (&uR)[4],
                                         const T (&vR)[3], T (&F)[4])
 {
+    // every fused multiply-add written out and no other contraction left to the compiler:
+    // the flux of a face is then the same bits whichever of its two cells computes it
+#pragma clang fp contract(off)
     const T lam = fmax(fabs(vL[D]), fabs(vR[D])) + cs;
     const T hl = T(0.5) * lam;
-    F[0] = T(0.5) * (uL[1 + D] + uR[1 + D]) - hl * (uR[0] - uL[0]);
+    F[0] = fma(-hl, uR[0] - uL[0], T(0.5) * (uL[1 + D] + uR[1 + D]));
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-        F[1 + j] = T(0.5) * (uL[1 + D] * vL[j] + uR[1 + D] * vR[j]) - hl * (uR[1 + j] - uL[1 + j]);
-    F[1 + D] += T(0.5) * cs2 * (uL[0] + uR[0]);
+        F[1 + j] = fma(-hl, uR[1 + j] - uL[1 + j], T(0.5) * fma(uL[1 + D], vL[j], uR[1 + D] * vR[j]));
+    F[1 + D] = fma(T(0.5) * cs2, uL[0] + uR[0], F[1 + D]);
 }
 
 // isothermal HLLC-type flux across a face with normal +e_D (the counterpart of the HLLC
@@ -592,7 +595,8 @@ __device__ __forceinline__ void face_shared(const T *share, int slot, ctab<T> *t
 // where G_nd(y, z) sums a_m,d exp(2 pi i (n_y y + n_z z)) over the modes with n_x = n.  The G
 // depend only on the cell's y-z pencil (j, l) and the point's (t_y, t_z): the pencil table
 // holds them (about 1 KB per pencil in FP64 at degree 2, built once per table update), and
-// X = P E_t with P = exp(2 pi i (i + 1/2) h) per cell and E_t = exp(pi i xi_t h) from the
+// X = P E_t with P = exp(2 pi i (i + 1/2) h) per cell, from the table's last block (one
+// (cos, sin) pair per x index i, after the pencils), and E_t = exp(pi i xi_t h) from the
 // table header.  The 64 cells of a wave usually share one pencil: their G are then read with
 // scalar loads.  Other tables are evaluated mode by mode at every point (k_rhs's direct form).
 template <int K>
@@ -601,6 +605,9 @@ struct PencilLayout {
     static constexpr int HDR = 16;                  // (cos, sin)(pi xi_t h) for t < N1, padded
     static constexpr int ENT = 16;                  // per (t_y, t_z): 3 x (G0, Re G1, Im G1, Re G2, Im G2), padded
     static constexpr int STRIDE = N1 * N1 * ENT;    // reals per pencil
+    // offset of the x phases P_i = (cos, sin)(2 pi (i + 1/2) h), after the ny nz pencils
+    __host__ __device__ static size_t phases(int ny, int nz) { return HDR + (size_t)ny * nz * STRIDE; }
+    __host__ __device__ static size_t size(int nx, int ny, int nz) { return phases(ny, nz) + 2 * (size_t)nx; }
 };
 
 // a at volume point q (q = t_x + N1 (t_y + N1 t_z)) from the pencil table: g = this pencil's
@@ -643,14 +650,12 @@ __device__ __forceinline__ void direct_accel(const double *modes, int nmodes, co
     acc[2] = (T)az;
 }
 
-// the cell's x phase P = exp(2 pi i (i + 1/2) h)
+// the cell's x phase P = exp(2 pi i (i + 1/2) h) from the table's phase block px
 template <typename T>
-__device__ __forceinline__ void cell_phase(int i, double h, T &pr, T &pim)
+__device__ __forceinline__ void cell_phase(ctab<T> *px, int i, T &pr, T &pim)
 {
-    double sp, cp;
-    sincospi(2.0 * (i + 0.5) * h, &sp, &cp);
-    pr = (T)cp;
-    pim = (T)sp;
+    pr = px[2 * i];
+    pim = px[2 * i + 1];
 }
 
 // Driving field forms of the right-hand-side kernels' volume loop
@@ -777,7 +782,7 @@ __device__ __forceinline__ void volume_mfma(const RhsArgs &a, ctab<float> *tab, 
         const float *gb = lgw;
         if (force) {
             const int ci = ct % a.g.nx;
-            cell_phase<float>(ci, a.h, pr, pim);
+            cell_phase<float>(as_tab<float>(a.ftab) + PencilLayout<2>::phases(a.g.ny, a.g.nz), ci, pr, pim);
             if (!uni) gb = (const float *)(a.ftab) + PL::HDR + (size_t)(ct / a.g.nx) * PL::STRIDE;
         }
         f4_t C[4];
@@ -938,8 +943,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const int pencil = c / a.g.nx;
     const int cijk[3] = {c % a.g.nx, pencil % a.g.ny, pencil / a.g.ny};
     T pr = T(0), pim = T(0);
-    if (force && !FDIRECT) cell_phase<T>(cijk[0], a.h, pr, pim);
     ctab<T> *ft = as_tab<T>(a.ftab);
+    if (force && !FDIRECT) cell_phase<T>(ft + PencilLayout<K>::phases(a.g.ny, a.g.nz), cijk[0], pr, pim);
 
     // ---- volume integral
     auto volume = [&](auto form, int pen) {
@@ -1301,8 +1306,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const int pencil = c / a.g.nx;
     const int cijk[3] = {c % a.g.nx, pencil % a.g.ny, pencil / a.g.ny};
     double pr = 0.0, pim = 0.0;
-    if (force && !FDIRECT) cell_phase<double>(cijk[0], a.h, pr, pim);
     ctab<double> *ft = as_tab<double>(a.ftab);
+    if (force && !FDIRECT) cell_phase<double>(ft + PencilLayout<K>::phases(a.g.ny, a.g.nz), cijk[0], pr, pim);
 
     // ---- volume integral
     auto volume = [&](auto form, int pen) {
@@ -1735,6 +1740,13 @@ __global__ void __launch_bounds__(BLOCK) k_forcing_pencils(void *ft_, const doub
             ft[2 * k] = (T)cp;
             ft[2 * k + 1] = (T)sp;
         }
+    if (t < g.nx) {
+        double sp, cp;
+        sincospi(2.0 * ((double)t + 0.5) * h, &sp, &cp);
+        T *px = ft + PL::phases(g.ny, g.nz);
+        px[2 * t] = (T)cp;
+        px[2 * t + 1] = (T)sp;
+    }
     if (t >= nt) return;
     const int pen = (int)(t / (N1 * N1)), tt = (int)(t % (N1 * N1));
     const int j = pen % g.ny, l = pen / g.ny;

@@ -525,6 +525,11 @@ int dg_mlp_forward(dg_ctx *c, const float *P, const float *x, int n, float *y)
     if (!c) return DG_EINVAL;
     if (!P || !x || !y || n < 0) return dg_fail(c, DG_EINVAL, "bad network arguments");
     if (n == 0) return DG_OK;
+    int rc;
+    if ((rc = dg_check_array(c, P, sizeof(float) * NPARAM, sizeof(float), "params")) ||
+        (rc = dg_check_array(c, x, sizeof(float) * NIN * (size_t)n, sizeof(float), "x")) ||
+        (rc = dg_check_array(c, y, sizeof(float) * (size_t)n, sizeof(float), "y")))
+        return rc;
     hipLaunchKernelGGL((k_mlp_forward<float>), dim3(fwd_blocks(c, n)), dim3(256), 0, c->stream, P, x, n, y,
                        (float *)nullptr, (const int *)nullptr, (double *)nullptr);
     LAUNCHCHK(c);
@@ -535,6 +540,12 @@ int dg_mlp_grad(dg_ctx *c, const float *P, const float *x, const float *t, int n
 {
     if (!c) return DG_EINVAL;
     if (!P || !x || !t || !grad || !loss || n <= 0) return dg_fail(c, DG_EINVAL, "bad network arguments");
+    if (dg_check_array(c, P, sizeof(float) * NPARAM, sizeof(float), "params") ||
+        dg_check_array(c, x, sizeof(float) * NIN * (size_t)n, sizeof(float), "x") ||
+        dg_check_array(c, t, sizeof(float) * (size_t)n, sizeof(float), "t") ||
+        dg_check_array(c, grad, sizeof(float) * NPARAM, sizeof(float), "grad") ||
+        dg_check_array(c, loss, sizeof(float), sizeof(float), "loss"))
+        return DG_EINVAL;
     if (!c->ws) return dg_fail(c, DG_ENOMEM, "no workspace set (dg_set_workspace)");
     const int nb = mlp_blocks(n);
     hipLaunchKernelGGL(k_mlp_grad, dim3(nb), dim3(256), 0, c->stream, P, x, t, n, mlp_part(c));
@@ -549,6 +560,11 @@ int dg_mlp_adam(dg_ctx *c, float *P, const float *G, float *m, float *v, int ste
 {
     if (!c) return DG_EINVAL;
     if (!P || !G || !m || !v || step < 1 || !(lr > 0.0f)) return dg_fail(c, DG_EINVAL, "bad Adam arguments");
+    if (dg_check_array(c, P, sizeof(float) * NPARAM, sizeof(float), "params") ||
+        dg_check_array(c, G, sizeof(float) * NPARAM, sizeof(float), "grad") ||
+        dg_check_array(c, m, sizeof(float) * NPARAM, sizeof(float), "m") ||
+        dg_check_array(c, v, sizeof(float) * NPARAM, sizeof(float), "v"))
+        return DG_EINVAL;
     hipLaunchKernelGGL(k_mlp_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, c->stream, P, G, m, v, step, lr);
     LAUNCHCHK(c);
     return DG_OK;
@@ -558,7 +574,7 @@ int dg_sensor_set_params(dg_ctx *c, const float *P)
 {
     if (!c) return DG_EINVAL;
     c->spec_valid = false;          // the viscosity or flags a launched next stage used change
-    if (!P) return dg_fail(c, DG_EINVAL, "params is null");
+    if (int rc = dg_check_array(c, P, sizeof(float) * NPARAM, sizeof(float), "params")) return rc;
     HIPCHK(c, hipMemcpyAsync(c->mlp_bf16, P, sizeof(float) * NPARAM, hipMemcpyDeviceToDevice, c->stream));
     c->have_params = true;
     return DG_OK;
@@ -583,7 +599,9 @@ int dg_sensor_features(dg_ctx *c, const void *u, float *x)
     if (!c) return DG_EINVAL;
     int rc = need_k2(c);
     if (rc) return rc;
-    if (!u || !x) return dg_fail(c, DG_EINVAL, "null pointer");
+    if ((rc = dg_check_array(c, u, dg_state_bytes(c), c->es, "u")) ||
+        (rc = dg_check_array(c, x, sizeof(float) * NIN * (size_t)c->nc, sizeof(float), "x")))
+        return rc;
     return launch_features(c, u, x, nullptr);
 }
 
@@ -599,7 +617,8 @@ template <typename OUT>
 static int labels_any(dg_ctx *c, const void *u, OUT *nu)
 {
     if (!c) return DG_EINVAL;
-    if (!u || !nu) return dg_fail(c, DG_EINVAL, "null pointer");
+    if (int rc = dg_check_array(c, u, dg_state_bytes(c), c->es, "u")) return rc;
+    if (int rc = dg_check_array(c, nu, sizeof(OUT) * (size_t)c->nc, sizeof(OUT), "output")) return rc;
     if (c->es == 8) {
         if (c->k == 1) launch_labels<double, 1>(c, u, nu);
         else if (c->k == 2) launch_labels<double, 2>(c, u, nu);
@@ -629,7 +648,7 @@ int sensor_infer_impl(dg_ctx *c, const void *u, int *nvmax, const void *vhat)
     if (rc) return rc;
     if (!c->have_params) return dg_fail(c, DG_ESTATE, "no network parameters (dg_sensor_set_params)");
     float *x = (float *)c->wp(c->off.feat);
-    if (!u) return dg_fail(c, DG_EINVAL, "u is null");
+    if ((rc = dg_check_array(c, u, dg_state_bytes(c), c->es, "u"))) return rc;
     rc = launch_features(c, u, x, vhat);
     if (rc) return rc;
     const int nblk = fwd_blocks(c, c->nc);
@@ -651,7 +670,7 @@ int dg_sensor_infer(dg_ctx *c, const void *u)
 {
     if (!c) return DG_EINVAL;
     c->spec_valid = false;          // the viscosity or flags a launched next stage used change
-    if (!u) return dg_fail(c, DG_EINVAL, "u is null");
+    if (int rc = dg_check_array(c, u, dg_state_bytes(c), c->es, "u")) return rc;
     return sensor_infer_impl(c, u);
 }
 
@@ -660,6 +679,7 @@ int dg_sensor_judge(dg_ctx *c, const void *u, double tau, long *nfallback)
     if (!c) return DG_EINVAL;
     c->spec_valid = false;          // the viscosity or flags a launched next stage used change
     if (!u || !(tau >= 0.0)) return dg_fail(c, DG_EINVAL, "bad judge arguments");
+    if (int rc = dg_check_array(c, u, dg_state_bytes(c), c->es, "u")) return rc;
     int rc = sensor_infer_impl(c, u);
     if (rc) return rc;
     double *lab = (double *)c->wp(c->off.lab);
@@ -688,6 +708,8 @@ int dg_sensor_set_nu(dg_ctx *c, const void *nu, const int32_t *fb)
     c->spec_valid = false;          // the viscosity or flags a launched next stage used change
     int rc = need_k2(c);
     if (rc) return rc;
+    if (nu && (rc = dg_check_array(c, nu, c->es * (size_t)c->nc, c->es, "nu"))) return rc;
+    if (fb && (rc = dg_check_array(c, fb, 4 * (size_t)c->nc, 4, "fallback"))) return rc;
     if (nu) {
         HIPCHK(c, hipMemcpyAsync(c->wp(c->off.nu), nu, c->es * (size_t)c->nc, hipMemcpyDeviceToDevice, c->stream));
         c->have_nu = true;

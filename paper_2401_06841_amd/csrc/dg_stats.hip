@@ -366,9 +366,7 @@ SpLayout sp_layout(const dg_ctx *c, int p)
 
 int check_state_ptr(dg_ctx *c, const void *u)
 {
-    if (!u) return dg_fail(c, DG_EINVAL, "u is null");
-    if ((uintptr_t)u & (c->es - 1)) return dg_fail(c, DG_EINVAL, "u is misaligned");
-    return DG_OK;
+    return dg_check_array(c, u, dg_state_bytes(c), c->es, "u");
 }
 
 int check_scratch(dg_ctx *c, const void *scratch, size_t bytes, size_t need)
@@ -376,7 +374,7 @@ int check_scratch(dg_ctx *c, const void *scratch, size_t bytes, size_t need)
     if (!scratch) return dg_fail(c, DG_EINVAL, "scratch is null");
     if ((uintptr_t)scratch & 255) return dg_fail(c, DG_EINVAL, "scratch must be 256-byte aligned");
     if (bytes < need) return dg_fail(c, DG_ENOMEM, "scratch too small: %zu < %zu bytes", bytes, need);
-    return DG_OK;
+    return dg_check_array(c, scratch, need, 256, "scratch");
 }
 
 template <typename T, int K>

@@ -76,7 +76,7 @@ def test_noalloc_rejects_what_it_cannot_do():
     h = ctypes.c_void_p()
     assert L.dg_init(ctypes.byref(big), ctypes.byref(h)) == dg.DG_OK
     try:
-        fake = torch.empty(8, dtype=torch.float64, device="cuda")     # never read: refused first
+        fake = torch.empty(8, dtype=torch.float64, device="cuda")     # never read: the size is refused first
         assert L.dg_dt_max_noalloc(h, ctypes.c_void_p(fake.data_ptr()), ctypes.byref(out), 1) == dg.DG_EINVAL
         assert b"static scratch" in L.dg_last_error(h)
     finally:
