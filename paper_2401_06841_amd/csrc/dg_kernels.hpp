@@ -146,35 +146,28 @@ __device__ __forceinline__ rsrc_t mkrs(const void *base)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xFFFFFFFF, 0x00020000);
 }
 
-template <typename T>
-__device__ __forceinline__ T bld(rsrc_t r, unsigned voff, unsigned soff);
+// Cache policy of an access: CP_NT marks data touched once (the non-temporal hint of the
+// gfx950 buffer instructions), so that it does not displace the traces that neighbouring
+// cells read again from L2.
+enum : int { CP_DEFAULT = 0, CP_NT = 2 };
 
-template <>
-__device__ __forceinline__ double bld<double>(rsrc_t r, unsigned voff, unsigned soff)
+template <typename T, int CP = CP_DEFAULT>
+__device__ __forceinline__ T bld(rsrc_t r, unsigned voff, unsigned soff)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, CP));
+    else
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, CP));
 }
 
-template <>
-__device__ __forceinline__ float bld<float>(rsrc_t r, unsigned voff, unsigned soff)
+template <typename T, int CP = CP_DEFAULT>
+__device__ __forceinline__ void bst(rsrc_t r, unsigned voff, unsigned soff, T v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-
-template <typename T>
-__device__ __forceinline__ void bst(rsrc_t r, unsigned voff, unsigned soff, T v);
-
-template <>
-__device__ __forceinline__ void bst<double>(rsrc_t r, unsigned voff, unsigned soff, double v)
-{
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
-                                          voff, soff, 0);
-}
-
-template <>
-__device__ __forceinline__ void bst<float>(rsrc_t r, unsigned voff, unsigned soff, float v)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    if constexpr (sizeof(T) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                              voff, soff, CP);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, CP);
 }
 
 // a [nvar][nb][nc] array viewed through one descriptor per variable
@@ -199,6 +192,15 @@ struct Field {
     __device__ __forceinline__ Field(const Field &) = default;
     __device__ __forceinline__ T get(int v, int l, unsigned boff) const { return bld<T>(r[v], boff, l * pstride); }
     __device__ __forceinline__ void put(int v, int l, unsigned boff, T x) const { bst<T>(r[v], boff, l * pstride, x); }
+    // the same with the non-temporal hint (data read or written once by this kernel)
+    __device__ __forceinline__ T get_nt(int v, int l, unsigned boff) const
+    {
+        return bld<T, CP_NT>(r[v], boff, l * pstride);
+    }
+    __device__ __forceinline__ void put_nt(int v, int l, unsigned boff, T x) const
+    {
+        bst<T, CP_NT>(r[v], boff, l * pstride, x);
+    }
 };
 
 // fast reciprocal: hardware estimate refined by two Newton steps (about 1 ulp)
@@ -902,9 +904,21 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const unsigned bo = (unsigned)c * sizeof(T);
     const Field<T, 4> U(a.u, NB, nc);
     const Field<T, 3> VH(a.vh, NB, nc);
+    // with the projected velocity on the faces the momentum weights are read only here:
+    // non-temporal, like the right-hand side written at the end
     T W[4][NB];
-    if constexpr (!VMFMA) load_field<T, K, 4>(U, bo, W);
-    else W[0][0] = U.get(0, 0, bo);
+    if constexpr (!VMFMA) {
+        if (prim) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int l = 0; l < NB; ++l) W[v][l] = v ? U.get_nt(v, l, bo) : U.get(v, l, bo);
+        } else {
+            load_field<T, K, 4>(U, bo, W);
+        }
+    } else {
+        W[0][0] = U.get(0, 0, bo);
+    }
 
     // divergence of the projected velocity (Sec. 3.1) as a degree-(K-1) polynomial:
     // its NDIV modal coefficients from the exact derivatives of the Legendre basis
@@ -1071,7 +1085,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int l = 0; l < NB; ++l) O.put(v, l, bo, L[v][l] * inv4h);
+            for (int l = 0; l < NB; ++l) O.put_nt(v, l, bo, L[v][l] * inv4h);
         if (a.pred_fail) predict_failure<T>(a, dt, c, mass0, L[0][0] * inv4h);
     }
     if (force && a.part) {
@@ -1261,11 +1275,14 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const unsigned bo = (unsigned)c * 8u;
     const Field<double, 4> U(a.u, NB, nc);
     double W[2][NB];
+    // with the projected velocity on the faces the momentum weights are read only here:
+    // non-temporal, like the right-hand side written at the end
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int l = 0; l < NB; ++l) {
-            const double w0 = U.get(i, l, bo), w1 = U.get(2 + i, l, bo);
+            const double w0 = (i && prim) ? U.get_nt(i, l, bo) : U.get(i, l, bo);
+            const double w1 = prim ? U.get_nt(2 + i, l, bo) : U.get(2 + i, l, bo);
             W[i][l] = h ? w1 : w0;
         }
 
@@ -1422,7 +1439,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int l = 0; l < NB; ++l) ob[((size_t)(2 * h + i) * NB + l) * ncs + c] = L[i][l] * inv4h;
+            for (int l = 0; l < NB; ++l)
+                __builtin_nontemporal_store(L[i][l] * inv4h, &ob[((size_t)(2 * h + i) * NB + l) * ncs + c]);
         if (a.pred_fail && h == 0) predict_failure<double>(a, dt, c, mass0, L[0][0] * inv4h);
     }
     if (force && a.part) {
@@ -1610,7 +1628,8 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         for (int v = 3; v >= 0; --v)
 #pragma unroll
             for (int l = 0; l < NB; ++l) {
-                T rhs = LF.get(v, l, bo);
+                // the right-hand side and u^n are read once (non-temporal)
+                T rhs = LF.get_nt(v, l, bo);
                 if (v > 0) rhs -= ab[v - 1] * U[0][l];
                 const T ui = U[v][l];
                 if (side) {
@@ -1619,7 +1638,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
                 }
                 // stage_value, written out so that the u^n load stays conditional
                 const T x = fma(cdt, rhs, cb * ui);
-                U[v][l] = use_un ? fma(ca, UN.get(v, l, bo), x) : x;
+                U[v][l] = use_un ? fma(ca, UN.get_nt(v, l, bo), x) : x;
             }
     }
     if (a.flags & F_LIMIT) {
