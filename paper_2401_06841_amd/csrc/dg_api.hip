@@ -227,8 +227,12 @@ static void layout(dg_ctx *c, size_t *total)
     // a third stage buffer for the five-stage scheme (degree 3 with DG_RK_BY_ORDER)
     c->off.stC = o; o += ((c->cfg.flags & DG_RK_BY_ORDER) && c->k == 3) ? state : 0;
     c->off.L = o; o += state;
-    c->off.vh0 = o; o += vh;
-    c->off.vh1 = o; o += vh;
+    // with the two-lane right-hand side (FP64, degree 3) each projection buffer is preceded by
+    // a copy of the density weights, so that density and projected velocity form one
+    // [4][nb][nc] array (vh_rho_of)
+    const size_t rho_blk = (c->es == 8 && c->k == 3) ? align_up((size_t)c->nb * nc * es) : 0;
+    c->off.vh0 = o + rho_blk; o = c->off.vh0 + vh;
+    c->off.vh1 = o + rho_blk; o = c->off.vh1 + vh;
     // driving field in pencil form: header, (k+1)^2 entries of 16 values per y-z pencil, and
     // the x phases (PencilLayout)
     c->off.ftab = o;
@@ -563,13 +567,22 @@ static ProjArgs proj_args(const dg_ctx *c)
     return pa;
 }
 
+// the density copy in front of a workspace projection buffer (two-lane configuration), or
+// NULL for any other buffer or configuration
+static void *vh_rho_of(const dg_ctx *c, const void *vh)
+{
+    if (!(c->es == 8 && c->k == 3) || !vh) return nullptr;
+    if (vh != c->wp(c->off.vh0) && vh != c->wp(c->off.vh1)) return nullptr;
+    return (char *)const_cast<void *>(vh) - (size_t)c->nb * c->nc * c->es;
+}
+
 template <typename T, int K>
 static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int *fail)
 {
     const Mesh g{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
     const ProjArgs pa = proj_args(c);
     hipLaunchKernelGGL((k_project<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, u, vh, c->tab, g, pa,
-                       part, fail);
+                       part, fail, vh_rho_of(c, vh));
     LAUNCHCHK(c);
     return DG_OK;
 }
@@ -580,6 +593,7 @@ static int launch_project(dg_ctx *c, const void *u, void *vh, double *part, int 
 // lane swap per point value, 194 -> 265 us at 64^3 degree 2).
 template <typename T, int K>
 constexpr bool rhs_pair() { return sizeof(T) == 8 && K == 3; }
+
 
 // failure prediction of a last stage (RhsArgs::pred_fail): its u^n operand and coefficients
 struct StagePred {
@@ -605,6 +619,8 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     RhsArgs a;
     a.u = u;
     a.vh = vh;
+    a.vh_rho = nullptr;
+    a.pair_vstride = 0;
     a.out = out;
     a.tab = c->tab;
     a.ftab = c->wp(c->off.ftab);
@@ -643,8 +659,20 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     }
     if constexpr (rhs_pair<T, K>()) {
         c->rhs_nblk = (c->nc + BLOCK / 2 - 1) / (BLOCK / 2);
-        if (direct) hipLaunchKernelGGL((k_rhs_pair<K, true>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_rhs_pair<K, false>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
+        // each lane loads only its own variables when two variable blocks and a cell offset fit
+        // a 32-bit buffer offset, and (projected traces) the density copy is in front of vh
+        const size_t vb = (size_t)c->nb * c->nc * 8;
+        const bool prim = c->cfg.flags & DG_PRIM_PROJ;
+        a.vh_rho = vh_rho_of(c, vh);
+        const bool lsel = 2 * vb + (size_t)c->nc * 8 < ((size_t)1 << 32) && (!prim || a.vh_rho);
+        a.pair_vstride = lsel ? (unsigned)(2 * vb) : 0u;
+        if (lsel) {
+            if (direct) hipLaunchKernelGGL((k_rhs_pair<K, true, true>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
+            else hipLaunchKernelGGL((k_rhs_pair<K, false, true>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
+        } else {
+            if (direct) hipLaunchKernelGGL((k_rhs_pair<K, true, false>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
+            else hipLaunchKernelGGL((k_rhs_pair<K, false, false>), dim3(c->rhs_nblk), dim3(BLOCK), 0, c->stream, a);
+        }
     } else {
         c->rhs_nblk = c->nblk;
         bool done = false;
@@ -692,6 +720,7 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.L = L;
     a.out = out;
     a.vh_out = vh_out;
+    a.rho_out = vh_rho_of(c, vh_out);
     a.skip_flag = skip_if_failed ? c->fail() : nullptr;
     a.tab = c->tab;
     // abar_in_stage: every block reduces the right-hand side's partials to the removed mean

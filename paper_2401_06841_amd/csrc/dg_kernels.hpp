@@ -245,6 +245,12 @@ struct RhsArgs {
     const double *dt_dev;   // the time step in device memory (a stage launched ahead), or NULL: dt
     int bpp, zt;            // block sweep order (plane_tiled): blocks per z-plane, planes per tile
     const float *mfma;      // A-operand tables of the matrix-core volume integral (MfmaTab), or NULL
+    // two-lane kernel: a copy of the density weights directly in front of vh (so that density
+    // and projected velocity form one [4][nb][nc] array), or NULL; and the byte distance of two
+    // variable blocks (2 nb nc 8) when every lane can reach its own variables through a 32-bit
+    // offset, else 0
+    const void *vh_rho;
+    unsigned pair_vstride;
 };
 
 // time-step bound inputs shared by the projection and stage kernels
@@ -263,6 +269,7 @@ struct StageArgs {
     const void *L;          // right-hand side of u^(i) (NULL: plain copy/limit of ui)
     void *out;              // u^(i+1) (may alias un)
     void *vh_out;           // projection of u^(i+1) for the next stage, or NULL
+    void *rho_out;          // with vh_out: a copy of the density weights of u^(i+1), or NULL
     const int *skip_flag;   // the last stage: the failure flag (write nothing when raised), or NULL
     const void *tab;
     const double *abar;     // removed mean acceleration (3), or NULL
@@ -1105,8 +1112,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
 // cell i: lane h owns variables 2h and 2h+1 (coefficients, accumulators, face traces), and
 // the partner's point values come across in registers (a DPP lane swap).  The flux at a
 // point, which needs all four variables, is formed in both lanes; each lane contracts and
-// lifts its own two variables.  Buffer resources must be uniform over the wave, so a lane
-// loads its variable 2h+i by loading variables i and 2+i and keeping its own.
+// lifts its own two variables.  Buffer resources are uniform over the wave: a lane reaches
+// its variable 2h+i through the buffer of variable i and a lane offset of two variable
+// blocks (LSEL: when that offset fits 32 bits, with the projected traces read from one
+// array that holds a copy of the density weights in front of the projected velocity);
+// otherwise it loads variables i and 2+i and keeps its own.
 
 // the value held by the other lane of the pair (lane ^ 1)
 __device__ __forceinline__ double pair_swap(double x)
@@ -1129,10 +1139,10 @@ __device__ __forceinline__ void pair_assemble(int h, double a0, double a1, doubl
 
 // one face of the cell for the lane's two variables; src[i] points at variable 2h+i of
 // the trace field (mode planes nc apart), c and cn the own and the neighbour cell
-template <int K, int D, int CB>
+template <int K, int D, int CB, bool LSEL>
 __device__ __forceinline__ void face_pair(const Field<double, 4> &src, unsigned bo, unsigned bn, int s, int h,
-                                          ctab<double> *tab, bool prim, bool use_hllc, double cs, double cs2,
-                                          double (&L)[2][Shape<K>::NB], double *share, int cb)
+                                          unsigned hoff, ctab<double> *tab, bool prim, bool use_hllc, double cs,
+                                          double cs2, double (&L)[2][Shape<K>::NB], double *share, int cb)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -1148,11 +1158,18 @@ __device__ __forceinline__ void face_pair(const Field<double, 4> &src, unsigned 
 #pragma unroll
         for (int l = 0; l < S::NB; ++l) {
             const int e = M.e[l][D];
-            // variable 2h+i through the uniform per-variable buffers: both candidates, then
-            // the lane's own
-            const double wo0 = src.get(i, l, bo), wo1 = src.get(2 + i, l, bo);
-            const double wn0 = src.get(i, l, bn), wn1 = src.get(2 + i, l, bn);
-            const double wo = h ? wo1 : wo0, wn = h ? wn1 : wn0;
+            double wo, wn;
+            if constexpr (LSEL) {
+                // variable 2h+i: the buffer of variable i, two variable blocks further in lane 1
+                wo = src.get(i, l, bo + hoff);
+                wn = src.get(i, l, bn + hoff);
+            } else {
+                // through the uniform per-variable buffers: both candidates, then the lane's own
+                const double wo0 = src.get(i, l, bo), wo1 = src.get(2 + i, l, bo);
+                const double wn0 = src.get(i, l, bn), wn1 = src.get(2 + i, l, bn);
+                wo = h ? wo1 : wo0;
+                wn = h ? wn1 : wn0;
+            }
             Co[i][M.d2[D][l]] += wo * lend[2 * e + s];
             Cn[i][M.d2[D][l]] += wn * lend[2 * e + 1 - s];
             // keep at most one variable's loads in flight (register pressure)
@@ -1241,7 +1258,7 @@ __device__ __forceinline__ void face_shared_pair(const double *share, int slot, 
 template <int K>
 constexpr int rhs_pair_waves() { return K <= 2 ? 3 : 2; }   // at K = 3: 256 VGPRs, 14 of them spilled
 
-template <int K, bool FDIRECT>
+template <int K, bool FDIRECT, bool LSEL>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_pair_waves<K>()))) k_rhs_pair(RhsArgs a)
 {
     using S = Shape<K>;
@@ -1274,6 +1291,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
 
     const unsigned bo = (unsigned)c * 8u;
     const Field<double, 4> U(a.u, NB, nc);
+    const unsigned hoff = h ? a.pair_vstride : 0u;
     double W[2][NB];
     // with the projected velocity on the faces the momentum weights are read only here:
     // non-temporal, like the right-hand side written at the end
@@ -1281,9 +1299,13 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int l = 0; l < NB; ++l) {
-            const double w0 = (i && prim) ? U.get_nt(i, l, bo) : U.get(i, l, bo);
-            const double w1 = prim ? U.get_nt(2 + i, l, bo) : U.get(2 + i, l, bo);
-            W[i][l] = h ? w1 : w0;
+            if constexpr (LSEL) {
+                W[i][l] = (i && prim) ? U.get_nt(i, l, bo + hoff) : U.get(i, l, bo + hoff);
+            } else {
+                const double w0 = (i && prim) ? U.get_nt(i, l, bo) : U.get(i, l, bo);
+                const double w1 = prim ? U.get_nt(2 + i, l, bo) : U.get(2 + i, l, bo);
+                W[i][l] = h ? w1 : w0;
+            }
         }
 
     constexpr DivMap<K> DM = make_divmap<K>();
@@ -1412,26 +1434,29 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     // one-lane kernel (cells of the block: CB consecutive cells)
     int nbr[6], ijk[3];
     neighbours(a.g, c, nbr, ijk);
-    const Field<double, 4> SRC = prim ? Field<double, 4>(a.u, a.vh, NB, nc) : U;
+    // trace sources: density and projected velocity (one array when the density copy is
+    // there), or the weights
+    const Field<double, 4> SRC = !prim ? U
+                                 : (LSEL ? Field<double, 4>(a.vh_rho, NB, nc) : Field<double, 4>(a.u, a.vh, NB, nc));
     const int base = blk * CB;
     const bool xsh = __all((unsigned)(nbr[1] - base) < (unsigned)CB);
     const bool ysh = __all((unsigned)(nbr[3] - base) < (unsigned)CB);
 #pragma unroll 1
     for (int s = 0; s < (xsh ? 1 : 2); ++s)
-        face_pair<K, 0, CB>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * 8u, s, h, tab, prim, use_hllc, cs, cs2, L,
+        face_pair<K, 0, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * 8u, s, h, hoff, tab, prim, use_hllc, cs, cs2, L,
                             s == 0 ? fsh : nullptr, cb);
     __syncthreads();
     if (xsh) face_shared_pair<K, 0, CB>(fsh, nbr[1] - base, h, tab, L);
     __syncthreads();
 #pragma unroll 1
     for (int s = 0; s < (ysh ? 1 : 2); ++s)
-        face_pair<K, 1, CB>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * 8u, s, h, tab, prim, use_hllc, cs, cs2, L,
+        face_pair<K, 1, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * 8u, s, h, hoff, tab, prim, use_hllc, cs, cs2, L,
                             s == 0 ? fsh : nullptr, cb);
     __syncthreads();
     if (ysh) face_shared_pair<K, 1, CB>(fsh, nbr[3] - base, h, tab, L);
 #pragma unroll 1
     for (int s = 0; s < 2; ++s)
-        face_pair<K, 2, CB>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * 8u, s, h, tab, prim, use_hllc, cs, cs2, L, nullptr, cb);
+        face_pair<K, 2, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * 8u, s, h, hoff, tab, prim, use_hllc, cs, cs2, L, nullptr, cb);
 
     const double inv4h = 0.25 / a.h;
     if (active) {
@@ -1711,6 +1736,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         }
     }
     if (active) store_field<T, K, 4>(Field<T, 4>(a.out, NB, nc), bo, U);
+    if (a.rho_out && active)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) ((T *)a.rho_out)[(size_t)l * nc + c] = U[0][l];
     if (a.vh_out) project_and_bounds<T, K>(U, tab, a.vh_out, nc, bo, c, active, a.pa, a.part, blk, lds);
 }
 
@@ -1719,7 +1747,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
 // vhat of u and, optionally, the per-block time-step maxima and a reset of the failure flag
 template <typename T, int K>
 __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, const void *tab_, Mesh g, ProjArgs pa,
-                                                   double *part, int *fail)
+                                                   double *part, int *fail, void *rho_out)
 {
     using S = Shape<K>;
     constexpr int NB = S::NB;
@@ -1734,6 +1762,9 @@ __global__ void __launch_bounds__(BLOCK) k_project(const void *u_, void *vh_, co
     ctab<T> *tab = as_tab<T>(tab_);
     T W[4][NB];
     load_field<T, K, 4>(Field<T, 4>(u_, NB, nc), bo, W);
+    if (rho_out && active)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) ((T *)rho_out)[(size_t)l * nc + c] = W[0][l];
     project_and_bounds<T, K>(W, tab, vh_, nc, bo, c, active, pa, part, blk, lds);
 }
 
