@@ -490,13 +490,50 @@ __device__ __forceinline__ T vnr_pi(T rho, T divv, T hp, T alpha, T beta, T cs, 
 }
 
 // ---------------------------------------------------------------- face pass
-// Surface integral of one face (normal axis D, side s: 0 = low, 1 = high) lifted into L.
-// With share != nullptr the physical flux at every face point is also stored for the
-// neighbour across the face: share[(r * 4 + v) * BLOCK + threadIdx.x].
+// Surface integral of one face (normal axis D, side s: 0 = low, 1 = high) from the point
+// fluxes in an LDS column (col: the column of the cell that stored them, [r][v] with stride
+// BLOCK): the flux moments against the 2D basis of the face, M_vj = sum_r w_r F_v(r) P2_j(r),
+// then per mode phi_l = Lt_{e_D}(+-1) P2_{d2(l)} on the face, so L_vl += Lt_{e_D}(+-1) M_v,d2(l)
+// (the lift of every point into all NB modes takes NB multiply-adds per point and variable,
+// the moments NB2).
+template <typename T, int K, int D>
+__device__ __forceinline__ void lift(const T *col, int s, ctab<T> *tab, T (&L)[4][Shape<K>::NB])
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    T Mv[4][S::NB2];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) Mv[v][j] = T(0);
+#pragma unroll 1
+    for (int r = 0; r < S::NF; ++r) {
+        const T wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];   // outward normal
+        ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const T g = wr * col[(r * 4 + v) * BLOCK];
+#pragma unroll
+            for (int j = 0; j < S::NB2; ++j) Mv[v][j] += g * f2[j];
+        }
+    }
+    ctab<T> *lend = tab + TL::LEND;
+#pragma unroll
+    for (int l = 0; l < S::NB; ++l) {
+        const T ls = lend[2 * M.e[l][D] + s];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) L[v][l] += ls * Mv[v][M.d2[D][l]];
+    }
+}
+
+// One face of the cell (normal axis D, side s): traces of the cell and its neighbour,
+// the numerical flux at every face point stored in the cell's LDS column col (where the
+// neighbour across a shared face reads it too), then lifted from there into L.
 template <typename T, int K, int D>
 __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsigned bn, int s,
                                      ctab<T> *tab, bool prim, bool use_hllc, T cs, T cs2,
-                                     T (&L)[4][Shape<K>::NB], T *share = nullptr)
+                                     T (&L)[4][Shape<K>::NB], T *col)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -520,7 +557,6 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
             // keep at most one variable's loads in flight (register pressure)
             if (l == S::NB - 1) __builtin_amdgcn_sched_barrier(0);
         }
-    ctab<T> *plift = tab + TL::PLIFT + (D * 2 + s) * S::NF * S::NB;
 #pragma unroll 1
     for (int r = 0; r < S::NF; ++r) {
         ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
@@ -559,40 +595,10 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
             if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
             else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
         }
-        if (share)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) share[(r * 4 + v) * BLOCK + threadIdx.x] = F[v];
-        const T wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];   // outward normal
-        ctab<T> *pl = plift + r * S::NB;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const T g = wr * F[v];
-#pragma unroll
-            for (int l = 0; l < S::NB; ++l) L[v][l] += g * pl[l];
-        }
+        for (int v = 0; v < 4; ++v) col[(r * 4 + v) * BLOCK] = F[v];
     }
-}
-
-// Surface integral of the high face (normal axis D) from the point fluxes the neighbour
-// across it stored in its low-face pass (slot = the neighbour's thread in this block): the
-// same flux values this cell would compute, lifted with the outward normal +e_D.
-template <typename T, int K, int D>
-__device__ __forceinline__ void face_shared(const T *share, int slot, ctab<T> *tab, T (&L)[4][Shape<K>::NB])
-{
-    using S = Shape<K>;
-    using TL = TabLayout<K>;
-    ctab<T> *plift = tab + TL::PLIFT + (D * 2 + 1) * S::NF * S::NB;
-#pragma unroll 1
-    for (int r = 0; r < S::NF; ++r) {
-        const T wr = -tab[TL::FW + r];
-        ctab<T> *pl = plift + r * S::NB;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const T g = wr * share[(r * 4 + v) * BLOCK + slot];
-#pragma unroll
-            for (int l = 0; l < S::NB; ++l) L[v][l] += g * pl[l];
-        }
-    }
+    lift<T, K, D>(col, s, tab, L);
 }
 
 // ------------------------------------------------------------ driving field
@@ -1069,22 +1075,34 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const int base = blk * BLOCK;
     const bool xsh = __all((unsigned)(nbr[1] - base) < (unsigned)BLOCK);
     const bool ysh = __all((unsigned)(nbr[3] - base) < (unsigned)BLOCK);
+    // Every face leaves its point fluxes in the cell's LDS column and lifts them from there.
+    // A wave whose high neighbours all lie in the block lifts their low-face fluxes (between
+    // two barriers) instead of computing its high face; a high face that is computed is
+    // stored only after the second barrier, when no other wave reads the columns any more.
+    T *col = fsh + threadIdx.x;
 #pragma unroll 1
-    for (int s = 0; s < (xsh ? 1 : 2); ++s)
-        face<T, K, 0>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L,
-                      s == 0 ? fsh : nullptr);
-    __syncthreads();
-    if (xsh) face_shared<T, K, 0>(fsh, nbr[1] - base, tab, L);
-    __syncthreads();                // the y pass overwrites the stored fluxes
+    for (int s = 0; s < 2; ++s) {
+        if (s == 1) {
+            __syncthreads();
+            if (xsh) lift<T, K, 0>(fsh + (nbr[1] - base), 1, tab, L);
+            __syncthreads();
+            if (xsh) break;
+        }
+        face<T, K, 0>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L, col);
+    }
 #pragma unroll 1
-    for (int s = 0; s < (ysh ? 1 : 2); ++s)
-        face<T, K, 1>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L,
-                      s == 0 ? fsh : nullptr);
-    __syncthreads();
-    if (ysh) face_shared<T, K, 1>(fsh, nbr[3] - base, tab, L);
+    for (int s = 0; s < 2; ++s) {
+        if (s == 1) {
+            __syncthreads();
+            if (ysh) lift<T, K, 1>(fsh + (nbr[3] - base), 1, tab, L);
+            __syncthreads();
+            if (ysh) break;
+        }
+        face<T, K, 1>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L, col);
+    }
 #pragma unroll 1
     for (int s = 0; s < 2; ++s)
-        face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L);
+        face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L, col);
 
     const T inv4h = (T)(0.25 / a.h);
     if (active) {
@@ -1137,12 +1155,49 @@ __device__ __forceinline__ void pair_assemble(int h, double a0, double a1, doubl
     x[3] = h ? a1 : b1;
 }
 
+// Surface integral of one face (normal axis D, side s) from the point fluxes in an LDS column
+// (col: the column of the cell that stored them, [r][v] with stride CB): the flux moments
+// against the 2D basis of the face, M_j = sum_r w_r F(r) P2_j(r), then per mode
+// phi_l = Lt_{e_D}(+-1) P2_{d2(l)} on the face
+template <int K, int D, int CB>
+__device__ __forceinline__ void lift_pair(const double *col, int h, int s, ctab<double> *tab,
+                                          double (&L)[2][Shape<K>::NB])
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    double M2[2][S::NB2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) M2[i][j] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < S::NF; ++r) {
+        const double wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];   // outward normal
+        ctab<double> *f2 = tab + TL::F2 + r * S::NB2;
+        const double g0 = wr * col[(r * 4 + 2 * h) * CB];
+        const double g1 = wr * col[(r * 4 + 2 * h + 1) * CB];
+#pragma unroll
+        for (int j = 0; j < S::NB2; ++j) {
+            M2[0][j] += g0 * f2[j];
+            M2[1][j] += g1 * f2[j];
+        }
+    }
+    ctab<double> *lend = tab + TL::LEND;
+#pragma unroll
+    for (int l = 0; l < S::NB; ++l) {
+        const double ls = lend[2 * M.e[l][D] + s];
+        L[0][l] += ls * M2[0][M.d2[D][l]];
+        L[1][l] += ls * M2[1][M.d2[D][l]];
+    }
+}
+
 // one face of the cell for the lane's two variables; src[i] points at variable 2h+i of
 // the trace field (mode planes nc apart), c and cn the own and the neighbour cell
 template <int K, int D, int CB, bool LSEL>
 __device__ __forceinline__ void face_pair(const Field<double, 4> &src, unsigned bo, unsigned bn, int s, int h,
                                           unsigned hoff, ctab<double> *tab, bool prim, bool use_hllc, double cs,
-                                          double cs2, double (&L)[2][Shape<K>::NB], double *share, int cb)
+                                          double cs2, double (&L)[2][Shape<K>::NB], double *col)
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
@@ -1175,7 +1230,6 @@ __device__ __forceinline__ void face_pair(const Field<double, 4> &src, unsigned 
             // keep at most one variable's loads in flight (register pressure)
             if (l == S::NB - 1) __builtin_amdgcn_sched_barrier(0);
         }
-    ctab<double> *plift = tab + TL::PLIFT + (D * 2 + s) * S::NF * S::NB;
 #pragma unroll 1
     for (int r = 0; r < S::NF; ++r) {
         ctab<double> *f2 = tab + TL::F2 + r * S::NB2;
@@ -1217,42 +1271,10 @@ __device__ __forceinline__ void face_pair(const Field<double, 4> &src, unsigned 
             if (s) rusanov<D>(cs, cs2, uo, vo, un, vn, F);
             else   rusanov<D>(cs, cs2, un, vn, uo, vo, F);
         }
-        const double f0 = h ? F[2] : F[0], f1 = h ? F[3] : F[1];
-        if (share) {
-            share[(r * 4 + 2 * h) * CB + cb] = f0;
-            share[(r * 4 + 2 * h + 1) * CB + cb] = f1;
-        }
-        const double wr = s ? -tab[TL::FW + r] : tab[TL::FW + r];
-        ctab<double> *pl = plift + r * S::NB;
-        const double g0 = wr * f0, g1 = wr * f1;
-#pragma unroll
-        for (int l = 0; l < S::NB; ++l) {
-            L[0][l] += g0 * pl[l];
-            L[1][l] += g1 * pl[l];
-        }
+        col[(r * 4 + 2 * h) * CB] = h ? F[2] : F[0];
+        col[(r * 4 + 2 * h + 1) * CB] = h ? F[3] : F[1];
     }
-}
-
-// high face from the fluxes the neighbour cell (slot) stored in its low-face pass
-template <int K, int D, int CB>
-__device__ __forceinline__ void face_shared_pair(const double *share, int slot, int h, ctab<double> *tab,
-                                                 double (&L)[2][Shape<K>::NB])
-{
-    using S = Shape<K>;
-    using TL = TabLayout<K>;
-    ctab<double> *plift = tab + TL::PLIFT + (D * 2 + 1) * S::NF * S::NB;
-#pragma unroll 1
-    for (int r = 0; r < S::NF; ++r) {
-        const double wr = -tab[TL::FW + r];
-        ctab<double> *pl = plift + r * S::NB;
-        const double g0 = wr * share[(r * 4 + 2 * h) * CB + slot];
-        const double g1 = wr * share[(r * 4 + 2 * h + 1) * CB + slot];
-#pragma unroll
-        for (int l = 0; l < S::NB; ++l) {
-            L[0][l] += g0 * pl[l];
-            L[1][l] += g1 * pl[l];
-        }
-    }
+    lift_pair<K, D, CB>(col, h, s, tab, L);
 }
 
 template <int K>
@@ -1441,22 +1463,38 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
     const int base = blk * CB;
     const bool xsh = __all((unsigned)(nbr[1] - base) < (unsigned)CB);
     const bool ysh = __all((unsigned)(nbr[3] - base) < (unsigned)CB);
+    // Every face leaves its point fluxes in the cell's LDS column and lifts them from there.
+    // The low x and y faces are the high faces of the neighbours below: a wave whose
+    // neighbours above all lie in the block lifts theirs (between two barriers) instead of
+    // computing its high face; a high face that is computed is stored only after the second
+    // barrier, when no other wave reads the columns any more.
+    double *col = fsh + cb;
 #pragma unroll 1
-    for (int s = 0; s < (xsh ? 1 : 2); ++s)
-        face_pair<K, 0, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * 8u, s, h, hoff, tab, prim, use_hllc, cs, cs2, L,
-                            s == 0 ? fsh : nullptr, cb);
-    __syncthreads();
-    if (xsh) face_shared_pair<K, 0, CB>(fsh, nbr[1] - base, h, tab, L);
-    __syncthreads();
+    for (int s = 0; s < 2; ++s) {
+        if (s == 1) {
+            __syncthreads();
+            if (xsh) lift_pair<K, 0, CB>(fsh + (nbr[1] - base), h, 1, tab, L);
+            __syncthreads();
+            if (xsh) break;
+        }
+        face_pair<K, 0, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[1] : nbr[0]) * 8u, s, h, hoff, tab, prim, use_hllc, cs,
+                                  cs2, L, col);
+    }
 #pragma unroll 1
-    for (int s = 0; s < (ysh ? 1 : 2); ++s)
-        face_pair<K, 1, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * 8u, s, h, hoff, tab, prim, use_hllc, cs, cs2, L,
-                            s == 0 ? fsh : nullptr, cb);
-    __syncthreads();
-    if (ysh) face_shared_pair<K, 1, CB>(fsh, nbr[3] - base, h, tab, L);
+    for (int s = 0; s < 2; ++s) {
+        if (s == 1) {
+            __syncthreads();
+            if (ysh) lift_pair<K, 1, CB>(fsh + (nbr[3] - base), h, 1, tab, L);
+            __syncthreads();
+            if (ysh) break;
+        }
+        face_pair<K, 1, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[3] : nbr[2]) * 8u, s, h, hoff, tab, prim, use_hllc, cs,
+                                  cs2, L, col);
+    }
 #pragma unroll 1
     for (int s = 0; s < 2; ++s)
-        face_pair<K, 2, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * 8u, s, h, hoff, tab, prim, use_hllc, cs, cs2, L, nullptr, cb);
+        face_pair<K, 2, CB, LSEL>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * 8u, s, h, hoff, tab, prim, use_hllc, cs,
+                                  cs2, L, col);
 
     const double inv4h = 0.25 / a.h;
     if (active) {
