@@ -749,7 +749,15 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.rho_floor_rel = c->cfg.rho_floor_rel;
     int rc = prof_mark(c, 1, 0);
     if (rc) return rc;
-    hipLaunchKernelGGL((k_stage<T, K>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    // u^n enters when its coefficient is not zero; the side combination when it has an output
+    const bool unv = a.L && a.ca != 0.0, side = a.L && a.w_out;
+    if (side) {
+        if (unv) hipLaunchKernelGGL((k_stage<T, K, true, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_stage<T, K, false, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    } else {
+        if (unv) hipLaunchKernelGGL((k_stage<T, K, true, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_stage<T, K, false, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    }
     LAUNCHCHK(c);
     return prof_mark(c, 1, 1);
 }

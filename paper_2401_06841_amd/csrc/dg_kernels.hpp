@@ -1640,7 +1640,7 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
 template <typename T, int K>
 constexpr int stage_waves() { return sizeof(T) == 8 ? (K == 1 ? 7 : (K == 2 ? 4 : 2)) : (K == 1 ? 7 : (K == 2 ? 5 : 3)); }
 
-template <typename T, int K>
+template <typename T, int K, bool UNV, bool SIDE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stage_waves<T, K>()))) k_stage(StageArgs a)
 {
     using S = Shape<K>;
@@ -1686,7 +1686,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         const Field<T, 4> WS(side ? a.w_src : a.ui, NB, nc);
         const Field<T, 4> WO(side ? a.w_out : a.ui, NB, nc);
         const T wa = (T)a.wa, wb = (T)a.wb, wcdt = (T)(a.wc * dt);
-        // momentum first: the removed mean acceleration multiplies the input density
+        // The combination of every weight, momentum first (the removed mean acceleration
+        // multiplies the input density).  Whether u^n and the side combination enter is a
+        // template choice (UNV, SIDE): with a branch per weight the compiler waited for each
+        // weight's loads in turn.
+        (void)use_un;
+        (void)side;
 #pragma unroll
         for (int v = 3; v >= 0; --v)
 #pragma unroll
@@ -1695,13 +1700,16 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
                 T rhs = LF.get_nt(v, l, bo);
                 if (v > 0) rhs -= ab[v - 1] * U[0][l];
                 const T ui = U[v][l];
-                if (side) {
+                if constexpr (SIDE) {
                     const T w = wa * WS.get(v, l, bo) + wb * ui + wcdt * rhs;
                     if (active) WO.put(v, l, bo, w);
                 }
-                // stage_value, written out so that the u^n load stays conditional
+                // stage_value, written out: u^n is loaded only where it enters
                 const T x = fma(cdt, rhs, cb * ui);
-                U[v][l] = use_un ? fma(ca, UN.get_nt(v, l, bo), x) : x;
+                if constexpr (UNV) U[v][l] = fma(ca, UN.get_nt(v, l, bo), x);
+                else U[v][l] = x;
+                // one variable's loads in flight at a time (register pressure)
+                if (l == NB - 1) __builtin_amdgcn_sched_barrier(0);
             }
     }
     if (a.flags & F_LIMIT) {
