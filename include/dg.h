@@ -65,11 +65,20 @@ enum dg_flags {
     DG_RK_BY_ORDER = 128,      /* SSP Runge-Kutta scheme by degree (Sec. 7: k+1 stages per step): two stages
                                   (second order) at degree 1, three at degree 2, five stages of fourth order
                                   at degree 3; without it every degree uses three stages (third order) */
-    DG_VOLUME_MFMA = 256       /* FP32 at degree 2 only (DG_EUNSUPPORTED otherwise): the volume integral's
+    DG_VOLUME_MFMA = 256,      /* FP32 at degree 2 only (DG_EUNSUPPORTED otherwise): the volume integral's
                                   evaluation at the points and its flux and driving contractions (Sec. 2.2,
                                   Sec. 7: the dominant dense products) on the matrix cores instead of the
                                   vector units; same results within the FP32 tolerance; tables off the
                                   driving shell keep the vector form */
+    DG_SEPARATE_STAGE = 512,   /* every Runge-Kutta stage of a step as its own kernel after the stored
+                                  right-hand side */
+    DG_SPLIT_STAGE = 1024      /* the stages that write workspace buffers (all but the last) split between
+                                  the right-hand-side kernel, which forms the stage's combination instead
+                                  of storing the right-hand side, and a kernel that limits and projects
+                                  it.  Same bits as DG_SEPARATE_STAGE.  With neither flag the split is
+                                  used where it measured faster (FP64 meshes of at least 2^22 cells); the
+                                  two-lane FP64 degree-3 kernel and DG_VOLUME_MFMA never split.  Both
+                                  flags together: DG_EINVAL */
 };
 
 typedef struct dg_config {
@@ -190,6 +199,13 @@ int dg_rk_step_next(dg_ctx *ctx, void *u, double dt, int reuse, int *status_host
 int dg_rk_step_next_ahead(dg_ctx *ctx, void *u, double dt, int reuse, double horizon, int *status_host,
                           double *dt_next_host);
 
+/* 1 when the steps of this context split their stages that write workspace buffers between
+ * the right-hand-side kernel (which forms the stage's combination) and a limit-and-project
+ * kernel (DG_SPLIT_STAGE, or the default choice for the mesh and precision; the SSP-RK
+ * combination of Sec. 2.2 / 7 with the limiter of Sec. 3.1 either way), else 0; DG_EINVAL
+ * for a null context.  No device call. */
+int dg_split_stages(const dg_ctx *ctx);
+
 /* Time step dt = min(dt_adv, dt_visc), reduced in FP64 over all cells and interior points:
  * dt_adv = cfl h / ((k+1) max sum_d (|m_d/rho| + cs)) (Sec. 7: dt proportional to h/(k+1));
  * with DG_AV and cfl_visc > 0, dt_visc = cfl_visc (h/p)^2 / max nu, the explicit stability
@@ -233,10 +249,12 @@ int dg_conserved_sums(dg_ctx *ctx, const void *u, double *out_host);
  * by HIP events on the context stream (without the system-scope fence) and the elapsed
  * times are accumulated (counters cleared).  Each event leaves the GPU idle for a few
  * microseconds, so enable = 1 brackets only the right-hand-side kernel of every dg_rhs and
- * of the first stage of every step (the stages of a step launch the same kernel on the same
- * mesh); enable = 2 brackets every right-hand-side and stage-combination launch; enable = 0
- * stops.  dg_profile_read synchronises and writes out_host[4] = {RHS-kernel milliseconds,
- * RHS launches, stage-kernel milliseconds, stage launches}. */
+ * of the first stage of every step (with split stages, DG_SPLIT_STAGE, that kernel also
+ * forms the stage's combination); enable = 3 brackets only the right-hand side of the last
+ * stage of every step (always stored for a stage kernel); enable = 2 brackets every
+ * right-hand-side and stage launch (a split stage's limit-and-project kernel counts as a
+ * stage launch); enable = 0 stops.  dg_profile_read synchronises and writes out_host[4] =
+ * {RHS-kernel milliseconds, RHS launches, stage-kernel milliseconds, stage launches}. */
 int dg_profile(dg_ctx *ctx, int enable);
 int dg_profile_read(dg_ctx *ctx, double *out_host);
 

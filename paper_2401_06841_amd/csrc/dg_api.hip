@@ -251,6 +251,9 @@ static void layout(dg_ctx *c, size_t *total)
     // the step's last stage: per-block time-step maxima (apart from the right-hand side's
     // partials, which the same stage reads)
     c->off.spart = o; o += align_up((size_t)c->nblk * 2 * 8);
+    // mean-acceleration partials of a stage's input formed before its right-hand side (split
+    // stages), apart from the right-hand side's own
+    c->off.dpart = o; o += align_up((size_t)c->nblk * 4 * 8);
     c->off.scal = o; o += align_up(64 * 8);
     c->off.iflags = o; o += align_up(64 * 4);
     *total = o;
@@ -288,9 +291,10 @@ int dg_init(const dg_config *cfg, dg_ctx **out)
         !(cfg->rho_floor >= 0.0) || !(cfg->rho_floor_rel >= 0.0) || !(cfg->rho_floor_rel < 1.0))
         return DG_EINVAL;
     const int known = DG_AV | DG_PRIM_PROJ | DG_FORCING | DG_POS_LIMITER | DG_LEARNED_SENSOR | DG_FORCE_MEANFREE |
-                      DG_HLLC | DG_RK_BY_ORDER | DG_VOLUME_MFMA;
+                      DG_HLLC | DG_RK_BY_ORDER | DG_VOLUME_MFMA | DG_SEPARATE_STAGE | DG_SPLIT_STAGE;
     if (cfg->flags & ~known) return DG_EINVAL;
     if ((cfg->flags & DG_VOLUME_MFMA) && !(cfg->precision == DG_FP32 && cfg->degree == 2)) return DG_EUNSUPPORTED;
+    if ((cfg->flags & DG_SEPARATE_STAGE) && (cfg->flags & DG_SPLIT_STAGE)) return DG_EINVAL;
     if ((cfg->flags & DG_LEARNED_SENSOR) && cfg->degree != 2) return DG_EUNSUPPORTED;
     {
         // each [var] block of nb mode planes is addressed through one buffer descriptor
@@ -495,6 +499,7 @@ static int prof_mark(dg_ctx *c, int kind, int stop)
 {
     if (!c->prof) return DG_OK;
     if (c->prof == 1 && (kind != 0 || !c->prof_first)) return DG_OK;
+    if (c->prof == 3 && (kind != 0 || !c->prof_last)) return DG_OK;
     if (!stop && c->nev >= 2 * dg_ctx::NEV) {
         int rc = prof_drain(c);
         if (rc) return rc;
@@ -519,7 +524,7 @@ int dg_profile(dg_ctx *c, int enable)
         c->prof_ms[0] = c->prof_ms[1] = 0.0;
         c->prof_n[0] = c->prof_n[1] = 0;
     }
-    c->prof = enable < 0 ? 0 : (enable > 2 ? 2 : enable);
+    c->prof = enable < 0 ? 0 : (enable > 3 ? 3 : enable);
     return DG_OK;
 }
 
@@ -607,9 +612,11 @@ struct StagePred {
 // FP64 34.6 -> 33.1 / 32.5 / 32.6 ms; 64^3 unchanged up to 8 and slower at 16
 constexpr int RHS_ZTILE = 8;
 
+// st: the stage that the right-hand side goes on with in the same kernel (fused), or NULL:
+// the right-hand side is stored into out
 template <typename T, int K>
 static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt, int *fail_reset = nullptr,
-                      const StagePred *pred = nullptr, const double *dt_dev = nullptr)
+                      const StagePred *pred = nullptr, const double *dt_dev = nullptr, const StageArgs *st = nullptr)
 {
     if ((c->cfg.flags & DG_FORCING) && c->forcing_dirty) {
         int rc = launch_forcing_table<T, K>(c);
@@ -650,6 +657,8 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     // tables off the pencil form: the kernel's direct (mode by mode) driving field
     const bool direct = (a.flags & DG_FORCING) && !c->modes_sep;
     a.mfma = c->mfma_tab;
+    const StageArgs st0{};
+    if (st) a.part = nullptr;   // a fused stage's kernel reads the partials of its input
     // sweep order: tiles of planes when whole blocks make up a plane
     {
         const int cpb = rhs_pair<T, K>() ? BLOCK / 2 : BLOCK;
@@ -676,16 +685,28 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     } else {
         c->rhs_nblk = c->nblk;
         bool done = false;
+        if (st) {
+            // u^n enters the fused stage when its coefficient is not zero
+            const dim3 gr(c->nblk), bl(BLOCK);
+            if (st->ca != 0.0) {
+                if (direct) hipLaunchKernelGGL((k_rhs<T, K, true, false, 2>), gr, bl, 0, c->stream, a, *st);
+                else hipLaunchKernelGGL((k_rhs<T, K, false, false, 2>), gr, bl, 0, c->stream, a, *st);
+            } else {
+                if (direct) hipLaunchKernelGGL((k_rhs<T, K, true, false, 1>), gr, bl, 0, c->stream, a, *st);
+                else hipLaunchKernelGGL((k_rhs<T, K, false, false, 1>), gr, bl, 0, c->stream, a, *st);
+            }
+            done = true;
+        }
         if constexpr (sizeof(T) == 4 && K == 2) {
             // volume integral on the matrix cores (tables in the pencil form or no driving)
-            if ((c->cfg.flags & DG_VOLUME_MFMA) && !direct) {
-                hipLaunchKernelGGL((k_rhs<T, K, false, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+            if (!done && (c->cfg.flags & DG_VOLUME_MFMA) && !direct) {
+                hipLaunchKernelGGL((k_rhs<T, K, false, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a, st0);
                 done = true;
             }
         }
         if (!done) {
-            if (direct) hipLaunchKernelGGL((k_rhs<T, K, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
-            else hipLaunchKernelGGL((k_rhs<T, K, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+            if (direct) hipLaunchKernelGGL((k_rhs<T, K, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a, st0);
+            else hipLaunchKernelGGL((k_rhs<T, K, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a, st0);
         }
     }
     LAUNCHCHK(c);
@@ -700,19 +721,24 @@ static bool use_meanfree(const dg_ctx *c)
     return (c->cfg.flags & DG_FORCING) && (c->cfg.flags & DG_FORCE_MEANFREE) && c->nmodes > 0;
 }
 
-static int launch_abar(dg_ctx *c)
+// the removed mean acceleration from per-block partials: by default the right-hand side's
+static int launch_abar(dg_ctx *c, const double *part = nullptr, int np = 0)
 {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, (const double *)c->wp(c->off.part), c->rhs_nblk, 1,
-                       1.0, 0.0, c->abar(), (const int *)nullptr, (volatile long long *)nullptr, 0LL, (const double *)nullptr, 0);
+    if (!part) {
+        part = (const double *)c->wp(c->off.part);
+        np = c->rhs_nblk;
+    }
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(BLOCK), 0, c->stream, part, np, 1, 1.0, 0.0, c->abar(),
+                       (const int *)nullptr, (volatile long long *)nullptr, 0LL, (const double *)nullptr, 0);
     LAUNCHCHK(c);
     return DG_OK;
 }
 
-template <typename T, int K>
-static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
-                        bool skip_if_failed, const double (&coef)[3], double dt, long long *nlim, double *part = nullptr,
-                        void *w = nullptr, const double (&wcoef)[3] = {0.0, 0.0, 0.0},
-                        const double *dt_dev = nullptr)
+// the arguments of one stage (k_stage, or the fused stage of k_rhs: L is then not read, and
+// with mean-free driving the partials or the mean are those of ui)
+static StageArgs stage_args(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
+                            bool skip_if_failed, const double (&coef)[3], double dt, long long *nlim, double *part,
+                            void *w, const double (&wcoef)[3], const double *dt_dev, bool fused = false)
 {
     StageArgs a;
     a.ui = ui;
@@ -725,10 +751,12 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.tab = c->tab;
     // abar_in_stage: every block reduces the right-hand side's partials to the removed mean
     // acceleration itself (no separate reduction kernel)
-    const bool mf = L && use_meanfree(c);
+    // (a stage whose combination the right-hand-side kernel forms reads the partials of its
+    // input from the region k_drive_parts and k_limit_project write)
+    const bool mf = (L || fused) && use_meanfree(c);
     a.abar = mf && !c->abar_in_stage ? c->abar() : nullptr;
-    a.abar_part = mf && c->abar_in_stage ? (const double *)c->wp(c->off.part) : nullptr;
-    a.abar_np = c->rhs_nblk;
+    a.abar_part = mf && c->abar_in_stage ? (const double *)c->wp(fused ? c->off.dpart : c->off.part) : nullptr;
+    a.abar_np = fused ? c->nblk : c->rhs_nblk;
     a.fail = c->fail();
     a.nlim = nlim;
     a.part = part;
@@ -747,6 +775,20 @@ static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L
     a.dt_dev = dt_dev;
     a.rho_floor = c->cfg.rho_floor;
     a.rho_floor_rel = c->cfg.rho_floor_rel;
+    a.drive_part = nullptr;
+    a.ftab = c->wp(c->off.ftab);
+    a.modes = c->modes_dev;
+    a.nmodes = c->nmodes;
+    return a;
+}
+
+template <typename T, int K>
+static int launch_stage(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
+                        bool skip_if_failed, const double (&coef)[3], double dt, long long *nlim, double *part = nullptr,
+                        void *w = nullptr, const double (&wcoef)[3] = {0.0, 0.0, 0.0},
+                        const double *dt_dev = nullptr)
+{
+    const StageArgs a = stage_args(c, ui, un, L, out, vh_out, skip_if_failed, coef, dt, nlim, part, w, wcoef, dt_dev);
     int rc = prof_mark(c, 1, 0);
     if (rc) return rc;
     // u^n enters when its coefficient is not zero; the side combination when it has an output
@@ -874,6 +916,61 @@ static const Scheme &scheme_of(const dg_ctx *c)
     return c->k == 1 ? SSPRK2 : (c->k == 2 ? SSPRK3 : SSPRK54);
 }
 
+// Whether a stage is split between its right-hand-side kernel, which forms the stage's
+// combination (k_rhs with FUSE), and k_limit_project, which limits and projects it, instead of
+// storing the right-hand side for a stage kernel: the one-lane kernel with the vector volume
+// integral, a stage without a side combination that writes a workspace buffer other than its
+// input (the last stage writes the caller's array, which must keep u^n when the step fails:
+// its failure is decided before its stage kernel runs), and not turned off by
+// DG_SEPARATE_STAGE.  Split and separate stages give the same bits.
+// The split pays where the right-hand side is long against the stage's memory time: measured
+// on one MI355X, 256^3 degree 2 FP64 steps 44.5 -> 43.7 ms; FP32 at 256^3 unchanged, slower at
+// 128^3 FP32 (2.74 -> 2.81 ms) and 64^3 FP64 (0.79 -> 0.83 ms).
+constexpr long long SPLIT_MIN_CELLS = 1LL << 22;
+
+template <typename T, int K>
+static bool fuse_stage(const dg_ctx *c, const StageSpec &g, bool last)
+{
+    if (rhs_pair<T, K>() || last || g.w || g.out == 0 || g.out == g.in) return false;
+    if (c->cfg.flags & (DG_SEPARATE_STAGE | DG_VOLUME_MFMA)) return false;
+    if (c->cfg.flags & DG_SPLIT_STAGE) return true;
+    return sizeof(T) == 8 && (long long)c->nc >= SPLIT_MIN_CELLS;
+}
+
+// whether split stage s leaves the partials of its result for stage s + 1 (k_limit_project):
+// the next stage is split too and reads that result, and the driving table is in the pencil form
+template <typename T, int K>
+static bool next_split_partials(const dg_ctx *c, const Scheme &S, int s)
+{
+    return s + 1 < S.stages && S.s[s + 1].in == S.s[s].out && c->modes_sep &&
+           fuse_stage<T, K>(c, S.s[s + 1], s + 1 == S.stages - 1);
+}
+
+// the mean-acceleration partials of u alone (k_drive_parts) into the split stages' region
+template <typename T, int K>
+static int launch_drive_parts(dg_ctx *c, const void *u, int *fail_reset)
+{
+    if ((c->cfg.flags & DG_FORCING) && c->forcing_dirty) {
+        int rc = launch_forcing_table<T, K>(c);
+        if (rc) return rc;
+        c->forcing_dirty = false;
+    }
+    RhsArgs a{};
+    a.u = u;
+    a.tab = c->tab;
+    a.ftab = c->wp(c->off.ftab);
+    a.modes = c->modes_dev;
+    a.nmodes = c->nmodes;
+    a.part = (double *)c->wp(c->off.dpart);
+    a.fail_reset = fail_reset;
+    a.g = Mesh{c->cfg.nx, c->cfg.ny, c->cfg.nz, c->nc};
+    a.h = c->cfg.h;
+    if (!c->modes_sep) hipLaunchKernelGGL((k_drive_parts<T, K, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    else hipLaunchKernelGGL((k_drive_parts<T, K, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, a);
+    LAUNCHCHK(c);
+    return DG_OK;
+}
+
 // Stage s of the scheme: right-hand side, mean acceleration, stage kernel.  reset_fail:
 // this right-hand side clears the failure flag (a first stage starting from a kept
 // projection); want_next: the step also returns the next time step (the last stage keeps the
@@ -887,11 +984,49 @@ static int launch_step_stage(dg_ctx *c, void *u, int s, double dt, bool reset_fa
     void *buf[4] = {u, c->wp(c->off.stA), c->wp(c->off.stB), c->wp(c->off.stC)};
     const StageSpec &g = S.s[s];
     const bool last = s == S.stages - 1;
+    if constexpr (!rhs_pair<T, K>()) if (fuse_stage<T, K>(c, g, last)) {
+        int rc = DG_OK;
+        int *reset = reset_fail ? c->fail() : nullptr;
+        const bool mf = use_meanfree(c);
+        const bool in_stage = c->nblk <= ABAR_IN_STAGE_BLOCKS;
+        // the mean acceleration of the input: its partials come from the previous split stage's
+        // k_limit_project, else from k_drive_parts; more blocks than a block reduces itself go
+        // through one reduction kernel
+        const bool prev_split = s > 0 && next_split_partials<T, K>(c, S, s - 1);
+        if (mf && !prev_split) {
+            if ((rc = launch_drive_parts<T, K>(c, buf[g.in], reset))) return rc;
+            reset = nullptr;
+        }
+        if (reset) {
+            hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, c->stream, reset);
+            LAUNCHCHK(c);
+        }
+        if (mf && !in_stage && (rc = launch_abar(c, (const double *)c->wp(c->off.dpart), c->nblk))) return rc;
+        c->abar_in_stage = in_stage;
+        StageArgs st = stage_args(c, buf[g.in], buf[g.un], nullptr, buf[g.out], vh[(s + 1) & 1], false, g.coef, dt,
+                                  nullptr, nullptr, nullptr, g.wcoef, dt_dev, true);
+        c->abar_in_stage = false;
+        c->prof_first = s == 0;
+        c->prof_last = false;
+        if ((rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], nullptr, dt, nullptr, nullptr, dt_dev, &st))) return rc;
+        // the next stage's partials, when it is split too and reads this stage's result (tables
+        // in the pencil form: the mode-by-mode field costs too many registers there, and the
+        // next stage runs k_drive_parts)
+        st.drive_part = mf && next_split_partials<T, K>(c, S, s) ? (double *)c->wp(c->off.dpart) : nullptr;
+        if ((rc = prof_mark(c, 1, 0))) return rc;
+        if (st.drive_part)
+            hipLaunchKernelGGL((k_limit_project<T, K, true>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, st);
+        else
+            hipLaunchKernelGGL((k_limit_project<T, K, false>), dim3(c->nblk), dim3(BLOCK), 0, c->stream, st);
+        LAUNCHCHK(c);
+        return prof_mark(c, 1, 1);
+    }
     // learned sensor: the network's viscosity of the new state serves its time step (and the
     // next step's stages).  The last stage reduces the signal speeds and the fallback cells'
     // viscosities; the network's forward pass on the new state reduces the learned cells'.
     const bool learned_next = want_next && (c->cfg.flags & DG_LEARNED_SENSOR);
     c->prof_first = s == 0;
+    c->prof_last = last;
     // the last stage writes the caller's array: its failure is decided by its right-hand
     // side, so that on failure the stage kernel leaves u^n in place (no copy to restore)
     const StagePred pred{buf[g.un], g.coef};
@@ -910,6 +1045,7 @@ static int launch_step_stage(dg_ctx *c, void *u, int s, double dt, bool reset_fa
     double *part = (last && want_next) ? (double *)c->wp(c->off.spart) : nullptr;
     c->learned_bounds_later = learned_next && last;
     c->abar_in_stage = in_stage;
+    c->prof_last = false;
     rc = launch_stage<T, K>(c, buf[g.in], buf[g.un], c->wp(c->off.L), buf[g.out], vnext, last, g.coef, dt, nullptr,
                             part, g.w ? buf[g.w] : nullptr, g.wcoef, dt_dev);
     c->learned_bounds_later = false;
@@ -988,6 +1124,15 @@ static int do_step(dg_ctx *c, void *u, double dt, int *status_host, bool reuse, 
     return DG_OK;
 }
 
+template <typename T, int K>
+static int split_stages_impl(const dg_ctx *c)
+{
+    const Scheme &S = scheme_of(c);
+    for (int s = 0; s < S.stages; ++s)
+        if (fuse_stage<T, K>(c, S.s[s], s == S.stages - 1)) return 1;
+    return 0;
+}
+
 #define DISPATCH(c, FN, ...)                                                        \
     ((c)->es == 8 ? ((c)->k == 1   ? FN<double, 1>(__VA_ARGS__)                     \
                      : (c)->k == 2 ? FN<double, 2>(__VA_ARGS__)                     \
@@ -1045,6 +1190,12 @@ int dg_rk_step_next_ahead(dg_ctx *c, void *u, double dt, int reuse, double horiz
     if (std::isnan(horizon)) return dg_fail(c, DG_EINVAL, "horizon is NaN");
     if ((rc = learned_ready(c))) return rc;
     return DISPATCH(c, do_step, c, u, dt, status_host, reuse != 0, dt_next_host, horizon);
+}
+
+int dg_split_stages(const dg_ctx *c)
+{
+    if (!c) return DG_EINVAL;
+    return DISPATCH(c, split_stages_impl, c);
 }
 
 template <typename T, int K>

@@ -11,7 +11,7 @@
 constexpr int MLP_PART_ROWS = 1024;
 
 struct dg_offsets {
-    size_t stA, stB, stC, L, vh0, vh1, ftab, nu, fb, feat, lab, mlp, part, spart, scal, iflags;
+    size_t stA, stB, stC, L, vh0, vh1, ftab, nu, fb, feat, lab, mlp, part, spart, dpart, scal, iflags;
 };
 
 struct dg_ctx {
@@ -57,6 +57,7 @@ struct dg_ctx {
     static constexpr int NEV = 64;
     int prof = 0;                      // 0 off, 1 first-stage right-hand sides, 2 every launch
     bool prof_first = false;           // the launch being issued belongs to a first stage
+    bool prof_last = false;            // the right-hand side being issued belongs to a last stage
     hipEvent_t ev[2 * NEV][2] = {};    // [slot][start/stop]
     int ev_kind[2 * NEV] = {};         // 0 = rhs kernel, 1 = stage kernel
     int nev = 0;

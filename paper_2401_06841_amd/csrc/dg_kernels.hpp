@@ -286,6 +286,12 @@ struct StageArgs {
     double ca, cb, cc, dt, rho_floor, rho_floor_rel;
     double wa, wb, wc;
     const double *dt_dev;   // the time step in device memory (a stage launched ahead), or NULL: dt
+    // k_limit_project: the mean-acceleration partials of the result for the next stage
+    // (drive_part [nblocks][4], or NULL) and the driving field they take
+    double *drive_part;
+    const void *ftab;
+    const double *modes;
+    int nmodes;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -627,20 +633,23 @@ struct PencilLayout {
 
 // a at volume point q (q = t_x + N1 (t_y + N1 t_z)) from the pencil table: g = this pencil's
 // block, (pr, pi) = the cell's phase P
+// (roundings fixed by explicit fused multiply-adds: every kernel that evaluates the field gets
+// the same bits)
 template <typename T, int K>
 __device__ __forceinline__ void pencil_accel(ctab<T> *ft, ctab<T> *g, int q, T pr, T pim, T (&acc)[3])
 {
+#pragma clang fp contract(off)
     using PL = PencilLayout<K>;
     const int tx = q % PL::N1, tt = q / PL::N1;
     const T er = ft[2 * tx], ei = ft[2 * tx + 1];
-    const T xr = pr * er - pim * ei;
-    const T xi = pr * ei + pim * er;
-    const T x2r = xr * xr - xi * xi;
-    const T x2i = T(2) * xr * xi;
+    const T xr = fma(pr, er, -(pim * ei));
+    const T xi = fma(pr, ei, pim * er);
+    const T x2r = fma(xr, xr, -(xi * xi));
+    const T x2i = (T(2) * xr) * xi;
     ctab<T> *e = g + tt * PL::ENT;
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        acc[d] = e[5 * d] + e[5 * d + 1] * xr - e[5 * d + 2] * xi + e[5 * d + 3] * x2r - e[5 * d + 4] * x2i;
+        acc[d] = fma(-e[5 * d + 4], x2i, fma(e[5 * d + 3], x2r, fma(-e[5 * d + 2], xi, fma(e[5 * d + 1], xr, e[5 * d]))));
 }
 
 // a at the point with reference coordinates xi of cell (i, j, l), mode by mode (any table)
@@ -648,6 +657,7 @@ template <typename T>
 __device__ __forceinline__ void direct_accel(const double *modes, int nmodes, const int (&ijk)[3], T xq, T yq, T zq,
                                              double h, T (&acc)[3])
 {
+#pragma clang fp contract(off)
     const double x = (ijk[0] + 0.5 + 0.5 * (double)xq) * h;
     const double y = (ijk[1] + 0.5 + 0.5 * (double)yq) * h;
     const double z = (ijk[2] + 0.5 + 0.5 * (double)zq) * h;
@@ -671,6 +681,22 @@ __device__ __forceinline__ void cell_phase(ctab<T> *px, int i, T &pr, T &pim)
 {
     pr = px[2 * i];
     pim = px[2 * i + 1];
+}
+
+// The driving source of one volume point, s = (rho w_q) a, and the running sums of the
+// cell's source for the removed mean acceleration, every rounding fixed (no contraction):
+// the sums come out the same in every kernel that forms them.
+template <typename T>
+__device__ __forceinline__ void drive_point(T rho, T wq, const T (&ac)[3], T (&s)[3], T &fs0, T &fs1, T &fs2)
+{
+#pragma clang fp contract(off)
+    const T rw = rho * wq;
+    s[0] = rw * ac[0];
+    s[1] = rw * ac[1];
+    s[2] = rw * ac[2];
+    fs0 = fs0 + s[0];
+    fs1 = fs1 + s[1];
+    fs2 = fs2 + s[2];
 }
 
 // Driving field forms of the right-hand-side kernels' volume loop
@@ -885,9 +911,18 @@ __device__ __forceinline__ void volume_mfma(const RhsArgs &a, ctab<float> *tab, 
 template <typename T, int K, bool VMFMA = false>
 constexpr int rhs_waves() { return VMFMA ? MFMA_WAVES : (sizeof(T) == 8 ? (K <= 2 ? 2 : 1) : (K <= 2 ? 4 : 2)); }
 
-template <typename T, int K, bool FDIRECT, bool VMFMA = false>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K, VMFMA>()))) k_rhs(RhsArgs a)
+template <typename T, int K, bool UNV>
+__device__ __forceinline__ void fused_stage(const void *ui, T (&L)[4][Shape<K>::NB], T inv4h, double dt,
+                                            const StageArgs &st, bool active, unsigned bo, double *lds);
+
+// FUSE: 0 stores the right-hand side (and the mean-acceleration partials); 1 and 2 go on with
+// the combination of the stage st of a Runge-Kutta step for the cell (fused_stage; 2: u^n
+// enters) and store nothing of the right-hand side
+template <typename T, int K, bool FDIRECT, bool VMFMA = false, int FUSE = 0>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K, VMFMA>())))
+k_rhs(RhsArgs a, StageArgs st)
 {
+    static_assert(!(FUSE && VMFMA), "fused stages: vector volume integral only");
     using S = Shape<K>;
     using TL = TabLayout<K>;
     constexpr Modes<K> M = make_modes<K>();
@@ -1032,12 +1067,9 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
                                     tab[TL::VXI + 3 * q + 2], a.h, ac);
                 else
                     pencil_accel<T, K>(ft, g, q, pr, pim, ac);
-                const T rw = rho * wq;
-                const T s0 = rw * ac[0];
-                const T s1 = rw * ac[1];
-                const T s2 = rw * ac[2];
-                fs0 += s0; fs1 += s1; fs2 += s2;
-                const T t0 = s0 * half_h, t1 = s1 * half_h, t2 = s2 * half_h;
+                T sp[3];
+                drive_point<T>(rho, wq, ac, sp, fs0, fs1, fs2);
+                const T t0 = sp[0] * half_h, t1 = sp[1] * half_h, t2 = sp[2] * half_h;
 #pragma unroll
                 for (int l = 0; l < NB; ++l) {
                     const T p = ph[l];
@@ -1105,22 +1137,29 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
         face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L, col);
 
     const T inv4h = (T)(0.25 / a.h);
-    if (active) {
-        const Field<T, 4> O(a.out, NB, nc);
+    if constexpr (FUSE != 0) {
+        (void)mass0;
+        __shared__ double lds_st[20];
+        fused_stage<T, K, FUSE == 2>(a.u, L, inv4h, dt, st, active, bo, lds_st);
+    } else {
+        (void)st;
+        if (active) {
+            const Field<T, 4> O(a.out, NB, nc);
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+            for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int l = 0; l < NB; ++l) O.put_nt(v, l, bo, L[v][l] * inv4h);
-        if (a.pred_fail) predict_failure<T>(a, dt, c, mass0, L[0][0] * inv4h);
-    }
-    if (force && a.part) {
-        const bool fsok = active || VMFMA;     // the matrix-core sums are masked per tile cell
-        double acc[4] = {fsok ? 0.125 * (double)fs0 : 0.0, fsok ? 0.125 * (double)fs1 : 0.0,
-                         fsok ? 0.125 * (double)fs2 : 0.0, active ? (double)mass0 : 0.0};
-        block_sum<4>(acc, lds);
-        if (threadIdx.x == 0)
+                for (int l = 0; l < NB; ++l) O.put_nt(v, l, bo, L[v][l] * inv4h);
+            if (a.pred_fail) predict_failure<T>(a, dt, c, mass0, L[0][0] * inv4h);
+        }
+        if (force && a.part) {
+            const bool fsok = active || VMFMA;     // the matrix-core sums are masked per tile cell
+            double acc[4] = {fsok ? 0.125 * (double)fs0 : 0.0, fsok ? 0.125 * (double)fs1 : 0.0,
+                             fsok ? 0.125 * (double)fs2 : 0.0, active ? (double)mass0 : 0.0};
+            block_sum<4>(acc, lds);
+            if (threadIdx.x == 0)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a.part[blk * 4 + i] = acc[i];
+                for (int i = 0; i < 4; ++i) a.part[blk * 4 + i] = acc[i];
+        }
     }
 }
 
@@ -1526,7 +1565,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_
 // interior points, and bulk viscosity alpha (h/p)^2 |div v| + beta cs h/p at compressing
 // points (or the learned cell viscosity where the learned sensor is in use), written to
 // part[2 blk] and part[2 blk + 1].  With part set every thread of the block must call it.
-template <typename T, int K>
+template <typename T, int K, bool SPLIT = split_projection<T>()>
 __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB], ctab<T> *tab, void *vh, int nc,
                                                    unsigned bo, int c, bool active, const ProjArgs &pa,
                                                    double *part, int blk, double *lds)
@@ -1575,7 +1614,7 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
                     for (int t = 0; t < DivMap<K>::MAXT; ++t)
                         if (DM.m[d][l][t] >= 0) Dv[DM.m[d][l][t]] += V[l] * T(__builtin_sqrt(double(DM.f[d][l][t])));
         };
-        if constexpr (split_projection<T>()) {
+        if constexpr (SPLIT) {
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 T V[NB];
@@ -1629,7 +1668,182 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
     }
 }
 
+// The driving source of a cell summed over its volume points (times 1/8) and its mean
+// density, from its density weights W0, with the arithmetic of the right-hand side's volume
+// loop: the point densities summed mode by mode in the same order, the source through
+// drive_point and pencil_accel or direct_accel.  acc[0..2]: source, acc[3]: mean density (all
+// 0 for an inactive lane).
+template <typename T, int K, bool FDIRECT>
+__device__ __forceinline__ void drive_sums(const T (&W0)[Shape<K>::NB], ctab<T> *tab, ctab<T> *ft,
+                                           const double *modes, int nmodes, const Mesh &g, double h, int c,
+                                           bool active, double (&acc)[4])
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr int NB = S::NB;
+    const int pencil = c / g.nx;
+    const int cijk[3] = {c % g.nx, pencil % g.ny, pencil / g.ny};
+    T pr = T(0), pim = T(0);
+    if (!FDIRECT) cell_phase<T>(ft + PencilLayout<K>::phases(g.ny, g.nz), cijk[0], pr, pim);
+    T fs0 = T(0), fs1 = T(0), fs2 = T(0);
+    auto sums = [&](auto form, int pen) {
+        constexpr int FM = decltype(form)::value;
+        ctab<T> *gp = ft + PencilLayout<K>::HDR + (size_t)pen * PencilLayout<K>::STRIDE;
+#pragma unroll 1
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<T> *ph = tab + TL::VPHI + q * NB;
+            const T wq = tab[TL::VW + q];
+            T rho = T(0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) rho += W0[l] * ph[l];
+            T ac[3];
+            if constexpr (FM == FM_DIRECT)
+                direct_accel<T>(modes, nmodes, cijk, tab[TL::VXI + 3 * q], tab[TL::VXI + 3 * q + 1],
+                                tab[TL::VXI + 3 * q + 2], h, ac);
+            else
+                pencil_accel<T, K>(ft, gp, q, pr, pim, ac);
+            T sp[3];
+            drive_point<T>(rho, wq, ac, sp, fs0, fs1, fs2);
+        }
+    };
+    if constexpr (FDIRECT) {
+        sums(std::integral_constant<int, FM_DIRECT>{}, 0);
+    } else {
+        const int p0 = __shfl(pencil, 0, 64);
+        if (__all(!active || pencil == p0))
+            sums(std::integral_constant<int, FM_UNIFORM>{}, __builtin_amdgcn_readfirstlane(p0));
+        else
+            sums(std::integral_constant<int, FM_LANE>{}, pencil);
+    }
+    acc[0] = active ? 0.125 * (double)fs0 : 0.0;
+    acc[1] = active ? 0.125 * (double)fs1 : 0.0;
+    acc[2] = active ? 0.125 * (double)fs2 : 0.0;
+    acc[3] = active ? (double)W0[0] : 0.0;
+}
+
 // --------------------------------------------------------------- stage kernel
+// The removed mean acceleration of a stage (Sec. 4.2, mean-free driving): given in abar, or
+// reduced here from the per-block partials of the stage input (every thread of the block
+// must call it then), or zero.
+template <typename T>
+__device__ __forceinline__ void stage_abar(const StageArgs &a, T (&ab)[3], double *lds_ab)
+{
+    ab[0] = ab[1] = ab[2] = T(0);
+    if (a.abar) { ab[0] = (T)a.abar[0]; ab[1] = (T)a.abar[1]; ab[2] = (T)a.abar[2]; }
+    if (a.abar_part) {
+        // the mass-weighted mean acceleration, as k_final computes it
+        double sum[4];
+        block_partial_sums4(a.abar_part, a.abar_np, sum, lds_ab);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) lds_ab[16 + k] = sum[k] / sum[3];
+        __syncthreads();
+        ab[0] = (T)lds_ab[16];
+        ab[1] = (T)lds_ab[17];
+        ab[2] = (T)lds_ab[18];
+    }
+}
+
+// Positivity limiter of one cell after a stage (Sec. 3.1; target minimum
+// max(floor, rel * mean)) with FP64 comparisons.  With a.nlim set every thread of the block
+// must call it.
+template <typename T, int K>
+__device__ __forceinline__ bool stage_limit(T (&U)[4][Shape<K>::NB], ctab<T> *tab, const StageArgs &a, bool active,
+                                            double *lds)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr Modes<K> M = make_modes<K>();
+    constexpr int NB = S::NB;
+    const double mean = (double)U[0][0];
+    const double fl = a.rho_floor;
+    const double target = fmax(fl, a.rho_floor_rel * mean);
+    // The density at any point of the cell differs from the mean by at most
+    // dev = sum_{l>0} |W_l| max|phi_l|, with max|phi_l| = prod_a sqrt(2 e_a + 1) (the
+    // normalised Legendre polynomials peak at the cell faces).  When mean - dev clears
+    // the target with a margin for the rounding of the point sums, the minimum below
+    // cannot fall short of the target and the limiter leaves the cell as it is; a wave
+    // whose cells all clear it skips the point evaluations (same result).
+    double dev = 0.0;
+#pragma unroll
+    for (int l = 1; l < NB; ++l) {
+        double pm = 1.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) pm *= __builtin_sqrt(2.0 * M.e[l][d] + 1.0);
+        dev += fabs((double)U[0][l]) * pm;
+    }
+    constexpr double EPS = sizeof(T) == 8 ? 1e-13 : 1e-5;
+    const bool clear = !active || mean - dev - EPS * (fabs(mean) + dev) >= target;
+    // minimum density over the volume and face Gauss points
+    T rmin = T(__builtin_huge_valf());
+    if (!__all(clear)) {
+#pragma unroll 1
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<T> *ph = tab + TL::VPHI + q * NB;
+            T r = T(0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) r += U[0][l] * ph[l];
+            rmin = fmin(rmin, r);
+        }
+        ctab<T> *lend = tab + TL::LEND;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                T C[S::NB2];
+#pragma unroll
+                for (int j = 0; j < S::NB2; ++j) C[j] = T(0);
+#pragma unroll
+                for (int l = 0; l < NB; ++l) C[M.d2[d][l]] += U[0][l] * lend[2 * M.e[l][d] + s];
+#pragma unroll 1
+                for (int r = 0; r < S::NF; ++r) {
+                    ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
+                    T val = T(0);
+#pragma unroll
+                    for (int j = 0; j < S::NB2; ++j) val += C[j] * f2[j];
+                    rmin = fmin(rmin, val);
+                }
+            }
+    }
+    const double rm = (double)rmin;
+    int bad = 0;
+    bool changed = false;
+    if (!(mean > fl)) {
+        bad = active ? 1 : 0;
+    } else if (rm < target) {
+        const T theta = (T)((mean - target) / (mean - rm));
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int l = 1; l < NB; ++l) U[v][l] *= theta;
+        changed = true;
+    }
+    if (bad) atomicOr(a.fail, 1);
+    if (a.nlim) {
+        double cnt[1] = {(double)bad};
+        block_sum<1>(cnt, lds);
+        if (threadIdx.x == 0 && cnt[0] > 0.0) atomicAdd((unsigned long long *)a.nlim, (unsigned long long)cnt[0]);
+    }
+    return changed;
+}
+
+// What follows the combination in every stage: the limiter, the new weights, their density
+// copy and their projected velocity (with the time-step maxima when a.part is set).  SPLIT:
+// project one velocity component at a time (fewer live registers; the same bits).
+template <typename T, int K, bool SPLIT = split_projection<T>()>
+__device__ __forceinline__ void stage_finish(T (&U)[4][Shape<K>::NB], ctab<T> *tab, const StageArgs &a, unsigned bo,
+                                             int c, bool active, int blk, double *lds)
+{
+    constexpr int NB = Shape<K>::NB;
+    const int nc = a.g.nc;
+    if (a.flags & F_LIMIT) stage_limit<T, K>(U, tab, a, active, lds);
+    if (active) store_field<T, K, 4>(Field<T, 4>(a.out, NB, nc), bo, U);
+    if (a.rho_out && active)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) ((T *)a.rho_out)[(size_t)l * nc + c] = U[0][l];
+    if (a.vh_out) project_and_bounds<T, K, SPLIT>(U, tab, a.vh_out, nc, bo, c, active, a.pa, a.part, blk, lds);
+}
+
 // out = ca*un + cb*ui + cc*dt*R with R = L - abar W_rho (one stage of an SSP Runge-Kutta
 // scheme in Shu-Osher form), optionally a side combination w = wa*w_src + wb*ui + wc*dt*R
 // of the same operands, then the positivity limiter (Sec. 3.1; target minimum
@@ -1644,8 +1858,6 @@ template <typename T, int K, bool UNV, bool SIDE>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stage_waves<T, K>()))) k_stage(StageArgs a)
 {
     using S = Shape<K>;
-    using TL = TabLayout<K>;
-    constexpr Modes<K> M = make_modes<K>();
     constexpr int NB = S::NB;
     __shared__ double lds[4];
     __shared__ double lds_ab[20];
@@ -1667,38 +1879,22 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         const Field<T, 4> UN(a.un, NB, nc);
         const double dt = a.dt_dev ? *a.dt_dev : a.dt;
         const T ca = (T)a.ca, cb = (T)a.cb, cdt = (T)(a.cc * dt);
-        T ab[3] = {T(0), T(0), T(0)};
-        if (a.abar) { ab[0] = (T)a.abar[0]; ab[1] = (T)a.abar[1]; ab[2] = (T)a.abar[2]; }
-        if (a.abar_part) {
-            // the mass-weighted mean acceleration, as k_final computes it
-            double sum[4];
-            block_partial_sums4(a.abar_part, a.abar_np, sum, lds_ab);
-            if (threadIdx.x == 0)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) lds_ab[16 + k] = sum[k] / sum[3];
-            __syncthreads();
-            ab[0] = (T)lds_ab[16];
-            ab[1] = (T)lds_ab[17];
-            ab[2] = (T)lds_ab[18];
-        }
-        const bool use_un = a.ca != 0.0;
-        const bool side = a.w_out != nullptr;
-        const Field<T, 4> WS(side ? a.w_src : a.ui, NB, nc);
-        const Field<T, 4> WO(side ? a.w_out : a.ui, NB, nc);
+        T ab[3];
+        stage_abar<T>(a, ab, lds_ab);
+        const Field<T, 4> WS(SIDE ? a.w_src : a.ui, NB, nc);
+        const Field<T, 4> WO(SIDE ? a.w_out : a.ui, NB, nc);
         const T wa = (T)a.wa, wb = (T)a.wb, wcdt = (T)(a.wc * dt);
         // The combination of every weight, momentum first (the removed mean acceleration
         // multiplies the input density).  Whether u^n and the side combination enter is a
         // template choice (UNV, SIDE): with a branch per weight the compiler waited for each
-        // weight's loads in turn.
-        (void)use_un;
-        (void)side;
+        // weight's loads in turn.  The roundings are those of the fused stage of k_rhs.
 #pragma unroll
         for (int v = 3; v >= 0; --v)
 #pragma unroll
             for (int l = 0; l < NB; ++l) {
                 // the right-hand side and u^n are read once (non-temporal)
                 T rhs = LF.get_nt(v, l, bo);
-                if (v > 0) rhs -= ab[v - 1] * U[0][l];
+                if (v > 0) rhs = fma(-ab[v - 1], U[0][l], rhs);
                 const T ui = U[v][l];
                 if constexpr (SIDE) {
                     const T w = wa * WS.get(v, l, bo) + wb * ui + wcdt * rhs;
@@ -1712,80 +1908,186 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
                 if (l == NB - 1) __builtin_amdgcn_sched_barrier(0);
             }
     }
+    stage_finish<T, K>(U, tab, a, bo, c, active, blk, lds);
+}
+
+// The combination of a stage formed in the right-hand-side kernel (k_rhs with FUSE): k_stage's
+// u^(i+1) = ca un + cb ui + cdt (L - abar W_rho) for the cell whose right-hand side the kernel
+// has just formed, with 4h dw/dt in L (it becomes the new weights) in place of the stored
+// right-hand side and the same roundings, stored into st.out unlimited.  k_limit_project then
+// limits and projects the result, so that the two kernels write the bits of the separate
+// right-hand side and stage kernels.  The input weights are read again (they are not kept
+// through the surface integral).  Every thread of the block calls it.
+template <typename T, int K, bool UNV>
+__device__ __forceinline__ void fused_stage(const void *ui, T (&L)[4][Shape<K>::NB], T inv4h, double dt,
+                                            const StageArgs &st, bool active, unsigned bo, double *lds)
+{
+    constexpr int NB = Shape<K>::NB;
+    const int nc = st.g.nc;
+    T ab[3];
+    stage_abar<T>(st, ab, lds);
+    const Field<T, 4> UI(ui, NB, nc);
+    const Field<T, 4> UN(st.un, NB, nc);
+    const T ca = (T)st.ca, cb = (T)st.cb, cdt = (T)(st.cc * dt);
+    const Field<T, 4> UO(st.out, NB, nc);
+    T R0[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) R0[l] = UI.get(0, l, bo);
+    // variable by variable, each stored as soon as it is formed (its registers are free then)
+#pragma unroll
+    for (int v = 3; v >= 0; --v)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            // the value the separate right-hand side stores
+            T rhs = L[v][l] * inv4h;
+            if (v > 0) rhs = fma(-ab[v - 1], R0[l], rhs);
+            const T u = v ? UI.get_nt(v, l, bo) : R0[l];
+            const T x = fma(cdt, rhs, cb * u);
+            T w;
+            if constexpr (UNV) w = fma(ca, UN.get_nt(v, l, bo), x);
+            else w = x;
+            if (active) UO.put(v, l, bo, w);
+            if (l == NB - 1) __builtin_amdgcn_sched_barrier(0);
+        }
+}
+
+// The rest of a stage whose combination the right-hand-side kernel has stored (a.out,
+// unlimited): the positivity limiter in place (a cell is written back only where it changes),
+// the projected velocity of the result (a.vh_out; project_cell's arithmetic), and with DRIVE
+// the mean-acceleration partials of the result for the next stage (block b: cells b BLOCK + t),
+// from the point densities of the same pass, as the right-hand side forms them (driving
+// table in the pencil form).  All three velocity components in one pass over the points: the
+// kernel is bound by that arithmetic.
+#ifndef LP_W64K2D
+#define LP_W64K2D 3
+#endif
+template <typename T, int K, bool DRIVE>
+constexpr int limit_project_waves()
+{
+    return sizeof(T) == 8 ? (K == 1 ? (DRIVE ? 5 : 6) : (K == 2 ? (DRIVE ? LP_W64K2D : 3) : 2))
+                          : (K == 1 ? 7 : (K == 2 ? 5 : 3));
+}
+
+template <typename T, int K, bool DRIVE>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(limit_project_waves<T, K, DRIVE>())))
+k_limit_project(StageArgs a)
+{
+    using S = Shape<K>;
+    using TL = TabLayout<K>;
+    constexpr int NB = S::NB;
+    __shared__ double lds[16];
+    const int nc = a.g.nc;
+    const int blk = blockIdx.x;
+    const int c0 = blk * BLOCK + threadIdx.x;
+    const bool active = c0 < nc;
+    const int c = active ? c0 : 0;
+    const unsigned bo = (unsigned)c * sizeof(T);
+    ctab<T> *tab = as_tab<T>(a.tab);
+    const Field<T, 4> UO(a.out, NB, nc);
+    T U[4][NB];
+    load_field<T, K, 4>(UO, bo, U);
     if (a.flags & F_LIMIT) {
-        const double mean = (double)U[0][0];
-        const double fl = a.rho_floor;
-        const double target = fmax(fl, a.rho_floor_rel * mean);
-        // The density at any point of the cell differs from the mean by at most
-        // dev = sum_{l>0} |W_l| max|phi_l|, with max|phi_l| = prod_a sqrt(2 e_a + 1) (the
-        // normalised Legendre polynomials peak at the cell faces).  When mean - dev clears
-        // the target with a margin for the rounding of the point sums, the minimum below
-        // cannot fall short of the target and the limiter leaves the cell as it is; a wave
-        // whose cells all clear it skips the point evaluations (same result).
-        double dev = 0.0;
-#pragma unroll
-        for (int l = 1; l < NB; ++l) {
-            double pm = 1.0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) pm *= __builtin_sqrt(2.0 * M.e[l][d] + 1.0);
-            dev += fabs((double)U[0][l]) * pm;
-        }
-        constexpr double EPS = sizeof(T) == 8 ? 1e-13 : 1e-5;
-        const bool clear = !active || mean - dev - EPS * (fabs(mean) + dev) >= target;
-        // minimum density over the volume and face Gauss points
-        T rmin = T(__builtin_huge_valf());
-        if (!__all(clear)) {
-#pragma unroll 1
-            for (int q = 0; q < S::NQ; ++q) {
-                ctab<T> *ph = tab + TL::VPHI + q * NB;
-                T r = T(0);
-#pragma unroll
-                for (int l = 0; l < NB; ++l) r += U[0][l] * ph[l];
-                rmin = fmin(rmin, r);
-            }
-            ctab<T> *lend = tab + TL::LEND;
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    T C[S::NB2];
-#pragma unroll
-                    for (int j = 0; j < S::NB2; ++j) C[j] = T(0);
-#pragma unroll
-                    for (int l = 0; l < NB; ++l) C[M.d2[d][l]] += U[0][l] * lend[2 * M.e[l][d] + s];
-#pragma unroll 1
-                    for (int r = 0; r < S::NF; ++r) {
-                        ctab<T> *f2 = tab + TL::F2 + r * S::NB2;
-                        T val = T(0);
-#pragma unroll
-                        for (int j = 0; j < S::NB2; ++j) val += C[j] * f2[j];
-                        rmin = fmin(rmin, val);
-                    }
-                }
-        }
-        const double rm = (double)rmin;
-        int bad = 0;
-        if (!(mean > fl)) {
-            bad = active ? 1 : 0;
-        } else if (rm < target) {
-            const T theta = (T)((mean - target) / (mean - rm));
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int l = 1; l < NB; ++l) U[v][l] *= theta;
-        }
-        if (bad) atomicOr(a.fail, 1);
-        if (a.nlim) {
-            double cnt[1] = {(double)bad};
-            block_sum<1>(cnt, lds);
-            if (threadIdx.x == 0 && cnt[0] > 0.0) atomicAdd((unsigned long long *)a.nlim, (unsigned long long)cnt[0]);
-        }
+        const bool changed = stage_limit<T, K>(U, tab, a, active, lds);
+        if (changed && active) store_field<T, K, 4>(UO, bo, U);
     }
-    if (active) store_field<T, K, 4>(Field<T, 4>(a.out, NB, nc), bo, U);
-    if (a.rho_out && active)
+    T V[3][NB];
 #pragma unroll
-        for (int l = 0; l < NB; ++l) ((T *)a.rho_out)[(size_t)l * nc + c] = U[0][l];
-    if (a.vh_out) project_and_bounds<T, K>(U, tab, a.vh_out, nc, bo, c, active, a.pa, a.part, blk, lds);
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) V[d][l] = T(0);
+    // driving field at the points (DRIVE): the cell's pencil and x phase, as in drive_sums
+    ctab<T> *ft = as_tab<T>(a.ftab);
+    const int pencil = c / a.g.nx;
+    const int cijk[3] = {c % a.g.nx, pencil % a.g.ny, pencil / a.g.ny};
+    T pr = T(0), pim = T(0);
+    if (DRIVE) cell_phase<T>(ft + PencilLayout<K>::phases(a.g.ny, a.g.nz), cijk[0], pr, pim);
+    T fs0 = T(0), fs1 = T(0), fs2 = T(0);
+    auto pass = [&](auto form, int pen) {
+        constexpr int FM = decltype(form)::value;
+        ctab<T> *gp = ft + PencilLayout<K>::HDR + (size_t)pen * PencilLayout<K>::STRIDE;
+#pragma unroll 1
+        for (int q = 0; q < S::NQ; ++q) {
+            ctab<T> *ph = tab + TL::VPHI + q * NB;
+            T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const T p = ph[l];
+                rho += U[0][l] * p;
+                m0 += U[1][l] * p;
+                m1 += U[2][l] * p;
+                m2 += U[3][l] * p;
+            }
+            const T ir = rcp(rho);
+            const T v0 = m0 * ir, v1 = m1 * ir, v2 = m2 * ir;
+            const T w = tab[TL::VW + q];
+            const T wq = T(0.125) * w;
+            const T a0 = wq * v0, a1 = wq * v1, a2 = wq * v2;
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const T p = ph[l];
+                V[0][l] += a0 * p;
+                V[1][l] += a1 * p;
+                V[2][l] += a2 * p;
+            }
+            if constexpr (DRIVE) {
+                (void)FM;
+                T ac[3];
+                pencil_accel<T, K>(ft, gp, q, pr, pim, ac);
+                T sp[3];
+                drive_point<T>(rho, w, ac, sp, fs0, fs1, fs2);
+            }
+        }
+    };
+    if constexpr (!DRIVE) {
+        (void)cijk;
+        pass(std::integral_constant<int, FM_LANE>{}, 0);
+    } else {
+        const int p0 = __shfl(pencil, 0, 64);
+        if (__all(!active || pencil == p0))
+            pass(std::integral_constant<int, FM_UNIFORM>{}, __builtin_amdgcn_readfirstlane(p0));
+        else
+            pass(std::integral_constant<int, FM_LANE>{}, pencil);
+    }
+    if (active) store_field<T, K, 3>(Field<T, 3>(a.vh_out, NB, nc), bo, V);
+    if constexpr (DRIVE) {
+        double acc[4] = {active ? 0.125 * (double)fs0 : 0.0, active ? 0.125 * (double)fs1 : 0.0,
+                         active ? 0.125 * (double)fs2 : 0.0, active ? (double)U[0][0] : 0.0};
+        block_sum<4>(acc, lds);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a.drive_part[blk * 4 + i] = acc[i];
+    }
+}
+
+// Per-block partial sums of the removed mean acceleration of a state alone (Sec. 4.2,
+// mean-free driving): the cell's driving source rho w_q a summed over the volume points (times
+// 1/8) and its mean density, the same values at the same block index as the right-hand-side
+// kernel forms in its volume loop (block b holds cells b BLOCK + t; the point densities summed mode by
+// mode in the same order; the source through drive_point and pencil_accel or direct_accel).
+// A fused stage needs the mean of its input before its kernel has formed any right-hand
+// side: this kernel runs first.  a.fail_reset: the failure flag to clear, or NULL.
+template <typename T, int K, bool FDIRECT>
+__global__ void __launch_bounds__(BLOCK) k_drive_parts(RhsArgs a)
+{
+    constexpr int NB = Shape<K>::NB;
+    __shared__ double lds[16];
+    const int nc = a.g.nc;
+    const int blk = blockIdx.x;
+    const int c0 = blk * BLOCK + threadIdx.x;
+    const bool active = c0 < nc;
+    const int c = active ? c0 : 0;
+    if (a.fail_reset && blk == 0 && threadIdx.x == 0) *a.fail_reset = 0;
+    const unsigned bo = (unsigned)c * sizeof(T);
+    const Field<T, 1> U(a.u, NB, nc);
+    T W0[NB];
+#pragma unroll
+    for (int l = 0; l < NB; ++l) W0[l] = U.get(0, l, bo);
+    double acc[4];
+    drive_sums<T, K, FDIRECT>(W0, as_tab<T>(a.tab), as_tab<T>(a.ftab), a.modes, a.nmodes, a.g, a.h, c, active, acc);
+    block_sum<4>(acc, lds);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a.part[blk * 4 + i] = acc[i];
 }
 
 // ------------------------------------------------------------ projection kernel
@@ -1952,6 +2254,9 @@ static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int 
         }
     }
 }
+
+// *f = 0 (a flag cleared on the stream, without a memset node)
+static __global__ void k_clear_flag(int *f) { *f = 0; }
 
 // dudt_m -= abar W_rho (mean-free driving applied to a stand-alone right-hand side)
 template <typename T, int K>

@@ -21,7 +21,7 @@ DG_OK, DG_RETRY = 0, 1
 DG_EINVAL, DG_EUNSUPPORTED, DG_EHIP, DG_ENOMEM, DG_ESTATE = -1, -2, -3, -4, -5
 DG_FP64, DG_FP32 = 0, 1
 DG_AV, DG_PRIM_PROJ, DG_FORCING, DG_POS_LIMITER, DG_LEARNED_SENSOR, DG_FORCE_MEANFREE = 1, 2, 4, 8, 16, 32
-DG_HLLC, DG_RK_BY_ORDER, DG_VOLUME_MFMA = 64, 128, 256
+DG_HLLC, DG_RK_BY_ORDER, DG_VOLUME_MFMA, DG_SEPARATE_STAGE, DG_SPLIT_STAGE = 64, 128, 256, 512, 1024
 DG_MLP_NIN, DG_MLP_NHID = 20, 64
 DG_MLP_NPARAM = 64 * 20 + 64 + 64 * 64 + 64 + 64 + 1
 
@@ -48,6 +48,7 @@ _SIGS = {
     "dg_last_error": (ctypes.c_char_p, [_vp]),
     "dg_set_wait_limit": (ctypes.c_int, [_vp, ctypes.c_double]),
     "dg_workspace_bytes": (ctypes.c_size_t, [_vp]),
+    "dg_split_stages": (ctypes.c_int, [_vp]),
     "dg_set_workspace": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t]),
     "dg_set_forcing": (ctypes.c_int, [_vp, _dp, ctypes.c_int]),
     "dg_rhs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_double]),
@@ -292,9 +293,17 @@ def dg_conserved_sums(ctx: Context, u):
 
 
 def dg_profile(ctx: Context, enable):
-    """enable: False/0 off, True/1 the first stage's right-hand side of each step, 2 every
-    right-hand-side and stage launch."""
+    """enable: False/0 off, True/1 the first stage's right-hand side of each step, 3 the last
+    stage's right-hand side of each step, 2 every right-hand-side and stage launch."""
     ctx._chk(_lib.dg_profile(ctx.h, int(enable)))
+
+
+def dg_split_stages(ctx: Context) -> bool:
+    """Whether the context's steps split their workspace stages (DG_SPLIT_STAGE or default)."""
+    r = _lib.dg_split_stages(ctx.h)
+    if r < 0:
+        ctx._chk(r)
+    return bool(r)
 
 
 def dg_profile_read(ctx: Context):

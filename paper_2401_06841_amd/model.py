@@ -61,6 +61,12 @@ def rhs_flops_per_cell(k: int, av: bool = True, proj: bool = True, forcing: bool
     return n
 
 
+def combination_flops_per_cell(k: int) -> int:
+    """The stage combination alone (5 per DOF, f = 4): the extra work of a right-hand-side
+    kernel that forms its stage's combination (split stages)."""
+    return 5 * 4 * nbasis(k)
+
+
 def stage_bytes_per_cell(k: int, elem_bytes: int) -> float:
     """Minimum HBM bytes of one stage averaged over the three SSP-RK3 stages:
     read u^(i) (and u^n for stages 2 and 3), write u^(i+1)."""

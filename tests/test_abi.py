@@ -39,7 +39,9 @@ def test_config_default_and_rejections_without_gpu():
     c.nx = 0
     assert dg._lib.dg_init(ctypes.byref(c), ctypes.byref(h)) == dg.DG_EINVAL
     c.nx = 16
-    c.flags = 512                                 # no such flag
+    c.flags = 2048                                # no such flag
+    assert dg._lib.dg_init(ctypes.byref(c), ctypes.byref(h)) == dg.DG_EINVAL
+    c.flags = dg.DG_SEPARATE_STAGE | dg.DG_SPLIT_STAGE   # separate and split stages at once
     assert dg._lib.dg_init(ctypes.byref(c), ctypes.byref(h)) == dg.DG_EINVAL
     assert dg._lib.dg_forcing_ou_ndraws() == 96
 
