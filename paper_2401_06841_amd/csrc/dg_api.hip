@@ -928,6 +928,8 @@ static const Scheme &scheme_of(const dg_ctx *c)
 // 128^3 FP32 (2.74 -> 2.81 ms) and 64^3 FP64 (0.79 -> 0.83 ms).
 constexpr long long SPLIT_MIN_CELLS = 1LL << 22;
 
+// (The last stage measured no gain split: its combination into a free buffer and k_stage from
+// there at 256^3 FP64 took 44.2 ms per step against 44.1 for the stored right-hand side.)
 template <typename T, int K>
 static bool fuse_stage(const dg_ctx *c, const StageSpec &g, bool last)
 {
@@ -937,13 +939,14 @@ static bool fuse_stage(const dg_ctx *c, const StageSpec &g, bool last)
     return sizeof(T) == 8 && (long long)c->nc >= SPLIT_MIN_CELLS;
 }
 
-// whether split stage s leaves the partials of its result for stage s + 1 (k_limit_project):
-// the next stage is split too and reads that result, and the driving table is in the pencil form
+// whether stage s is split and leaves the partials of its result for stage s + 1
+// (k_limit_project): the next stage is split too and reads that result, and the driving table
+// is in the pencil form
 template <typename T, int K>
 static bool next_split_partials(const dg_ctx *c, const Scheme &S, int s)
 {
     return s + 1 < S.stages && S.s[s + 1].in == S.s[s].out && c->modes_sep &&
-           fuse_stage<T, K>(c, S.s[s + 1], s + 1 == S.stages - 1);
+           fuse_stage<T, K>(c, S.s[s], s == S.stages - 1) && fuse_stage<T, K>(c, S.s[s + 1], s + 1 == S.stages - 1);
 }
 
 // the mean-acceleration partials of u alone (k_drive_parts) into the split stages' region

@@ -300,13 +300,15 @@ def _oracle_stage_minima(ocfg, u, dt):
     return out
 
 
+@pytest.mark.parametrize("split", [0, dg.DG_SPLIT_STAGE], ids=["default", "split"])
 @pytest.mark.parametrize("rel", [0.1, 0.0])
 @pytest.mark.parametrize("precision", [dg.DG_FP64, dg.DG_FP32])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_last_stage_failure_leaves_state(k, precision, rel):
+def test_last_stage_failure_leaves_state(k, precision, rel, split):
     """Only the last stage writes the caller's array, and its failure is decided from the
-    stage's density means before it writes: on DG_RETRY the array is bitwise the input."""
-    print(f"last-stage failure k={k} precision={precision} rel={rel}", flush=True)
+    stage's density means before it writes (also after split earlier stages): on DG_RETRY the
+    array is bitwise the input."""
+    print(f"last-stage failure k={k} precision={precision} rel={rel} split={split}", flush=True)
     u = synthetic.turbulent_like(6, 5, 4, k, mach=4.0, seed=0)
     if precision == dg.DG_FP32:
         u = u.astype(np.float32).astype(np.float64)
@@ -315,7 +317,7 @@ def test_last_stage_failure_leaves_state(k, precision, rel):
     m = _oracle_stage_minima(ocfg, u, dt)
     assert m[0] > 1e-2 and m[1] > 1e-2 and m[2] < -1e-2, m
     assert oracle.rk_step(ocfg, u, dt)[1] == oracle.RETRY
-    ctx = make(6, 5, 4, k, ALL, precision, rho_floor_rel=rel)
+    ctx = make(6, 5, 4, k, ALL | split, precision, rho_floor_rel=rel)
     ud = dev(u, ctx)
     before = ud.clone()
     assert dg.dg_rk_step(ctx, ud, dt) == dg.DG_RETRY
