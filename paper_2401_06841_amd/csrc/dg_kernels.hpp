@@ -80,11 +80,15 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
 
 // totals of per-block partials part[4 i + k], i < np, over the threads of one block of
 // BLOCK threads (thread t adds i = t, t + BLOCK, ... in order, then the block sum); the
-// totals end in thread 0.  Every reduction of such partials uses this one order.
+// totals end in thread 0.  Every reduction of such partials uses this one order.  U: loop
+// steps unrolled, so that their loads are in flight together (the order of the additions
+// stays the same).
+template <int U = 1>
 __device__ __forceinline__ void block_partial_sums4(const double *part, int np, double (&s)[4], double *lds)
 {
 #pragma unroll
     for (int k = 0; k < 4; ++k) s[k] = 0.0;
+#pragma unroll U
     for (int i = threadIdx.x; i < np; i += BLOCK)
 #pragma unroll
         for (int k = 0; k < 4; ++k) s[k] += part[4 * i + k];
@@ -2216,6 +2220,7 @@ static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int 
     __shared__ double lds[16];
     if (mode == 2) {
         double m = 0.0, n = 0.0;
+#pragma unroll 16
         for (int i = threadIdx.x; i < np; i += BLOCK) {
             m = fmax(m, part[2 * i]);
             n = fmax(n, part[2 * i + 1]);
@@ -2242,7 +2247,7 @@ static __global__ void __launch_bounds__(BLOCK) k_final(const double *part, int 
         return;
     }
     double s[4];
-    block_partial_sums4(part, np, s, lds);
+    block_partial_sums4<16>(part, np, s, lds);
     if (threadIdx.x == 0) {
         if (mode == 0) {
 #pragma unroll
