@@ -156,6 +156,8 @@ void build_tables(std::vector<double> &t)
         t[TL::LEND + 2 * n + 0] = lt(n, -1.0);
         t[TL::LEND + 2 * n + 1] = lt(n, 1.0);
     }
+    for (int p = 0; p <= K; ++p)
+        for (int a = 0; a <= K; ++a) t[TL::WLT + p * (K + 1) + a] = w[p] * lt(a, g[p]);
     // basis values on the faces: the face point r = r1 + (k+1) r2 has the tangential
     // coordinates (g[r1], g[r2]) along the axes tan1(d) < tan2(d), and xi_d = -1 or +1
     for (int d = 0; d < 3; ++d)
@@ -236,9 +238,12 @@ static void layout(dg_ctx *c, size_t *total)
     // driving field in pencil form: header, (k+1)^2 entries of 16 values per y-z pencil, and
     // the x phases (PencilLayout)
     c->off.ftab = o;
-    o += (c->cfg.flags & DG_FORCING)
-             ? align_up((16 + (size_t)c->cfg.ny * c->cfg.nz * (c->k + 1) * (c->k + 1) * 16 + 2 * (size_t)c->cfg.nx) * es)
-             : 0;
+    {
+        const int nx = c->cfg.nx, ny = c->cfg.ny, nz = c->cfg.nz;
+        const size_t reals = c->k == 1 ? PencilLayout<1>::size(nx, ny, nz)
+                             : c->k == 2 ? PencilLayout<2>::size(nx, ny, nz) : PencilLayout<3>::size(nx, ny, nz);
+        o += (c->cfg.flags & DG_FORCING) ? align_up(reals * es) : 0;
+    }
     const bool learned = c->cfg.flags & DG_LEARNED_SENSOR;
     c->off.nu = o; o += align_up(nc * es);
     c->off.fb = o; o += align_up(nc * 4);
@@ -552,6 +557,11 @@ static int launch_forcing_table(dg_ctx *c)
     const int nb = (int)((nt + BLOCK - 1) / BLOCK);
     hipLaunchKernelGGL((k_forcing_pencils<T, K>), dim3(nb), dim3(BLOCK), 0, c->stream, c->wp(c->off.ftab),
                        c->modes_dev, c->nmodes, c->tab, g, c->cfg.h);
+    LAUNCHCHK(c);
+    // the pencils' moments from the values just written (stream order)
+    const long long nm = (long long)c->cfg.ny * c->cfg.nz * PencilLayout<K>::NB2 * 3;
+    hipLaunchKernelGGL((k_forcing_moments<T, K>), dim3((int)((nm + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, c->stream,
+                       c->wp(c->off.ftab), c->tab, g);
     LAUNCHCHK(c);
     return DG_OK;
 }

@@ -118,7 +118,9 @@ struct TabLayout {
     static constexpr int VXI = LEND + 2 * (K + 1);          // [NQ][3]    reference coordinates
     static constexpr int PLIFT = VXI + 3 * S::NQ;           // [3][2][NF][NB] phi_l at the face points of
                                                             //   face (normal d, side s: 0 low, 1 high)
-    static constexpr int SIZE = PLIFT + 3 * 2 * S::NF * S::NB;
+    static constexpr int WLT = PLIFT + 3 * 2 * S::NF * S::NB;  // [K+1][K+1] w_t Lt_a(xi_t): 1D weight times
+                                                            //   the 1D basis of degree a at 1D point t
+    static constexpr int SIZE = WLT + (K + 1) * (K + 1);
 };
 
 }  // namespace dg

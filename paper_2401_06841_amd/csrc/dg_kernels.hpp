@@ -624,15 +624,30 @@ __device__ __forceinline__ void face(const Field<T, 4> &src, unsigned bo, unsign
 // (cos, sin) pair per x index i, after the pencils), and E_t = exp(pi i xi_t h) from the
 // table header.  The 64 cells of a wave usually share one pencil: their G are then read with
 // scalar loads.  Other tables are evaluated mode by mode at every point (k_rhs's direct form).
+//
+// For the mean acceleration the tables also hold moments.  The cell's source summed over its
+// points, sum_q w_q rho(q) a(q) = sum_l W_l M_l with M_l = sum_q w_q phi_l(q) a(q), factors
+// with phi_l = Lt_a(xi_x) phi2_j(xi_y, xi_z) (a the x degree of mode l, j its 2D mode) into
+//     M_l,d = C0_jd Sx0_a + Re[C1_jd P Sx1_a] + Re[C2_jd P^2 Sx2_a],
+// with the pencil's moments Cn_jd = sum_(t_y, t_z) w phi2_j Gn_d and the x factors
+// Sxn_a = sum_t w_t Lt_a(xi_t) E_t^n: about 10 multiply-adds per mode and component instead of
+// the field at every point.
 template <int K>
 struct PencilLayout {
     static constexpr int N1 = K + 1;
+    static constexpr int NB2 = (K + 1) * (K + 2) / 2;
     static constexpr int HDR = 16;                  // (cos, sin)(pi xi_t h) for t < N1, padded
     static constexpr int ENT = 16;                  // per (t_y, t_z): 3 x (G0, Re G1, Im G1, Re G2, Im G2), padded
     static constexpr int STRIDE = N1 * N1 * ENT;    // reals per pencil
+    static constexpr int SXN = 24;                  // per x degree a: Sx0, Sx1 (re, im), Sx2 (re, im), padded
+    static constexpr int MST = NB2 * 3 * 5;         // per pencil: per 2D mode j and component d,
+                                                    //   C0, C1 (re, im), C2 (re, im)
     // offset of the x phases P_i = (cos, sin)(2 pi (i + 1/2) h), after the ny nz pencils
     __host__ __device__ static size_t phases(int ny, int nz) { return HDR + (size_t)ny * nz * STRIDE; }
-    __host__ __device__ static size_t size(int nx, int ny, int nz) { return phases(ny, nz) + 2 * (size_t)nx; }
+    // the x factors, after the phases; the pencils' moments after them
+    __host__ __device__ static size_t xfactors(int nx, int ny, int nz) { return phases(ny, nz) + 2 * (size_t)nx; }
+    __host__ __device__ static size_t moments(int nx, int ny, int nz) { return xfactors(nx, ny, nz) + SXN; }
+    __host__ __device__ static size_t size(int nx, int ny, int nz) { return moments(nx, ny, nz) + (size_t)ny * nz * MST; }
 };
 
 // a at volume point q (q = t_x + N1 (t_y + N1 t_z)) from the pencil table: g = this pencil's
@@ -701,6 +716,79 @@ __device__ __forceinline__ void drive_point(T rho, T wq, const T (&ac)[3], T (&s
     fs0 = fs0 + s[0];
     fs1 = fs1 + s[1];
     fs2 = fs2 + s[2];
+}
+
+// The cell's driving source summed over its volume points, from its density weights W0 and
+// the moments of its pencil (mp: MST values; sx: the x factors; (pr, pim): the cell's phase P),
+// in the modal form of the pencil layout, with fixed roundings and order (2D mode, component,
+// then the modes with that 2D part): every kernel that forms the mean-acceleration partials
+// gets the same bits.  fs[d] = sum_l W0_l M_l,d.  Each moment is loaded once and used by the
+// modes that share its 2D part.  LANE: the moments differ between lanes (vector loads), one 2D
+// mode's loads in flight at a time.
+template <typename T, int K, bool LANE>
+__device__ __forceinline__ void drive_moments(const T (&W0)[Shape<K>::NB], ctab<T> *mp, ctab<T> *sx, T pr, T pim,
+                                              T (&fs)[3])
+{
+#pragma clang fp contract(off)
+    constexpr Modes<K> M = make_modes<K>();
+    const T p2r = fma(pr, pr, -(pim * pim)), p2i = (T(2) * pr) * pim;
+    T s0[K + 1], q1r[K + 1], q1i[K + 1], q2r[K + 1], q2i[K + 1];
+#pragma unroll
+    for (int a = 0; a <= K; ++a) {
+        ctab<T> *x = sx + 5 * a;
+        s0[a] = x[0];
+        q1r[a] = fma(pr, x[1], -(pim * x[2]));
+        q1i[a] = fma(pr, x[2], pim * x[1]);
+        q2r[a] = fma(p2r, x[3], -(p2i * x[4]));
+        q2i[a] = fma(p2r, x[4], p2i * x[3]);
+    }
+    fs[0] = fs[1] = fs[2] = T(0);
+#pragma unroll
+    for (int j = 0; j < Shape<K>::NB2; ++j) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            ctab<T> *cm = mp + (j * 3 + d) * 5;
+            const T c0 = cm[0], c1r = cm[1], c1i = cm[2], c2r = cm[3], c2i = cm[4];
+#pragma unroll
+            for (int l = 0; l < Shape<K>::NB; ++l) {
+                if (M.d2[0][l] != j) continue;
+                const int a = M.e[l][0];
+                const T m = fma(-c2i, q2i[a], fma(c2r, q2r[a], fma(-c1i, q1i[a], fma(c1r, q1r[a], c0 * s0[a]))));
+                fs[d] = fma(W0[l], m, fs[d]);
+            }
+        }
+        if constexpr (LANE) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// drive_moments for a lane's cell (index c), the moments read with scalar loads when the
+// wave's cells share one pencil.  ft: the pencil-form table.
+template <typename T, int K>
+__device__ __forceinline__ void drive_moment_sums(const T (&W0)[Shape<K>::NB], ctab<T> *ft, const Mesh &g, int c,
+                                                  bool active, T (&fs)[3])
+{
+    using PL = PencilLayout<K>;
+    const int pencil = c / g.nx;
+    T pr, pim;
+    cell_phase<T>(ft + PL::phases(g.ny, g.nz), c % g.nx, pr, pim);
+    ctab<T> *sx = ft + PL::xfactors(g.nx, g.ny, g.nz);
+    ctab<T> *m0 = ft + PL::moments(g.nx, g.ny, g.nz);
+    const int p0 = __shfl(pencil, 0, 64);
+    if (__all(!active || pencil == p0))
+        drive_moments<T, K, false>(W0, m0 + (size_t)__builtin_amdgcn_readfirstlane(p0) * PL::MST, sx, pr, pim, fs);
+    else
+        drive_moments<T, K, true>(W0, m0 + (size_t)pencil * PL::MST, sx, pr, pim, fs);
+}
+
+// the right-hand side's partials of a cell: the three sums times 1/8 and the mean density (0
+// for an inactive lane)
+template <typename T>
+__device__ __forceinline__ void drive_partial(const T (&fs)[3], T mass, bool active, double (&acc)[4])
+{
+    acc[0] = active ? 0.125 * (double)fs[0] : 0.0;
+    acc[1] = active ? 0.125 * (double)fs[1] : 0.0;
+    acc[2] = active ? 0.125 * (double)fs[2] : 0.0;
+    acc[3] = active ? (double)mass : 0.0;
 }
 
 // Driving field forms of the right-hand-side kernels' volume loop
@@ -972,6 +1060,8 @@ k_rhs(RhsArgs a, StageArgs st)
         W[0][0] = U.get(0, 0, bo);
     }
 
+    ctab<T> *ft = as_tab<T>(a.ftab);
+
     // divergence of the projected velocity (Sec. 3.1) as a degree-(K-1) polynomial:
     // its NDIV modal coefficients from the exact derivatives of the Legendre basis
     constexpr DivMap<K> DM = make_divmap<K>();
@@ -1009,7 +1099,6 @@ k_rhs(RhsArgs a, StageArgs st)
     const int pencil = c / a.g.nx;
     const int cijk[3] = {c % a.g.nx, pencil % a.g.ny, pencil / a.g.ny};
     T pr = T(0), pim = T(0);
-    ctab<T> *ft = as_tab<T>(a.ftab);
     if (force && !FDIRECT) cell_phase<T>(ft + PencilLayout<K>::phases(a.g.ny, a.g.nz), cijk[0], pr, pim);
 
     // ---- volume integral
@@ -1693,7 +1782,8 @@ __device__ __forceinline__ void drive_sums(const T (&W0)[Shape<K>::NB], ctab<T> 
     auto sums = [&](auto form, int pen) {
         constexpr int FM = decltype(form)::value;
         ctab<T> *gp = ft + PencilLayout<K>::HDR + (size_t)pen * PencilLayout<K>::STRIDE;
-#pragma unroll 1
+        // three points per loop step: their table loads in flight together (the same sums)
+#pragma unroll 3
         for (int q = 0; q < S::NQ; ++q) {
             ctab<T> *ph = tab + TL::VPHI + q * NB;
             const T wq = tab[TL::VW + q];
@@ -1957,11 +2047,10 @@ __device__ __forceinline__ void fused_stage(const void *ui, T (&L)[4][Shape<K>::
 
 // The rest of a stage whose combination the right-hand-side kernel has stored (a.out,
 // unlimited): the positivity limiter in place (a cell is written back only where it changes),
-// the projected velocity of the result (a.vh_out; project_cell's arithmetic), and with DRIVE
-// the mean-acceleration partials of the result for the next stage (block b: cells b BLOCK + t),
-// from the point densities of the same pass, as the right-hand side forms them (driving
-// table in the pencil form).  All three velocity components in one pass over the points: the
-// kernel is bound by that arithmetic.
+// the projected velocity of the result (a.vh_out; project_cell's arithmetic, all three
+// components in one pass over the points), and with DRIVE the mean-acceleration partials of the
+// result for the next stage (block b: cells b BLOCK + t), in the modal form the right-hand
+// side uses (driving table in the pencil form).
 #ifndef LP_W64K2D
 #define LP_W64K2D 3
 #endif
@@ -1999,63 +2088,36 @@ k_limit_project(StageArgs a)
     for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int l = 0; l < NB; ++l) V[d][l] = T(0);
-    // driving field at the points (DRIVE): the cell's pencil and x phase, as in drive_sums
-    ctab<T> *ft = as_tab<T>(a.ftab);
-    const int pencil = c / a.g.nx;
-    const int cijk[3] = {c % a.g.nx, pencil % a.g.ny, pencil / a.g.ny};
-    T pr = T(0), pim = T(0);
-    if (DRIVE) cell_phase<T>(ft + PencilLayout<K>::phases(a.g.ny, a.g.nz), cijk[0], pr, pim);
-    T fs0 = T(0), fs1 = T(0), fs2 = T(0);
-    auto pass = [&](auto form, int pen) {
-        constexpr int FM = decltype(form)::value;
-        ctab<T> *gp = ft + PencilLayout<K>::HDR + (size_t)pen * PencilLayout<K>::STRIDE;
 #pragma unroll 1
-        for (int q = 0; q < S::NQ; ++q) {
-            ctab<T> *ph = tab + TL::VPHI + q * NB;
-            T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
+    for (int q = 0; q < S::NQ; ++q) {
+        ctab<T> *ph = tab + TL::VPHI + q * NB;
+        T rho = T(0), m0 = T(0), m1 = T(0), m2 = T(0);
 #pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                const T p = ph[l];
-                rho += U[0][l] * p;
-                m0 += U[1][l] * p;
-                m1 += U[2][l] * p;
-                m2 += U[3][l] * p;
-            }
-            const T ir = rcp(rho);
-            const T v0 = m0 * ir, v1 = m1 * ir, v2 = m2 * ir;
-            const T w = tab[TL::VW + q];
-            const T wq = T(0.125) * w;
-            const T a0 = wq * v0, a1 = wq * v1, a2 = wq * v2;
-#pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                const T p = ph[l];
-                V[0][l] += a0 * p;
-                V[1][l] += a1 * p;
-                V[2][l] += a2 * p;
-            }
-            if constexpr (DRIVE) {
-                (void)FM;
-                T ac[3];
-                pencil_accel<T, K>(ft, gp, q, pr, pim, ac);
-                T sp[3];
-                drive_point<T>(rho, w, ac, sp, fs0, fs1, fs2);
-            }
+        for (int l = 0; l < NB; ++l) {
+            const T p = ph[l];
+            rho += U[0][l] * p;
+            m0 += U[1][l] * p;
+            m1 += U[2][l] * p;
+            m2 += U[3][l] * p;
         }
-    };
-    if constexpr (!DRIVE) {
-        (void)cijk;
-        pass(std::integral_constant<int, FM_LANE>{}, 0);
-    } else {
-        const int p0 = __shfl(pencil, 0, 64);
-        if (__all(!active || pencil == p0))
-            pass(std::integral_constant<int, FM_UNIFORM>{}, __builtin_amdgcn_readfirstlane(p0));
-        else
-            pass(std::integral_constant<int, FM_LANE>{}, pencil);
+        const T ir = rcp(rho);
+        const T v0 = m0 * ir, v1 = m1 * ir, v2 = m2 * ir;
+        const T wq = T(0.125) * tab[TL::VW + q];
+        const T a0 = wq * v0, a1 = wq * v1, a2 = wq * v2;
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            const T p = ph[l];
+            V[0][l] += a0 * p;
+            V[1][l] += a1 * p;
+            V[2][l] += a2 * p;
+        }
     }
     if (active) store_field<T, K, 3>(Field<T, 3>(a.vh_out, NB, nc), bo, V);
     if constexpr (DRIVE) {
-        double acc[4] = {active ? 0.125 * (double)fs0 : 0.0, active ? 0.125 * (double)fs1 : 0.0,
-                         active ? 0.125 * (double)fs2 : 0.0, active ? (double)U[0][0] : 0.0};
+        double acc[4];
+        T fs[3];
+        drive_moment_sums<T, K>(U[0], as_tab<T>(a.ftab), a.g, c, active, fs);
+        drive_partial<T>(fs, U[0][0], active, acc);
         block_sum<4>(acc, lds);
         if (threadIdx.x == 0)
 #pragma unroll
@@ -2087,7 +2149,13 @@ __global__ void __launch_bounds__(BLOCK) k_drive_parts(RhsArgs a)
 #pragma unroll
     for (int l = 0; l < NB; ++l) W0[l] = U.get(0, l, bo);
     double acc[4];
-    drive_sums<T, K, FDIRECT>(W0, as_tab<T>(a.tab), as_tab<T>(a.ftab), a.modes, a.nmodes, a.g, a.h, c, active, acc);
+    if constexpr (FDIRECT) {
+        drive_sums<T, K, true>(W0, as_tab<T>(a.tab), as_tab<T>(a.ftab), a.modes, a.nmodes, a.g, a.h, c, active, acc);
+    } else {
+        T fs[3];
+        drive_moment_sums<T, K>(W0, as_tab<T>(a.ftab), a.g, c, active, fs);
+        drive_partial<T>(fs, W0[0], active, acc);
+    }
     block_sum<4>(acc, lds);
     if (threadIdx.x == 0)
 #pragma unroll
@@ -2179,6 +2247,56 @@ __global__ void __launch_bounds__(BLOCK) k_forcing_pencils(void *ft_, const doub
 #pragma unroll
         for (int k = 0; k < 5; ++k) o[5 * d + k] = (T)G[d][k];
     o[15] = T(0);
+}
+
+// The moments of the pencil form (see PencilLayout), from the pencil values k_forcing_pencils
+// has written: one thread per pencil, 2D mode j and component d; thread 0 also writes the x
+// factors.  Sums in FP64 over the table values, stored in the element type.
+template <typename T, int K>
+__global__ void __launch_bounds__(BLOCK) k_forcing_moments(void *ft_, const void *tab_, Mesh g)
+{
+    using TL = TabLayout<K>;
+    using PL = PencilLayout<K>;
+    using S = Shape<K>;
+    constexpr int N1 = PL::N1;
+    ctab<T> *tab = as_tab<T>(tab_);
+    T *ft = (T *)ft_;
+    const long long t = (long long)blockIdx.x * BLOCK + threadIdx.x;
+    if (t == 0) {
+        T *sx = ft + PL::xfactors(g.nx, g.ny, g.nz);
+        for (int a = 0; a <= K; ++a) {
+            double s0 = 0.0, s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+            for (int p = 0; p < N1; ++p) {
+                const double wl = (double)tab[TL::WLT + p * (K + 1) + a];
+                const double er = (double)ft[2 * p], ei = (double)ft[2 * p + 1];
+                s0 += wl;
+                s1r += wl * er;
+                s1i += wl * ei;
+                s2r += wl * (er * er - ei * ei);
+                s2i += wl * (2.0 * er * ei);
+            }
+            sx[5 * a] = (T)s0;
+            sx[5 * a + 1] = (T)s1r;
+            sx[5 * a + 2] = (T)s1i;
+            sx[5 * a + 3] = (T)s2r;
+            sx[5 * a + 4] = (T)s2i;
+        }
+    }
+    const long long nt = (long long)g.ny * g.nz * PL::NB2 * 3;
+    if (t >= nt) return;
+    const int pen = (int)(t / (PL::NB2 * 3)), r = (int)(t % (PL::NB2 * 3));
+    const int j = r / 3, d = r % 3;
+    const T *gp = ft + PL::HDR + (size_t)pen * PL::STRIDE;
+    double cm[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int tt = 0; tt < S::NF; ++tt) {
+        const double w = (double)tab[TL::FW + tt] * (double)tab[TL::F2 + tt * S::NB2 + j];
+        const T *e = gp + tt * PL::ENT + 5 * d;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) cm[k] += w * (double)e[k];
+    }
+    T *o = ft + PL::moments(g.nx, g.ny, g.nz) + (size_t)pen * PL::MST + (j * 3 + d) * 5;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) o[k] = (T)cm[k];
 }
 
 // per-block sums of the cell means (conservation totals, Sec. 2.2: w_0 is the mean)

@@ -1,16 +1,18 @@
-"""Split Runge-Kutta stages against separate stage kernels, bit for bit.
+"""Split Runge-Kutta stages against separate stage kernels.
 
 With DG_SPLIT_STAGE every stage of a step that writes a workspace buffer (all but the last)
 is split: once a cell's right-hand side is formed, the right-hand-side kernel combines it with
 the cell's input weights (and u^n) and stores the result, and a second kernel limits it
 (Sec. 3.1) and projects its velocity (Sec. 3.2) for the next stage.  DG_SEPARATE_STAGE stores
-the right-hand side and runs the stage kernel instead.  The two give the same bits: every
-combination has the same roundings, and with mean-free driving (Sec. 4.2) the mean
-acceleration of a stage input comes from partial sums formed exactly as the right-hand side
-forms them (by the previous split stage, or by a kernel of their own before a step's first
-stage).  Each case steps one seeded state in two contexts and compares the states and the time
-steps for equality.  Without either flag the split is used on large FP64 meshes only; the
-parity of both paths with the oracle is checked by the step tests of the other files.
+the right-hand side and runs the stage kernel instead.  Every combination has the same
+roundings in both, so they give the same bits, except with mean-free driving (Sec. 4.2) and a
+table on the driving shell: the split path then forms the mean-acceleration partials of a
+stage input (in the previous split stage, or in a kernel of their own before a step's first
+stage) in the modal form of the pencil table, the same sums as the right-hand side's point
+sums up to rounding, and the two paths agree to the parity bars (1e-12 FP64, 1e-5 FP32, in
+the field norms and weight by weight, and the time steps).  Each case steps one seeded state in
+two contexts.  Without either flag the split is used on large FP64 meshes only; the parity of
+both paths with the oracle is checked by the step tests of the other files.
 """
 import numpy as np
 import pytest
@@ -18,7 +20,7 @@ import torch
 
 import oracle
 import synthetic
-from gpu_util import dev, make
+from gpu_util import assert_state_close, dev, host, make
 from paper_2401_06841_amd import dg
 
 pytestmark = pytest.mark.gpu
@@ -57,7 +59,24 @@ def _pair(shape, k, precision, flags, table, seed, split=dg.DG_SPLIT_STAGE, **kw
     return a, b
 
 
-def _steps_equal(a, b, ua, ub, nsteps, ahead=False):
+TOL = {FP64: 1e-12, FP32: 1e-5}
+
+
+def _exact(flags, table):
+    """Whether the two paths form the same partial sums (see the module text)."""
+    return not (flags & dg.DG_FORCE_MEANFREE and flags & dg.DG_FORCING and table == "shell")
+
+
+def _compare(ua, ub, da, db, exact, tol, label):
+    if exact:
+        assert da == db, (label, da, db)
+        assert torch.equal(ua, ub), f"{label}: largest difference {(ua - ub).abs().max().item():.3e}"
+    else:
+        assert abs(da - db) <= tol * abs(db), (label, da, db)
+        assert_state_close(host(ua), host(ub), tol, label)
+
+
+def _steps_equal(a, b, ua, ub, nsteps, ahead=False, exact=True, tol=0.0):
     dt = dg.dg_dt_max(a, ua)
     assert dt == dg.dg_dt_max(b, ub)
     for i in range(nsteps):
@@ -68,8 +87,7 @@ def _steps_equal(a, b, ua, ub, nsteps, ahead=False):
             ra, da = dg.dg_rk_step_next(a, ua, dt, i > 0)
             rb, db = dg.dg_rk_step_next(b, ub, dt, i > 0)
         assert ra == rb == dg.DG_OK, (i, ra, rb)
-        assert da == db, (i, da, db)
-        assert torch.equal(ua, ub), f"step {i}: largest difference {(ua - ub).abs().max().item():.3e}"
+        _compare(ua, ub, da, db, exact, tol, f"step {i}")
         dt = da
 
 
@@ -79,7 +97,7 @@ def test_split_stage_equals_separate_stage(label, shape, k, precision, flags, ta
     u0 = synthetic.turbulent_like(*shape, k, mach=3.0, seed=70 + k, high_amp=0.02, kmax_frac=0.125)
     a, b = _pair(shape, k, precision, flags, table, 30 + k)
     ua, ub = dev(u0, a), dev(u0, b)
-    _steps_equal(a, b, ua, ub, 3)
+    _steps_equal(a, b, ua, ub, 3, exact=_exact(flags, table), tol=TOL[precision])
 
 
 def test_split_stage_launched_ahead():
@@ -90,7 +108,7 @@ def test_split_stage_launched_ahead():
     u0 = synthetic.turbulent_like(*shape, k, mach=3.0, seed=75, high_amp=0.02, kmax_frac=0.125)
     a, b = _pair(shape, k, FP64, FORCE, "shell", 35)
     ua, ub = dev(u0, a), dev(u0, b)
-    _steps_equal(a, b, ua, ub, 4, ahead=True)
+    _steps_equal(a, b, ua, ub, 4, ahead=True, exact=False, tol=TOL[FP64])
 
 
 @pytest.mark.parametrize("precision", [FP64, FP32])
@@ -113,8 +131,14 @@ def test_split_stage_limits_cells(precision):
     ra, da = dg.dg_rk_step_next(a, ua, dt, False)
     rb, db = dg.dg_rk_step_next(b, ub, dt, False)
     assert ra == rb == dg.DG_OK
-    assert da == db
-    assert torch.equal(ua, ub)
+    _compare(ua, ub, da, db, False, TOL[precision], "limited step")
+    # without mean-free driving the two paths give the same bits
+    a, b = _pair(shape, k, precision, BASE | dg.DG_FORCING, "shell", 36)
+    ua, ub = dev(u0, a), dev(u0, b)
+    ra, da = dg.dg_rk_step_next(a, ua, dt, False)
+    rb, db = dg.dg_rk_step_next(b, ub, dt, False)
+    assert ra == rb == dg.DG_OK
+    _compare(ua, ub, da, db, True, 0.0, "limited step, mean kept")
 
 
 def test_split_stage_failure_keeps_state():
@@ -154,7 +178,7 @@ def test_split_stage_learned_sensor(precision):
     ua, ub = dev(u0, a), dev(u0, b)
     for c, ud in ((a, ua), (b, ub)):
         dg.dg_sensor_infer(c, ud)
-    _steps_equal(a, b, ua, ub, 3)
+    _steps_equal(a, b, ua, ub, 3, exact=False, tol=TOL[precision])
 
 
 def test_split_stage_partials_across_a_table_upload():
@@ -165,20 +189,20 @@ def test_split_stage_partials_across_a_table_upload():
     u0 = synthetic.turbulent_like(*shape, k, mach=3.0, seed=78, high_amp=0.02, kmax_frac=0.125)
     a, b = _pair(shape, k, FP64, FORCE, "shell", 38)
     ua, ub = dev(u0, a), dev(u0, b)
-    _steps_equal(a, b, ua, ub, 2)
+    _steps_equal(a, b, ua, ub, 2, exact=False, tol=TOL[FP64])
     modes = synthetic.forcing_table(39, amp=4.0)
     for c in (a, b):
         dg.dg_set_forcing(c, modes)
     dt = dg.dg_dt_max(a, ua)
     ra, da = dg.dg_rk_step_next(a, ua, dt, True)
     rb, db = dg.dg_rk_step_next(b, ub, dt, True)
-    assert ra == rb == dg.DG_OK and da == db
-    assert torch.equal(ua, ub)
+    assert ra == rb == dg.DG_OK
+    _compare(ua, ub, da, db, False, TOL[FP64], "after the upload")
 
 
 def test_default_splits_large_fp64_meshes():
-    """Without either flag a mesh of 2^22 cells in FP64 takes the split stages (and a smaller
-    one the separate kernels); both equal the separate path bit for bit."""
+    """Without either flag a mesh of 2^22 cells in FP64 takes the split stages; they agree with
+    the separate path."""
     shape, k = (256, 128, 128), 1
     print(f"default stage choice {shape} k={k} FP64", flush=True)
     u0 = synthetic.turbulent_like(64, 64, 64, k, mach=3.0, seed=79, high_amp=0.02, kmax_frac=0.125)
@@ -188,7 +212,7 @@ def test_default_splits_large_fp64_meshes():
     del u0
     dg.dg_profile(a, 2)
     dg.dg_profile(b, 2)
-    _steps_equal(a, b, ua, ub, 2)
+    _steps_equal(a, b, ua, ub, 2, exact=False, tol=TOL[FP64])
     pa, pb = dg.dg_profile_read(a), dg.dg_profile_read(b)
     ta, tb = pa[2] / pa[3], pb[2] / pb[3]
     print(f"mean stage-kernel times: default {ta:.3f} ms, separate {tb:.3f} ms", flush=True)
