@@ -218,3 +218,29 @@ def test_default_splits_large_fp64_meshes():
     print(f"mean stage-kernel times: default {ta:.3f} ms, separate {tb:.3f} ms", flush=True)
     # the split's second kernel moves about a third of the stage kernel's bytes
     assert ta < 0.9 * tb
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_split_stage_step_matches_oracle(k, precision):
+    """Split stages with mean-free driving on the driving shell (the modal partials) against
+    the oracle's SSP-RK3 step, whole mesh (the two-lane FP64 degree-3 kernel keeps separate
+    stages: that case checks the flag is accepted)."""
+    shape = (24, 16, 16)
+    print(f"split step vs oracle {shape} k={k} precision={precision}", flush=True)
+    u0 = synthetic.turbulent_like(*shape, k, mach=3.0, seed=80 + k, high_amp=0.02, kmax_frac=0.125)
+    if precision == FP32:
+        u0 = u0.astype(np.float32).astype(np.float64)
+    modes = synthetic.forcing_table(41 + k, amp=2.5)
+    ocfg = oracle.Cfg(*shape, k, flags=FORCE)
+    ctx = make(*shape, k, FORCE | dg.DG_SPLIT_STAGE, precision)
+    dg.dg_set_forcing(ctx, modes)
+    ud = dev(u0, ctx)
+    dt = oracle.dt_max(ocfg, u0)
+    rc, dt_next = dg.dg_rk_step_next(ctx, ud, dt, False)
+    assert rc == dg.DG_OK
+    ref, st = oracle.rk_step(ocfg, u0, dt, modes)
+    assert st == oracle.OK
+    assert_state_close(host(ud), ref, TOL[precision], "split step")
+    d1 = oracle.dt_max(ocfg, ref)
+    assert abs(dt_next - d1) <= TOL[precision] * d1
