@@ -622,7 +622,7 @@ struct StagePred {
 // FP64 34.6 -> 33.1 / 32.5 / 32.6 ms; 64^3 unchanged up to 8 and slower at 16
 constexpr int RHS_ZTILE = 8;
 
-// st: the stage that the right-hand side goes on with in the same kernel (fused), or NULL:
+// st: the split stage whose combination the right-hand-side kernel forms, or NULL:
 // the right-hand side is stored into out
 template <typename T, int K>
 static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, double dt, int *fail_reset = nullptr,
@@ -668,7 +668,7 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
     const bool direct = (a.flags & DG_FORCING) && !c->modes_sep;
     a.mfma = c->mfma_tab;
     const StageArgs st0{};
-    if (st) a.part = nullptr;   // a fused stage's kernel reads the partials of its input
+    if (st) a.part = nullptr;   // a split stage's kernel reads the partials of its input
     // sweep order: tiles of planes when whole blocks make up a plane
     {
         const int cpb = rhs_pair<T, K>() ? BLOCK / 2 : BLOCK;
@@ -696,7 +696,7 @@ static int launch_rhs(dg_ctx *c, const void *u, const void *vh, void *out, doubl
         c->rhs_nblk = c->nblk;
         bool done = false;
         if (st) {
-            // u^n enters the fused stage when its coefficient is not zero
+            // u^n enters the combination when its coefficient is not zero
             const dim3 gr(c->nblk), bl(BLOCK);
             if (st->ca != 0.0) {
                 if (direct) hipLaunchKernelGGL((k_rhs<T, K, true, false, 2>), gr, bl, 0, c->stream, a, *st);
@@ -744,11 +744,11 @@ static int launch_abar(dg_ctx *c, const double *part = nullptr, int np = 0)
     return DG_OK;
 }
 
-// the arguments of one stage (k_stage, or the fused stage of k_rhs: L is then not read, and
+// the arguments of one stage (k_stage, or the split stage of k_rhs: L is then not read, and
 // with mean-free driving the partials or the mean are those of ui)
 static StageArgs stage_args(dg_ctx *c, const void *ui, const void *un, const void *L, void *out, void *vh_out,
                             bool skip_if_failed, const double (&coef)[3], double dt, long long *nlim, double *part,
-                            void *w, const double (&wcoef)[3], const double *dt_dev, bool fused = false)
+                            void *w, const double (&wcoef)[3], const double *dt_dev, bool split = false)
 {
     StageArgs a;
     a.ui = ui;
@@ -763,10 +763,10 @@ static StageArgs stage_args(dg_ctx *c, const void *ui, const void *un, const voi
     // acceleration itself (no separate reduction kernel)
     // (a stage whose combination the right-hand-side kernel forms reads the partials of its
     // input from the region k_drive_parts and k_limit_project write)
-    const bool mf = (L || fused) && use_meanfree(c);
+    const bool mf = (L || split) && use_meanfree(c);
     a.abar = mf && !c->abar_in_stage ? c->abar() : nullptr;
-    a.abar_part = mf && c->abar_in_stage ? (const double *)c->wp(fused ? c->off.dpart : c->off.part) : nullptr;
-    a.abar_np = fused ? c->nblk : c->rhs_nblk;
+    a.abar_part = mf && c->abar_in_stage ? (const double *)c->wp(split ? c->off.dpart : c->off.part) : nullptr;
+    a.abar_np = split ? c->nblk : c->rhs_nblk;
     a.fail = c->fail();
     a.nlim = nlim;
     a.part = part;
@@ -927,7 +927,7 @@ static const Scheme &scheme_of(const dg_ctx *c)
 }
 
 // Whether a stage is split between its right-hand-side kernel, which forms the stage's
-// combination (k_rhs with FUSE), and k_limit_project, which limits and projects it, instead of
+// combination (k_rhs with COMB), and k_limit_project, which limits and projects it, instead of
 // storing the right-hand side for a stage kernel: the one-lane kernel with the vector volume
 // integral, a stage without a side combination that writes a workspace buffer other than its
 // input (the last stage writes the caller's array, which must keep u^n when the step fails:
@@ -941,7 +941,7 @@ constexpr long long SPLIT_MIN_CELLS = 1LL << 22;
 // (The last stage measured no gain split: its combination into a free buffer and k_stage from
 // there at 256^3 FP64 took 44.2 ms per step against 44.1 for the stored right-hand side.)
 template <typename T, int K>
-static bool fuse_stage(const dg_ctx *c, const StageSpec &g, bool last)
+static bool split_stage(const dg_ctx *c, const StageSpec &g, bool last)
 {
     if (rhs_pair<T, K>() || last || g.w || g.out == 0 || g.out == g.in) return false;
     if (c->cfg.flags & (DG_SEPARATE_STAGE | DG_VOLUME_MFMA)) return false;
@@ -956,7 +956,7 @@ template <typename T, int K>
 static bool next_split_partials(const dg_ctx *c, const Scheme &S, int s)
 {
     return s + 1 < S.stages && S.s[s + 1].in == S.s[s].out && c->modes_sep &&
-           fuse_stage<T, K>(c, S.s[s], s == S.stages - 1) && fuse_stage<T, K>(c, S.s[s + 1], s + 1 == S.stages - 1);
+           split_stage<T, K>(c, S.s[s], s == S.stages - 1) && split_stage<T, K>(c, S.s[s + 1], s + 1 == S.stages - 1);
 }
 
 // the mean-acceleration partials of u alone (k_drive_parts) into the split stages' region
@@ -997,7 +997,7 @@ static int launch_step_stage(dg_ctx *c, void *u, int s, double dt, bool reset_fa
     void *buf[4] = {u, c->wp(c->off.stA), c->wp(c->off.stB), c->wp(c->off.stC)};
     const StageSpec &g = S.s[s];
     const bool last = s == S.stages - 1;
-    if constexpr (!rhs_pair<T, K>()) if (fuse_stage<T, K>(c, g, last)) {
+    if constexpr (!rhs_pair<T, K>()) if (split_stage<T, K>(c, g, last)) {
         int rc = DG_OK;
         int *reset = reset_fail ? c->fail() : nullptr;
         const bool mf = use_meanfree(c);
@@ -1142,7 +1142,7 @@ static int split_stages_impl(const dg_ctx *c)
 {
     const Scheme &S = scheme_of(c);
     for (int s = 0; s < S.stages; ++s)
-        if (fuse_stage<T, K>(c, S.s[s], s == S.stages - 1)) return 1;
+        if (split_stage<T, K>(c, S.s[s], s == S.stages - 1)) return 1;
     return 0;
 }
 

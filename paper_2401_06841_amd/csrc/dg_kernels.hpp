@@ -1004,17 +1004,17 @@ template <typename T, int K, bool VMFMA = false>
 constexpr int rhs_waves() { return VMFMA ? MFMA_WAVES : (sizeof(T) == 8 ? (K <= 2 ? 2 : 1) : (K <= 2 ? 4 : 2)); }
 
 template <typename T, int K, bool UNV>
-__device__ __forceinline__ void fused_stage(const void *ui, T (&L)[4][Shape<K>::NB], T inv4h, double dt,
+__device__ __forceinline__ void rhs_combination(const void *ui, T (&L)[4][Shape<K>::NB], T inv4h, double dt,
                                             const StageArgs &st, bool active, unsigned bo, double *lds);
 
-// FUSE: 0 stores the right-hand side (and the mean-acceleration partials); 1 and 2 go on with
-// the combination of the stage st of a Runge-Kutta step for the cell (fused_stage; 2: u^n
+// COMB: 0 stores the right-hand side (and the mean-acceleration partials); 1 and 2 go on with
+// the combination of the stage st of a Runge-Kutta step for the cell (rhs_combination; 2: u^n
 // enters) and store nothing of the right-hand side
-template <typename T, int K, bool FDIRECT, bool VMFMA = false, int FUSE = 0>
+template <typename T, int K, bool FDIRECT, bool VMFMA = false, int COMB = 0>
 __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(rhs_waves<T, K, VMFMA>())))
 k_rhs(RhsArgs a, StageArgs st)
 {
-    static_assert(!(FUSE && VMFMA), "fused stages: vector volume integral only");
+    static_assert(!(COMB && VMFMA), "split stages: vector volume integral only");
     using S = Shape<K>;
     using TL = TabLayout<K>;
     constexpr Modes<K> M = make_modes<K>();
@@ -1230,10 +1230,10 @@ k_rhs(RhsArgs a, StageArgs st)
         face<T, K, 2>(SRC, bo, (unsigned)(s ? nbr[5] : nbr[4]) * sizeof(T), s, tab, prim, use_hllc, cs, cs2, L, col);
 
     const T inv4h = (T)(0.25 / a.h);
-    if constexpr (FUSE != 0) {
+    if constexpr (COMB != 0) {
         (void)mass0;
         __shared__ double lds_st[20];
-        fused_stage<T, K, FUSE == 2>(a.u, L, inv4h, dt, st, active, bo, lds_st);
+        rhs_combination<T, K, COMB == 2>(a.u, L, inv4h, dt, st, active, bo, lds_st);
     } else {
         (void)st;
         if (active) {
@@ -1762,52 +1762,34 @@ __device__ __forceinline__ void project_and_bounds(const T (&W)[4][Shape<K>::NB]
 }
 
 // The driving source of a cell summed over its volume points (times 1/8) and its mean
-// density, from its density weights W0, with the arithmetic of the right-hand side's volume
-// loop: the point densities summed mode by mode in the same order, the source through
-// drive_point and pencil_accel or direct_accel.  acc[0..2]: source, acc[3]: mean density (all
-// 0 for an inactive lane).
-template <typename T, int K, bool FDIRECT>
-__device__ __forceinline__ void drive_sums(const T (&W0)[Shape<K>::NB], ctab<T> *tab, ctab<T> *ft,
-                                           const double *modes, int nmodes, const Mesh &g, double h, int c,
-                                           bool active, double (&acc)[4])
+// density, from its density weights W0, for tables off the driving shell (the field mode by
+// mode at each point), with the arithmetic of the right-hand side's volume loop: the point
+// densities summed mode by mode in the same order, the source through drive_point and
+// direct_accel.  acc[0..2]: source, acc[3]: mean density (all 0 for an inactive lane).
+template <typename T, int K>
+__device__ __forceinline__ void drive_sums_direct(const T (&W0)[Shape<K>::NB], ctab<T> *tab, const double *modes,
+                                                  int nmodes, const Mesh &g, double h, int c, bool active,
+                                                  double (&acc)[4])
 {
     using S = Shape<K>;
     using TL = TabLayout<K>;
     constexpr int NB = S::NB;
     const int pencil = c / g.nx;
     const int cijk[3] = {c % g.nx, pencil % g.ny, pencil / g.ny};
-    T pr = T(0), pim = T(0);
-    if (!FDIRECT) cell_phase<T>(ft + PencilLayout<K>::phases(g.ny, g.nz), cijk[0], pr, pim);
     T fs0 = T(0), fs1 = T(0), fs2 = T(0);
-    auto sums = [&](auto form, int pen) {
-        constexpr int FM = decltype(form)::value;
-        ctab<T> *gp = ft + PencilLayout<K>::HDR + (size_t)pen * PencilLayout<K>::STRIDE;
-        // three points per loop step: their table loads in flight together (the same sums)
+    // three points per loop step: their table loads in flight together (the same sums)
 #pragma unroll 3
-        for (int q = 0; q < S::NQ; ++q) {
-            ctab<T> *ph = tab + TL::VPHI + q * NB;
-            const T wq = tab[TL::VW + q];
-            T rho = T(0);
+    for (int q = 0; q < S::NQ; ++q) {
+        ctab<T> *ph = tab + TL::VPHI + q * NB;
+        const T wq = tab[TL::VW + q];
+        T rho = T(0);
 #pragma unroll
-            for (int l = 0; l < NB; ++l) rho += W0[l] * ph[l];
-            T ac[3];
-            if constexpr (FM == FM_DIRECT)
-                direct_accel<T>(modes, nmodes, cijk, tab[TL::VXI + 3 * q], tab[TL::VXI + 3 * q + 1],
-                                tab[TL::VXI + 3 * q + 2], h, ac);
-            else
-                pencil_accel<T, K>(ft, gp, q, pr, pim, ac);
-            T sp[3];
-            drive_point<T>(rho, wq, ac, sp, fs0, fs1, fs2);
-        }
-    };
-    if constexpr (FDIRECT) {
-        sums(std::integral_constant<int, FM_DIRECT>{}, 0);
-    } else {
-        const int p0 = __shfl(pencil, 0, 64);
-        if (__all(!active || pencil == p0))
-            sums(std::integral_constant<int, FM_UNIFORM>{}, __builtin_amdgcn_readfirstlane(p0));
-        else
-            sums(std::integral_constant<int, FM_LANE>{}, pencil);
+        for (int l = 0; l < NB; ++l) rho += W0[l] * ph[l];
+        T ac[3];
+        direct_accel<T>(modes, nmodes, cijk, tab[TL::VXI + 3 * q], tab[TL::VXI + 3 * q + 1], tab[TL::VXI + 3 * q + 2],
+                        h, ac);
+        T sp[3];
+        drive_point<T>(rho, wq, ac, sp, fs0, fs1, fs2);
     }
     acc[0] = active ? 0.125 * (double)fs0 : 0.0;
     acc[1] = active ? 0.125 * (double)fs1 : 0.0;
@@ -1981,7 +1963,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         // The combination of every weight, momentum first (the removed mean acceleration
         // multiplies the input density).  Whether u^n and the side combination enter is a
         // template choice (UNV, SIDE): with a branch per weight the compiler waited for each
-        // weight's loads in turn.  The roundings are those of the fused stage of k_rhs.
+        // weight's loads in turn.  The roundings are those of the combination k_rhs forms for a split stage.
 #pragma unroll
         for (int v = 3; v >= 0; --v)
 #pragma unroll
@@ -2005,7 +1987,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
     stage_finish<T, K>(U, tab, a, bo, c, active, blk, lds);
 }
 
-// The combination of a stage formed in the right-hand-side kernel (k_rhs with FUSE): k_stage's
+// The combination of a stage formed in the right-hand-side kernel (k_rhs with COMB): k_stage's
 // u^(i+1) = ca un + cb ui + cdt (L - abar W_rho) for the cell whose right-hand side the kernel
 // has just formed, with 4h dw/dt in L (it becomes the new weights) in place of the stored
 // right-hand side and the same roundings, stored into st.out unlimited.  k_limit_project then
@@ -2013,7 +1995,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
 // right-hand side and stage kernels.  The input weights are read again (they are not kept
 // through the surface integral).  Every thread of the block calls it.
 template <typename T, int K, bool UNV>
-__device__ __forceinline__ void fused_stage(const void *ui, T (&L)[4][Shape<K>::NB], T inv4h, double dt,
+__device__ __forceinline__ void rhs_combination(const void *ui, T (&L)[4][Shape<K>::NB], T inv4h, double dt,
                                             const StageArgs &st, bool active, unsigned bo, double *lds)
 {
     constexpr int NB = Shape<K>::NB;
@@ -2127,11 +2109,12 @@ k_limit_project(StageArgs a)
 
 // Per-block partial sums of the removed mean acceleration of a state alone (Sec. 4.2,
 // mean-free driving): the cell's driving source rho w_q a summed over the volume points (times
-// 1/8) and its mean density, the same values at the same block index as the right-hand-side
-// kernel forms in its volume loop (block b holds cells b BLOCK + t; the point densities summed mode by
-// mode in the same order; the source through drive_point and pencil_accel or direct_accel).
-// A fused stage needs the mean of its input before its kernel has formed any right-hand
-// side: this kernel runs first.  a.fail_reset: the failure flag to clear, or NULL.
+// 1/8) and its mean density, at the block index the right-hand-side kernel uses (block b holds
+// cells b BLOCK + t): in the modal form of the pencil table (drive_moment_sums, as
+// k_limit_project forms them), or for tables off the driving shell with the right-hand side's
+// own point sums (drive_sums_direct).  A split stage needs the mean of its input before its
+// kernel has formed any right-hand side: this kernel runs first.  a.fail_reset: the failure
+// flag to clear, or NULL.
 template <typename T, int K, bool FDIRECT>
 __global__ void __launch_bounds__(BLOCK) k_drive_parts(RhsArgs a)
 {
@@ -2150,7 +2133,7 @@ __global__ void __launch_bounds__(BLOCK) k_drive_parts(RhsArgs a)
     for (int l = 0; l < NB; ++l) W0[l] = U.get(0, l, bo);
     double acc[4];
     if constexpr (FDIRECT) {
-        drive_sums<T, K, true>(W0, as_tab<T>(a.tab), as_tab<T>(a.ftab), a.modes, a.nmodes, a.g, a.h, c, active, acc);
+        drive_sums_direct<T, K>(W0, as_tab<T>(a.tab), a.modes, a.nmodes, a.g, a.h, c, active, acc);
     } else {
         T fs[3];
         drive_moment_sums<T, K>(W0, as_tab<T>(a.ftab), a.g, c, active, fs);

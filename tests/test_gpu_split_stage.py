@@ -37,6 +37,10 @@ CASES = [
     ("k2 fp64 driven, mean kept", (16, 16, 16), 2, FP64, BASE | dg.DG_FORCING, "shell"),
     ("k2 fp64 general table", (16, 16, 16), 2, FP64, FORCE, "general"),
     ("k2 fp64 plain traces", (16, 16, 16), 2, FP64, FORCE & ~dg.DG_PRIM_PROJ, "shell"),
+    # a last block with inactive lanes, and waves spanning several pencils (x lines of 20)
+    ("k2 fp64 ragged", (20, 15, 13), 2, FP64, FORCE, "shell"),
+    ("k2 fp32 ragged", (20, 15, 13), 2, FP32, FORCE, "shell"),
+    ("k3 fp32 ragged", (9, 7, 5), 3, FP32, FORCE, "shell"),
     ("k1 fp64 two-stage scheme", (16, 16, 16), 1, FP64, FORCE | dg.DG_RK_BY_ORDER, "shell"),
     ("k2 fp32", (16, 16, 16), 2, FP32, FORCE, "shell"),
     ("k3 fp32", (12, 12, 12), 3, FP32, FORCE, "shell"),
