@@ -75,10 +75,12 @@ enum dg_flags {
     DG_SPLIT_STAGE = 1024      /* the stages that write workspace buffers (all but the last) split between
                                   the right-hand-side kernel, which forms the stage's combination instead
                                   of storing the right-hand side, and a kernel that limits and projects
-                                  it.  Same bits as DG_SEPARATE_STAGE.  With neither flag the split is
-                                  used where it measured faster (FP64 meshes of at least 2^22 cells); the
-                                  two-lane FP64 degree-3 kernel and DG_VOLUME_MFMA never split.  Both
-                                  flags together: DG_EINVAL */
+                                  it.  The same results as DG_SEPARATE_STAGE (bit for bit, or to rounding
+                                  with mean-free driving on the driving shell, whose mean the split path
+                                  sums in modal form).  With neither flag the split is used where it
+                                  measured faster (meshes of at least 2^21 cells); the two-lane FP64
+                                  degree-3 kernel and DG_VOLUME_MFMA never split.  Both flags together:
+                                  DG_EINVAL */
 };
 
 typedef struct dg_config {

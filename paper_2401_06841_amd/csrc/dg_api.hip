@@ -933,10 +933,11 @@ static const Scheme &scheme_of(const dg_ctx *c)
 // input (the last stage writes the caller's array, which must keep u^n when the step fails:
 // its failure is decided before its stage kernel runs), and not turned off by
 // DG_SEPARATE_STAGE.  Split and separate stages give the same bits.
-// The split pays where the right-hand side is long against the stage's memory time: measured
-// on one MI355X, 256^3 degree 2 FP64 steps 44.5 -> 43.7 ms; FP32 at 256^3 unchanged, slower at
-// 128^3 FP32 (2.74 -> 2.81 ms) and 64^3 FP64 (0.79 -> 0.83 ms).
-constexpr long long SPLIT_MIN_CELLS = 1LL << 22;
+// The split pays where the mesh takes many rounds of blocks: measured on one MI355X (split
+// against separate, alternated in one call, degree 2, driven, mean-free): 256^3 FP64 42.7 vs
+// 43.8 ms per step, 256^3 FP32 21.5 vs 22.2 ms, 128^3 FP64 5.43 vs 5.52 ms, 128^3 FP32 2.76 vs
+// 2.79 ms; slower at 64^3 FP64 (0.81-0.82 vs 0.78 ms).
+constexpr long long SPLIT_MIN_CELLS = 1LL << 21;
 
 // (The last stage measured no gain split: its combination into a free buffer and k_stage from
 // there at 256^3 FP64 took 44.2 ms per step against 44.1 for the stored right-hand side.)
@@ -946,7 +947,7 @@ static bool split_stage(const dg_ctx *c, const StageSpec &g, bool last)
     if (rhs_pair<T, K>() || last || g.w || g.out == 0 || g.out == g.in) return false;
     if (c->cfg.flags & (DG_SEPARATE_STAGE | DG_VOLUME_MFMA)) return false;
     if (c->cfg.flags & DG_SPLIT_STAGE) return true;
-    return sizeof(T) == 8 && (long long)c->nc >= SPLIT_MIN_CELLS;
+    return (long long)c->nc >= SPLIT_MIN_CELLS;
 }
 
 // whether stage s is split and leaves the partials of its result for stage s + 1

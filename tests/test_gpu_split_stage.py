@@ -248,3 +248,19 @@ def test_split_stage_step_matches_oracle(k, precision):
     assert_state_close(host(ud), ref, TOL[precision], "split step")
     d1 = oracle.dt_max(ocfg, ref)
     assert abs(dt_next - d1) <= TOL[precision] * d1
+
+
+def test_default_stage_choice_by_mesh_size():
+    """The default splits meshes of at least 2^21 cells in either precision, never the two-lane
+    FP64 degree-3 configuration; the flags force either path."""
+    for shape, k, precision, flags, want in [((64, 64, 64), 2, FP64, FORCE, False),
+                                             ((128, 128, 128), 2, FP64, FORCE, True),
+                                             ((128, 128, 128), 2, FP32, FORCE, True),
+                                             ((128, 128, 127), 1, FP32, BASE, False),
+                                             ((128, 128, 128), 3, FP64, FORCE, False),
+                                             ((128, 128, 128), 3, FP32, FORCE, True),
+                                             ((64, 64, 64), 2, FP64, FORCE | dg.DG_SPLIT_STAGE, True),
+                                             ((128, 128, 128), 2, FP64, FORCE | dg.DG_SEPARATE_STAGE, False)]:
+        ctx = make(*shape, k, flags, precision)
+        assert dg.dg_split_stages(ctx) == want, (shape, k, precision, flags)
+        ctx.close()
