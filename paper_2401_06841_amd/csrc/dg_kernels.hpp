@@ -1941,7 +1941,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int c0 = blk * BLOCK + threadIdx.x;
     const bool active = c0 < nc;
-    const int c = active ? c0 : 0;
+    // With the side combination, lanes past the mesh take its last cell: in the wave that holds
+    // that cell they read, form and store exactly what its own lane does (every load of the
+    // wave before its store), so the side combination is stored without a per-lane branch,
+    // which made the compiler spill (233 VGPRs in FP64 at degree 3); a wave with no cell of the
+    // mesh leaves the combination out.
+    const int c = active ? c0 : (SIDE ? nc - 1 : 0);
     const unsigned bo = (unsigned)c * sizeof(T);
     ctab<T> *tab = as_tab<T>(a.tab);
 
@@ -1960,10 +1965,12 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         const Field<T, 4> WS(SIDE ? a.w_src : a.ui, NB, nc);
         const Field<T, 4> WO(SIDE ? a.w_out : a.ui, NB, nc);
         const T wa = (T)a.wa, wb = (T)a.wb, wcdt = (T)(a.wc * dt);
+        const bool wave_has_cell = __builtin_amdgcn_ballot_w64(active) != 0;
         // The combination of every weight, momentum first (the removed mean acceleration
         // multiplies the input density).  Whether u^n and the side combination enter is a
         // template choice (UNV, SIDE): with a branch per weight the compiler waited for each
         // weight's loads in turn.  The roundings are those of the combination k_rhs forms for a split stage.
+        if (!SIDE || wave_has_cell)
 #pragma unroll
         for (int v = 3; v >= 0; --v)
 #pragma unroll
@@ -1974,7 +1981,7 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
                 const T ui = U[v][l];
                 if constexpr (SIDE) {
                     const T w = wa * WS.get(v, l, bo) + wb * ui + wcdt * rhs;
-                    if (active) WO.put(v, l, bo, w);
+                    WO.put(v, l, bo, w);
                 }
                 // stage_value, written out: u^n is loaded only where it enters
                 const T x = fma(cdt, rhs, cb * ui);
