@@ -1970,26 +1970,55 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         // multiplies the input density).  Whether u^n and the side combination enter is a
         // template choice (UNV, SIDE): with a branch per weight the compiler waited for each
         // weight's loads in turn.  The roundings are those of the combination k_rhs forms for a split stage.
-        if (!SIDE || wave_has_cell)
+        if constexpr (!SIDE) {
 #pragma unroll
-        for (int v = 3; v >= 0; --v)
+            for (int v = 3; v >= 0; --v)
 #pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                // the right-hand side and u^n are read once (non-temporal)
-                T rhs = LF.get_nt(v, l, bo);
-                if (v > 0) rhs = fma(-ab[v - 1], U[0][l], rhs);
-                const T ui = U[v][l];
-                if constexpr (SIDE) {
-                    const T w = wa * WS.get(v, l, bo) + wb * ui + wcdt * rhs;
-                    WO.put(v, l, bo, w);
+                for (int l = 0; l < NB; ++l) {
+                    // the right-hand side and u^n are read once (non-temporal)
+                    T rhs = LF.get_nt(v, l, bo);
+                    if (v > 0) rhs = fma(-ab[v - 1], U[0][l], rhs);
+                    const T ui = U[v][l];
+                    // stage_value, written out: u^n is loaded only where it enters
+                    const T x = fma(cdt, rhs, cb * ui);
+                    if constexpr (UNV) U[v][l] = fma(ca, UN.get_nt(v, l, bo), x);
+                    else U[v][l] = x;
+                    // one variable's loads in flight at a time (register pressure)
+                    if (l == NB - 1) __builtin_amdgcn_sched_barrier(0);
                 }
-                // stage_value, written out: u^n is loaded only where it enters
-                const T x = fma(cdt, rhs, cb * ui);
-                if constexpr (UNV) U[v][l] = fma(ca, UN.get_nt(v, l, bo), x);
-                else U[v][l] = x;
-                // one variable's loads in flight at a time (register pressure)
-                if (l == NB - 1) __builtin_amdgcn_sched_barrier(0);
-            }
+        } else if (wave_has_cell) {
+            // The same with the side combination stored as it is formed.  The loads of a chunk
+            // of weights come before its stores: the compiler cannot tell that the side
+            // combination's array does not overlap the other inputs, so a load placed after a
+            // store was issued only once the store's own loads had returned.
+            constexpr int CH = (sizeof(T) == 8 && K >= 2) ? 5 : NB;
+#pragma unroll
+            for (int v = 3; v >= 0; --v)
+#pragma unroll
+                for (int l0 = 0; l0 < NB; l0 += CH) {
+                    T rl[CH], wl[CH], nl[UNV ? CH : 1];
+#pragma unroll
+                    for (int j = 0; j < CH; ++j)
+                        if (l0 + j < NB) {
+                            rl[j] = LF.get_nt(v, l0 + j, bo);
+                            wl[j] = WS.get(v, l0 + j, bo);
+                            if constexpr (UNV) nl[j] = UN.get_nt(v, l0 + j, bo);
+                        }
+#pragma unroll
+                    for (int j = 0; j < CH; ++j)
+                        if (l0 + j < NB) {
+                            const int l = l0 + j;
+                            T rhs = rl[j];
+                            if (v > 0) rhs = fma(-ab[v - 1], U[0][l], rhs);
+                            const T ui = U[v][l];
+                            WO.put(v, l, bo, wa * wl[j] + wb * ui + wcdt * rhs);
+                            const T x = fma(cdt, rhs, cb * ui);
+                            if constexpr (UNV) U[v][l] = fma(ca, nl[j], x);
+                            else U[v][l] = x;
+                        }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+        }
     }
     stage_finish<T, K>(U, tab, a, bo, c, active, blk, lds);
 }
@@ -2016,22 +2045,31 @@ __device__ __forceinline__ void rhs_combination(const void *ui, T (&L)[4][Shape<
     T R0[NB];
 #pragma unroll
     for (int l = 0; l < NB; ++l) R0[l] = UI.get(0, l, bo);
-    // variable by variable, each stored as soon as it is formed (its registers are free then)
+    // variable by variable, each stored as soon as it is formed (its registers are free then).
+    // All of a variable's loads come before its stores: the compiler cannot tell that the output
+    // does not overlap the inputs, so a load placed after a store was issued only once the
+    // store's own load had returned (one memory latency per weight).
 #pragma unroll
-    for (int v = 3; v >= 0; --v)
+    for (int v = 3; v >= 0; --v) {
+        T ui[NB], un[UNV ? NB : 1];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) {
+            ui[l] = v ? UI.get_nt(v, l, bo) : R0[l];
+            if constexpr (UNV) un[l] = UN.get_nt(v, l, bo);
+        }
 #pragma unroll
         for (int l = 0; l < NB; ++l) {
             // the value the separate right-hand side stores
             T rhs = L[v][l] * inv4h;
             if (v > 0) rhs = fma(-ab[v - 1], R0[l], rhs);
-            const T u = v ? UI.get_nt(v, l, bo) : R0[l];
-            const T x = fma(cdt, rhs, cb * u);
+            const T x = fma(cdt, rhs, cb * ui[l]);
             T w;
-            if constexpr (UNV) w = fma(ca, UN.get_nt(v, l, bo), x);
+            if constexpr (UNV) w = fma(ca, un[l], x);
             else w = x;
             if (active) UO.put(v, l, bo, w);
-            if (l == NB - 1) __builtin_amdgcn_sched_barrier(0);
         }
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // The rest of a stage whose combination the right-hand-side kernel has stored (a.out,
