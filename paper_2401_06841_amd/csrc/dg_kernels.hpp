@@ -1970,42 +1970,60 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(stag
         // multiplies the input density).  Whether u^n and the side combination enter is a
         // template choice (UNV, SIDE): with a branch per weight the compiler waited for each
         // weight's loads in turn.  The roundings are those of the combination k_rhs forms for a split stage.
+        // Weights in chunks of CH, each chunk's loads issued together before its arithmetic:
+        // with a whole variable's right-hand side and u^n in flight the FP64 kernel at degree 2
+        // does not fit its registers (128 VGPRs for 4 waves), and the compiler then issued one
+        // load at a time, each waiting for the last.  At degree 3 (2 waves) a whole variable's
+        // loads fit and go out together (chunks of 5 measured 1 % slower per step).
+        constexpr int CH = (sizeof(T) == 8 && K == 2) ? 5 : NB;
         if constexpr (!SIDE) {
 #pragma unroll
             for (int v = 3; v >= 0; --v)
 #pragma unroll
-                for (int l = 0; l < NB; ++l) {
+                for (int l0 = 0; l0 < NB; l0 += CH) {
                     // the right-hand side and u^n are read once (non-temporal)
-                    T rhs = LF.get_nt(v, l, bo);
-                    if (v > 0) rhs = fma(-ab[v - 1], U[0][l], rhs);
-                    const T ui = U[v][l];
-                    // stage_value, written out: u^n is loaded only where it enters
-                    const T x = fma(cdt, rhs, cb * ui);
-                    if constexpr (UNV) U[v][l] = fma(ca, UN.get_nt(v, l, bo), x);
-                    else U[v][l] = x;
-                    // one variable's loads in flight at a time (register pressure)
-                    if (l == NB - 1) __builtin_amdgcn_sched_barrier(0);
+                    T rl[CH], nl[UNV ? CH : 1];
+#pragma unroll
+                    for (int j = 0; j < CH; ++j)
+                        if (l0 + j < NB) {
+                            rl[j] = LF.get_nt(v, l0 + j, bo);
+                            if constexpr (UNV) nl[j] = UN.get_nt(v, l0 + j, bo);
+                        }
+#pragma unroll
+                    for (int j = 0; j < CH; ++j)
+                        if (l0 + j < NB) {
+                            const int l = l0 + j;
+                            T rhs = rl[j];
+                            if (v > 0) rhs = fma(-ab[v - 1], U[0][l], rhs);
+                            const T ui = U[v][l];
+                            // stage_value, written out: u^n is loaded only where it enters
+                            const T x = fma(cdt, rhs, cb * ui);
+                            if constexpr (UNV) U[v][l] = fma(ca, nl[j], x);
+                            else U[v][l] = x;
+                        }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
         } else if (wave_has_cell) {
             // The same with the side combination stored as it is formed.  The loads of a chunk
             // of weights come before its stores: the compiler cannot tell that the side
             // combination's array does not overlap the other inputs, so a load placed after a
-            // store was issued only once the store's own loads had returned.
-            constexpr int CH = (sizeof(T) == 8 && K >= 2) ? 5 : NB;
+            // store was issued only once the store's own loads had returned.  Chunks of 5 in
+            // FP64 from degree 2 (the third operand does not fit otherwise).
+            constexpr int CS = (sizeof(T) == 8 && K >= 2) ? 5 : NB;
 #pragma unroll
             for (int v = 3; v >= 0; --v)
 #pragma unroll
-                for (int l0 = 0; l0 < NB; l0 += CH) {
-                    T rl[CH], wl[CH], nl[UNV ? CH : 1];
+                for (int l0 = 0; l0 < NB; l0 += CS) {
+                    T rl[CS], wl[CS], nl[UNV ? CS : 1];
 #pragma unroll
-                    for (int j = 0; j < CH; ++j)
+                    for (int j = 0; j < CS; ++j)
                         if (l0 + j < NB) {
                             rl[j] = LF.get_nt(v, l0 + j, bo);
                             wl[j] = WS.get(v, l0 + j, bo);
                             if constexpr (UNV) nl[j] = UN.get_nt(v, l0 + j, bo);
                         }
 #pragma unroll
-                    for (int j = 0; j < CH; ++j)
+                    for (int j = 0; j < CS; ++j)
                         if (l0 + j < NB) {
                             const int l = l0 + j;
                             T rhs = rl[j];
@@ -2419,12 +2437,19 @@ __global__ void __launch_bounds__(BLOCK) k_meanfree(const void *u_, void *dudt_,
     const T *u = (const T *)u_;
     T *o = (T *)dudt_;
     const T ab[3] = {(T)abar[0], (T)abar[1], (T)abar[2]};
+    // every load before the first store: o and u may overlap as far as the compiler can tell,
+    // so a load placed after a store was issued only once that store's value had arrived
+    T r[NB], x[3][NB];
 #pragma unroll
-    for (int l = 0; l < NB; ++l) {
-        const T r = u[l * (size_t)nc + c];
+    for (int l = 0; l < NB; ++l) r[l] = u[l * (size_t)nc + c];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) o[((1 + d) * NB + l) * (size_t)nc + c] -= ab[d] * r;
-    }
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) x[d][l] = o[((1 + d) * NB + l) * (size_t)nc + c];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) o[((1 + d) * NB + l) * (size_t)nc + c] = x[d][l] - ab[d] * r[l];
 }
 
 }  // namespace dg
