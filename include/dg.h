@@ -72,10 +72,11 @@ enum dg_flags {
                                   driving shell keep the vector form */
     DG_SEPARATE_STAGE = 512,   /* every Runge-Kutta stage of a step as its own kernel after the stored
                                   right-hand side */
-    DG_SPLIT_STAGE = 1024      /* the stages that write workspace buffers (all but the last) split between
-                                  the right-hand-side kernel, which forms the stage's combination instead
-                                  of storing the right-hand side, and a kernel that limits and projects
-                                  it.  The same results as DG_SEPARATE_STAGE (bit for bit, or to rounding
+    DG_SPLIT_STAGE = 1024      /* the stages without a side combination split between the right-hand-side
+                                  kernel, which forms the stage's combination instead of storing the
+                                  right-hand side, and a kernel that limits and projects it (the last
+                                  stage: the stage kernel, which writes the caller's array from the
+                                  combination unless a cell failed).  The same results as DG_SEPARATE_STAGE (bit for bit, or to rounding
                                   with mean-free driving on the driving shell, whose mean the split path
                                   sums in modal form).  With neither flag the split is used where it
                                   measured faster (meshes of at least 2^21 cells); the two-lane FP64

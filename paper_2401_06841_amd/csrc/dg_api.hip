@@ -786,6 +786,7 @@ static StageArgs stage_args(dg_ctx *c, const void *ui, const void *un, const voi
     a.rho_floor = c->cfg.rho_floor;
     a.rho_floor_rel = c->cfg.rho_floor_rel;
     a.drive_part = nullptr;
+    a.fail_on_mean = 0;
     a.ftab = c->wp(c->off.ftab);
     a.modes = c->modes_dev;
     a.nmodes = c->nmodes;
@@ -930,21 +931,35 @@ static const Scheme &scheme_of(const dg_ctx *c)
 // combination (k_rhs with COMB), and k_limit_project, which limits and projects it, instead of
 // storing the right-hand side for a stage kernel: the one-lane kernel with the vector volume
 // integral, a stage without a side combination that writes a workspace buffer other than its
-// input (the last stage writes the caller's array, which must keep u^n when the step fails:
-// its failure is decided before its stage kernel runs), and not turned off by
-// DG_SEPARATE_STAGE.  Split and separate stages give the same bits.
+// input, and not turned off by DG_SEPARATE_STAGE.  The last stage writes the caller's array,
+// which must keep u^n when the step fails: split, it stores its combination into a free
+// workspace buffer (raising the failure flag from the combination's mean density) and k_stage
+// writes the caller's array from there unless a cell failed.  Split and separate stages give
+// the same bits (to rounding with mean-free driving on the driving shell).
 // The split pays where the mesh takes many rounds of blocks: measured on one MI355X (split
 // against separate, alternated in one call, degree 2, driven, mean-free): 256^3 FP64 42.7 vs
 // 43.8 ms per step, 256^3 FP32 21.5 vs 22.2 ms, 128^3 FP64 5.43 vs 5.52 ms, 128^3 FP32 2.76 vs
 // 2.79 ms; slower at 64^3 FP64 (0.81-0.82 vs 0.78 ms).
 constexpr long long SPLIT_MIN_CELLS = 1LL << 21;
 
-// (The last stage measured no gain split: its combination into a free buffer and k_stage from
-// there at 256^3 FP64 took 44.2 ms per step against 44.1 for the stored right-hand side.)
+// (The split last stage: 256^3 FP64 39.19 against 39.83 ms per step, FP32 20.22 against 20.71
+// ms, 128^3 FP32 2.57 against 2.60 ms, alternated in one call; before the combination's loads
+// and k_stage's were batched it measured 44.2 against 44.1 ms.)
+// a workspace stage buffer that stage g neither reads nor writes (a split last stage stores its
+// combination there), or 0
+static int free_stage_buffer(const dg_ctx *c, const StageSpec &g)
+{
+    const int n = ((c->cfg.flags & DG_RK_BY_ORDER) && c->k == 3) ? 3 : 2;
+    for (int b = 1; b <= n; ++b)
+        if (b != g.in && b != g.un && b != g.w) return b;
+    return 0;
+}
+
 template <typename T, int K>
 static bool split_stage(const dg_ctx *c, const StageSpec &g, bool last)
 {
-    if (rhs_pair<T, K>() || last || g.w || g.out == 0 || g.out == g.in) return false;
+    if (rhs_pair<T, K>() || g.w || g.out == g.in) return false;
+    if (last ? free_stage_buffer(c, g) == 0 : g.out == 0) return false;
     if (c->cfg.flags & (DG_SEPARATE_STAGE | DG_VOLUME_MFMA)) return false;
     if (c->cfg.flags & DG_SPLIT_STAGE) return true;
     return (long long)c->nc >= SPLIT_MIN_CELLS;
@@ -1017,12 +1032,26 @@ static int launch_step_stage(dg_ctx *c, void *u, int s, double dt, bool reset_fa
         }
         if (mf && !in_stage && (rc = launch_abar(c, (const double *)c->wp(c->off.dpart), c->nblk))) return rc;
         c->abar_in_stage = in_stage;
-        StageArgs st = stage_args(c, buf[g.in], buf[g.un], nullptr, buf[g.out], vh[(s + 1) & 1], false, g.coef, dt,
+        const int outb = last ? free_stage_buffer(c, g) : g.out;
+        StageArgs st = stage_args(c, buf[g.in], buf[g.un], nullptr, buf[outb], vh[(s + 1) & 1], false, g.coef, dt,
                                   nullptr, nullptr, nullptr, g.wcoef, dt_dev, true);
+        st.fail_on_mean = last;
         c->abar_in_stage = false;
         c->prof_first = s == 0;
-        c->prof_last = false;
+        c->prof_last = last;
         if ((rc = launch_rhs<T, K>(c, buf[g.in], vh[s & 1], nullptr, dt, nullptr, nullptr, dt_dev, &st))) return rc;
+        c->prof_last = false;
+        if (last) {
+            // the caller's array from the combination, unless a cell failed (the stage kernel's
+            // limiter, projection and time-step maxima)
+            void *vnext = want_next ? vh[0] : nullptr;
+            double *part = want_next ? (double *)c->wp(c->off.spart) : nullptr;
+            c->learned_bounds_later = want_next && (c->cfg.flags & DG_LEARNED_SENSOR);
+            rc = launch_stage<T, K>(c, buf[outb], buf[outb], nullptr, buf[g.out], vnext, true, g.coef, dt, nullptr,
+                                    part, nullptr, g.wcoef, dt_dev);
+            c->learned_bounds_later = false;
+            return rc;
+        }
         // the next stage's partials, when it is split too and reads this stage's result (tables
         // in the pencil form: the mode-by-mode field costs too many registers there, and the
         // next stage runs k_drive_parts)

@@ -296,6 +296,9 @@ struct StageArgs {
     const void *ftab;
     const double *modes;
     int nmodes;
+    // a split last stage: raise *fail where the combination's mean density is at or below
+    // rho_floor (before the stage kernel writes the caller's state), else 0
+    int fail_on_mean;
 };
 
 // ------------------------------------------------------------------ helpers
@@ -2085,6 +2088,9 @@ __device__ __forceinline__ void rhs_combination(const void *ui, T (&L)[4][Shape<
             if constexpr (UNV) w = fma(ca, un[l], x);
             else w = x;
             if (active) UO.put(v, l, bo, w);
+            // a last stage's failure, from its mean density as the stage kernel's limiter
+            // decides it (Sec. 3.1: a cell whose mean is at or below the floor cannot be limited)
+            if (v == 0 && l == 0 && st.fail_on_mean && active && !((double)w > st.rho_floor)) atomicOr(st.fail, 1);
         }
         __builtin_amdgcn_sched_barrier(0);
     }

@@ -1,9 +1,11 @@
 """Split Runge-Kutta stages against separate stage kernels.
 
-With DG_SPLIT_STAGE every stage of a step that writes a workspace buffer (all but the last)
-is split: once a cell's right-hand side is formed, the right-hand-side kernel combines it with
-the cell's input weights (and u^n) and stores the result, and a second kernel limits it
-(Sec. 3.1) and projects its velocity (Sec. 3.2) for the next stage.  DG_SEPARATE_STAGE stores
+With DG_SPLIT_STAGE every stage of a step without a side combination is split: once a cell's
+right-hand side is formed, the right-hand-side kernel combines it with the cell's input weights
+(and u^n) and stores the result, and a second kernel limits it (Sec. 3.1) and projects its
+velocity (Sec. 3.2) for the next stage.  The last stage stores its combination into a free
+workspace buffer, raises the failure flag from its mean density, and the stage kernel writes
+the caller's array from there unless a cell failed.  DG_SEPARATE_STAGE stores
 the right-hand side and runs the stage kernel instead.  Every combination has the same
 roundings in both, so they give the same bits, except with mean-free driving (Sec. 4.2) and a
 table on the driving shell: the split path then forms the mean-acceleration partials of a
@@ -11,7 +13,7 @@ stage input (in the previous split stage, or in a kernel of their own before a s
 stage) in the modal form of the pencil table, the same sums as the right-hand side's point
 sums up to rounding, and the two paths agree to the parity bars (1e-12 FP64, 1e-5 FP32, in
 the field norms and weight by weight, and the time steps).  Each case steps one seeded state in
-two contexts.  Without either flag the split is used on large FP64 meshes only; the parity of
+two contexts.  Without either flag the split is used on meshes of at least 2^21 cells; the parity of
 both paths with the oracle is checked by the step tests of the other files.
 """
 import numpy as np
