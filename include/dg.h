@@ -202,9 +202,10 @@ int dg_rk_step_next(dg_ctx *ctx, void *u, double dt, int reuse, int *status_host
 int dg_rk_step_next_ahead(dg_ctx *ctx, void *u, double dt, int reuse, double horizon, int *status_host,
                           double *dt_next_host);
 
-/* 1 when the steps of this context split their stages that write workspace buffers between
- * the right-hand-side kernel (which forms the stage's combination) and a limit-and-project
- * kernel (DG_SPLIT_STAGE, or the default choice for the mesh and precision; the SSP-RK
+/* 1 when the steps of this context split their stages between the right-hand-side kernel
+ * (which forms the stage's combination) and a limit-and-project kernel, the last stage's
+ * stage kernel writing the caller's array from the combination (DG_SPLIT_STAGE, or the
+ * default choice for the mesh and precision; the SSP-RK
  * combination of Sec. 2.2 / 7 with the limiter of Sec. 3.1 either way), else 0; DG_EINVAL
  * for a null context.  No device call. */
 int dg_split_stages(const dg_ctx *ctx);

@@ -299,7 +299,7 @@ def dg_profile(ctx: Context, enable):
 
 
 def dg_split_stages(ctx: Context) -> bool:
-    """Whether the context's steps split their workspace stages (DG_SPLIT_STAGE or default)."""
+    """Whether the context's steps split their stages (DG_SPLIT_STAGE or the default)."""
     r = _lib.dg_split_stages(ctx.h)
     if r < 0:
         ctx._chk(r)
